@@ -1,0 +1,152 @@
+/*
+ * pldl.h -- C-ABI of the MI355X (gfx950) library computing the symmetric
+ * indefinite factorization  A = P L D L^T P^T  over a prime field F_p that
+ * reveals the rank profile matrix (Dumas & Pernet, "Symmetric indefinite
+ * triangular factorization revealing the rank profile matrix").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All matrix arguments are DEVICE pointers (memory of the context's GPU),
+ *    row-major with an explicit leading dimension (elements, >= row length).
+ *  - Residues are canonical, in [0, p).  The building-block calls take and
+ *    return FP64 residues (integers held exactly in doubles).
+ *  - p must be prime with 2 <= p < 2^23 (primality is the caller's duty;
+ *    p >= 2^23 or p < 2 gives PLDL_EUNSUPPORTED_P).
+ *  - `stream` is a hipStream_t (NULL = default stream).  Every call is ordered
+ *    on that stream; calls that must return a rank to the host synchronise it.
+ *  - The caller owns every array; the library never frees or reallocates
+ *    caller memory.  The context owns its workspace (grown on demand, freed by
+ *    pldl_destroy).  A context is not thread-safe: one per host thread.
+ *  - Return value: 0 on success; -k when argument k (1-based) is invalid;
+ *    a positive PLDL_E* code for runtime failures (text: pldl_last_error).
+ *    Arguments are checked before any work is queued.
+ */
+#ifndef PLDL_H
+#define PLDL_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PLDL_OK 0
+#define PLDL_ERANGE 1          /* an input entry is >= p                         */
+#define PLDL_EUNSUPPORTED_P 2  /* p outside [2, 2^23)                            */
+#define PLDL_EHIP 3            /* HIP runtime error (text in pldl_last_error)    */
+#define PLDL_ENOMEM 4          /* workspace allocation failed                    */
+#define PLDL_EINTERNAL 5       /* internal consistency check failed              */
+
+#define PLDL_U32 0             /* uint32 residues */
+#define PLDL_F64 1             /* FP64 residues   */
+
+#define PLDL_PATH_AUTO 0       /* FP64 MFMA                                      */
+#define PLDL_PATH_F64 1        /* products on FP64 MFMA with delayed reduction   */
+
+typedef struct pldl_ctx pldl_ctx;
+
+typedef struct {
+    int32_t path;          /* PLDL_PATH_*                                              */
+    int32_t threshold;     /* base-case order t of the cascade (Section 5); 0 = default */
+    int32_t standard_form; /* p == 2 only: turn relaxed 2x2 blocks into the standard
+                              form of Section 2.3 (after the rank profile is taken)     */
+    int32_t check_range;   /* nonzero: reject inputs with an entry >= p (PLDL_ERANGE)   */
+} pldl_opts;
+
+/* Create a context bound to HIP device `device`.  *ctx receives the handle. */
+int pldl_create(pldl_ctx **ctx, int device);
+/* Release the context and its workspace.  NULL is accepted. */
+int pldl_destroy(pldl_ctx *ctx);
+/* Text of the last error recorded on this context ("" if none). */
+const char *pldl_last_error(const pldl_ctx *ctx);
+
+/*
+ * pldl_factor -- Algorithm 2 of the paper (recursive symmetric elimination,
+ * Section 4) cascaded with the Crout-style base case of Section 5 below order
+ * `threshold`, with Algorithm 3 (zero leading block) and Algorithm 1 (TRSS) as
+ * sub-steps.  Computes P, L, D with A = P L D L^T P^T, the rank r, and the rank
+ * profile matrix R = P Psi P^T (Section 2.1, pivoting matrix).
+ *
+ *  p      prime modulus.
+ *  n      order of A (n >= 0).
+ *  A      device, n x n, leading dimension lda >= max(1, n), dtype `dtype`.
+ *         In: the lower triangle (j <= i) of the symmetric A; the strict upper
+ *         triangle is neither read nor written.
+ *         Out: strict lower triangle = L (unit diagonal implied), including the
+ *         entry L[q+1][q] of a 2x2 block; diagonal = diag(D) (x for a 1x1 block,
+ *         0 and 0 for an odd-characteristic 2x2 block, 0 and d for a relaxed
+ *         characteristic-2 block [[0,c],[c,d]]).
+ *  e      device, n entries (dtype `dtype`): e[q] = D[q+1][q] for a 2x2 block
+ *         starting at position q, else 0.
+ *  perm   device int32[n]: perm[q] = original index at position q, i.e.
+ *         P = [e_perm[0] ... e_perm[n-1]]; the rank pivots come first, the n - r
+ *         non-pivots last in increasing original order.
+ *  rpm    device int32[n]: rpm[i] = j if R[i][j] = 1, else -1 (R is a symmetric
+ *         rook placement with r ones).
+ *  rank   host int64*: receives r (the call synchronises `stream`).
+ *  opts   may be NULL (defaults).
+ * With standard_form set and p == 2, perm/L/diag/e are returned in the standard
+ * form of Section 2.3 while rpm still holds R.
+ */
+int pldl_factor(pldl_ctx *ctx, uint32_t p, int64_t n, void *A, int64_t lda, int32_t dtype,
+                void *e, int32_t *perm, int32_t *rpm, int64_t *rank, const pldl_opts *opts,
+                void *stream);
+
+/* ---------------- building blocks (Section 3), FP64 residues ---------------- */
+
+/*
+ * GEMM (Section 3): C <- C - op(A) op(B) mod p, C m x n, op(A) m x k, op(B) k x n;
+ * op(X) = X (trans = 0) or X^T (trans = 1).  With lower_only = 1 (m == n) only
+ * the entries j <= i of C are updated: this is SYRDK / SYRD2K's output mode.
+ */
+int pldl_gemm(pldl_ctx *ctx, uint32_t p, int64_t m, int64_t n, int64_t k,
+              const double *A, int64_t lda, int32_t transA,
+              const double *B, int64_t ldb, int32_t transB,
+              double *C, int64_t ldc, int32_t lower_only, void *stream);
+
+/*
+ * TRSM (Section 3) with a unit triangular T of order m (its diagonal and other
+ * triangle are not read), B m x n in place:
+ *   lower = 1: B <- T^{-1} B with T unit lower;   lower = 0: T unit upper.
+ */
+int pldl_trsm(pldl_ctx *ctx, uint32_t p, int32_t lower, int64_t m, int64_t n,
+              const double *T, int64_t ldt, double *B, int64_t ldb, void *stream);
+
+/*
+ * SYRDK (Section 3): lower triangle of C <- C - A D A^T, A n x k, D block
+ * diagonal of order k with diagonal dd[k] and off-diagonal de[k]
+ * (de[q] = D[q+1][q] = D[q][q+1]).  SYRD2K: C <- C - A D B^T - B D A^T.
+ * B may be NULL for SYRDK.
+ */
+int pldl_syrdk(pldl_ctx *ctx, uint32_t p, int64_t n, int64_t k, const double *A, int64_t lda,
+               const double *B, int64_t ldb, const double *dd, const double *de,
+               double *C, int64_t ldc, void *stream);
+
+/*
+ * TRSS (Problem 1, Algorithm 1): given U unit upper (n x n, diagonal and strict
+ * lower part not read) and symmetric C (lower triangle read), overwrite the
+ * upper triangle of X (n x n, strict lower part set to 0) with the upper
+ * triangular solution of X^T U + U^T X = C.  For p = 2 the diagonal of C must be
+ * zero (else -6 ... see return codes) and the diagonal of X is set to 0.
+ */
+int pldl_trss(pldl_ctx *ctx, uint32_t p, int64_t n, const double *U, int64_t ldu,
+              const double *C, int64_t ldc, double *X, int64_t ldx, void *stream);
+
+/*
+ * PLDUQ revealing the rank profile matrix of the m x n matrix Y (the
+ * elimination Algorithm 3 starts with; Sections 4.2 and 5 for its pivoting):
+ * Y = P [L1; M1] D1 [U1 V1] Q.  On return:
+ *   rows[0..m): original row indices, the rank pivot rows first (pivot order),
+ *               then the non-pivot rows in increasing order;
+ *   cols[0..n): pivot columns in pivot order, then non-pivot columns increasing;
+ *   Y (in place, in (rows, cols) coordinates): strict lower part of the leading
+ *     r columns = L1/M1, diagonal = D1, strict upper part of the leading r rows =
+ *     U1/V1, trailing block zero.  The pivot set {(rows[t], cols[t])} is the rank
+ *     profile matrix of Y; the pivot order is the one of the recursive search.
+ *   rank: host int64*.
+ */
+int pldl_plduq(pldl_ctx *ctx, uint32_t p, int64_t m, int64_t n, double *Y, int64_t ldy,
+               int32_t *rows, int32_t *cols, int64_t *rank, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

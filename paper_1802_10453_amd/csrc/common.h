@@ -1,0 +1,72 @@
+// common.h -- device arithmetic over F_p held in FP64, matrix views, kernel
+// launch declarations shared by the HIP sources of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pldl {
+
+// ---------------------------------------------------------------------------
+// Field parameters.  Residues are integers held exactly in doubles; every
+// kernel keeps W canonical ([0, p)).  Products of two centered residues are
+// below p^2/4 < 2^44 for p < 2^23, so a double accumulates `kred` of them
+// (plus one carried residue) before the 2^53 exactness limit.
+struct Field {
+    double p;       // modulus
+    double pinv;    // 1/p rounded
+    double half;    // floor(p/2): centered representative threshold
+    double inv2;    // (p+1)/2 = 1/2 mod p (unused for p = 2)
+    int32_t ip;     // p as an integer
+    int32_t kred;   // products accumulated between two reductions (multiple of 16)
+};
+
+Field make_field(uint32_t p);
+
+// v mod p in [0, p) for any integer-valued |v| < 2^53.  q may be off by one
+// from floor(v/p) because of the rounded reciprocal; the two corrections bring
+// the exact remainder (computed by one fma) back into range.
+__device__ __forceinline__ double fred(double v, const Field& F) {
+    double q = floor(v * F.pinv);
+    double r = fma(-q, F.p, v);
+    r = (r < 0.0) ? r + F.p : r;
+    r = (r >= F.p) ? r - F.p : r;
+    return r;
+}
+// centered representative of a canonical residue: (-p/2, p/2]
+__device__ __forceinline__ double fcen(double v, const Field& F) { return v > F.half ? v - F.p : v; }
+// canonical representative of a residue in (-p, p)
+__device__ __forceinline__ double fcan(double v, const Field& F) { return v < 0.0 ? v + F.p : v; }
+__device__ __forceinline__ double fmulm(double a, double b, const Field& F) { return fred(a * b, F); }
+
+// Inverse by the extended Euclidean algorithm on 32-bit integers.
+__device__ __forceinline__ double finv(double a, const Field& F) {
+    int r0 = F.ip, r1 = (int)a, s0 = 0, s1 = 1;
+    while (r1 != 0) {
+        int q = r0 / r1, t;
+        t = r0 - q * r1; r0 = r1; r1 = t;
+        t = s0 - q * s1; s0 = s1; s1 = t;
+    }
+    if (s0 < 0) s0 += F.ip;
+    return (double)s0;
+}
+
+// ---------------------------------------------------------------------------
+// Strided matrix view: element (i, j) at p[i*rs + j*cs].  One of the strides
+// is 1 for every view the library forms (row-major: cs = 1; column-major: rs = 1).
+struct MatV {
+    double* p;
+    int64_t rs, cs;
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (host functions; each validates nothing -- callers check bounds).
+struct GemmSeg {
+    MatV A, B;     // A: m x k, B: k x n
+    int64_t k;
+};
+// C (row-major, ldc) <- C - sum_seg A_seg B_seg   (mod p)
+//   lower_c: only entries j <= i of C (m == n);  b_upper: B[t][j] taken as 0 for t > j (segment 0)
+void launch_gemm(hipStream_t s, const Field& F, int64_t m, int64_t n, double* C, int64_t ldc,
+                 const GemmSeg* segs, int nseg, bool lower_c, bool b_upper);
+
+}  // namespace pldl

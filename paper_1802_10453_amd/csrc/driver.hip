@@ -1,0 +1,634 @@
+// driver.hip -- host side of the library: workspace, the recursive algorithms of
+// Section 4 (Algorithm 2 RECALL, Algorithm 3 ZLP with the PLDUQ it starts with,
+// Algorithm 1 TRSS), the cascade to the base case of Section 5, and the C-ABI.
+//
+// Data layout (device): W is an n x n FP64 matrix, row-major, leading dimension
+// n, of which only the lower triangle is meaningful.  Each recursive call owns a
+// contiguous range [lo, hi) of positions; on entry W[lo:hi, lo:hi] holds the
+// symmetric Schur complement of the range, W[lo:hi, 0:lo] the rows of L computed
+// so far, W[hi:n, lo:hi] the coupling with the positions after the range.  A call
+// permutes its range symmetrically (all three parts), leaves L (strict lower)
+// and D (dd, de) for its pivots, its rank pivots first and its non-pivots last in
+// increasing original index.  `orig` maps positions to original indices.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/pldl.h"
+#include "common.h"
+#include "kernels.h"
+
+namespace pldl {
+
+Field make_field(uint32_t p) {
+    Field F;
+    F.p = (double)p;
+    F.pinv = 1.0 / (double)p;
+    F.half = (double)(p / 2);
+    F.inv2 = (double)((p + 1) / 2);
+    F.ip = (int32_t)p;
+    double mh = (double)((p - 1) / 2);
+    double lim = 9007199254740992.0 - (double)p;
+    int64_t k = (mh > 0.0) ? (int64_t)(lim / (mh * mh)) : ((int64_t)1 << 30);
+    if (k > ((int64_t)1 << 30)) k = (int64_t)1 << 30;
+    k = (k / 16) * 16;
+    F.kred = (int32_t)std::max<int64_t>(16, k);
+    return F;
+}
+
+struct Err : std::runtime_error {
+    int code;
+    Err(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                                  \
+    do {                                                                                           \
+        hipError_t e_ = (x);                                                                       \
+        if (e_ != hipSuccess) throw Err(PLDL_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+#define REQUIRE(c)                                                                                         \
+    do {                                                                                                   \
+        if (!(c)) throw Err(PLDL_EINTERNAL, std::string("internal check failed: ") + #c + " at line " +   \
+                                                std::to_string(__LINE__));                                 \
+    } while (0)
+
+static inline unsigned nblk(int64_t x, int b = 256) { return (unsigned)((x + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// Workspace: device buffers sized for order n (grown monotonically).
+struct Workspace {
+    int64_t cap = -1;
+    double *W = nullptr, *tmp1 = nullptr, *tmp2 = nullptr, *dd = nullptr, *de = nullptr;
+    double *xinv = nullptr, *yy = nullptr, *dvec = nullptr;
+    int8_t* kind = nullptr;
+    int32_t *orig = nullptr, *sig = nullptr, *tmpo = nullptr, *info = nullptr;
+    int32_t* hinfo = nullptr;  // pinned host mirror of info (rank, error flag, sigma)
+    void release() {
+        double* ds[] = {W, tmp1, tmp2, dd, de, xinv, yy, dvec};
+        for (double* p : ds) if (p) (void)hipFree(p);
+        if (kind) (void)hipFree(kind);
+        int32_t* is[] = {orig, sig, tmpo, info};
+        for (int32_t* p : is) if (p) (void)hipFree(p);
+        if (hinfo) (void)hipHostFree(hinfo);
+        *this = Workspace();
+    }
+    void ensure(int64_t n) {
+        if (n <= cap) return;
+        release();
+        int64_t m = std::max<int64_t>(n, 1);
+        size_t nn = (size_t)m * (size_t)m;
+        auto dalloc = [&](double** p, size_t cnt) {
+            if (hipMalloc((void**)p, cnt * sizeof(double)) != hipSuccess) {
+                (void)hipGetLastError();
+                release();
+                throw Err(PLDL_ENOMEM, "device allocation of " + std::to_string(cnt * 8) + " bytes failed");
+            }
+        };
+        dalloc(&W, nn);
+        dalloc(&tmp1, nn + 256);
+        dalloc(&tmp2, 2 * nn + 256);
+        dalloc(&dd, m + 1);
+        dalloc(&de, m + 1);
+        dalloc(&xinv, m + 1);
+        dalloc(&yy, m + 1);
+        dalloc(&dvec, 2 * m + 2);
+        if (hipMalloc((void**)&kind, m + 1) != hipSuccess) { release(); throw Err(PLDL_ENOMEM, "alloc"); }
+        int32_t** ips[] = {&orig, &sig, &tmpo};
+        for (int32_t** p : ips)
+            if (hipMalloc((void**)p, std::max<int64_t>(2 * m + 2, 512) * sizeof(int32_t)) != hipSuccess) {
+                release();
+                throw Err(PLDL_ENOMEM, "alloc");
+            }
+        if (hipMalloc((void**)&info, 1024 * sizeof(int32_t)) != hipSuccess) { release(); throw Err(PLDL_ENOMEM, "alloc"); }
+        if (hipHostMalloc((void**)&hinfo, 1024 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+            release();
+            throw Err(PLDL_ENOMEM, "pinned alloc");
+        }
+        cap = n;
+    }
+};
+
+// ---------------------------------------------------------------------------
+struct Engine {
+    hipStream_t st;
+    Field F;
+    int64_t n, ld;
+    int t_leaf;
+    Workspace& ws;
+    double* W;
+    Engine(Workspace& w, hipStream_t s, uint32_t p, int64_t n_, int t) : st(s), F(make_field(p)), n(n_), ld(std::max<int64_t>(n_, 1)), t_leaf(t), ws(w), W(w.W) {}
+
+    // bounds of a view inside W (every view the algorithms form lies in W's lower triangle)
+    void chk(int64_t r0, int64_t c0, int64_t rows, int64_t cols) const {
+        REQUIRE(r0 >= 0 && c0 >= 0 && rows >= 0 && cols >= 0 && r0 + rows <= n && c0 + cols <= n);
+    }
+    MatV vrow(int64_t r0, int64_t c0) { return MatV{W + r0 * ld + c0, ld, 1}; }  // W[r0+i][c0+j]
+    MatV vcol(int64_t r0, int64_t c0) { return MatV{W + r0 * ld + c0, 1, ld}; }  // W[r0+j][c0+i]
+
+    int32_t* read_info(int cnt) {
+        HIPCHK(hipMemcpyAsync(ws.hinfo, ws.info, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return ws.hinfo;
+    }
+
+    void gemm(double* C, int64_t m, int64_t nn, GemmSeg s0, GemmSeg s1 = GemmSeg{MatV{nullptr, 0, 1}, MatV{nullptr, 0, 1}, 0},
+              bool lower = false, bool b_upper = false) {
+        if (m <= 0 || nn <= 0 || (s0.k <= 0 && s1.k <= 0)) return;
+        GemmSeg segs[2] = {s0, s1};
+        if (s0.k > 0 && s1.k > 0) REQUIRE((s0.A.cs == 1) == (s1.A.cs == 1) && (s0.B.cs == 1) == (s1.B.cs == 1));
+        launch_gemm(st, F, m, nn, C, ld, segs, 2, lower, b_upper);
+    }
+
+    // Symmetric permutation of [lo, hi): new lo+q <- old lo+sig[q].
+    // parts: 1 = rows x [0,lo), 2 = block, 4 = rows below x range, 8 = orig.
+    void perm_sym(int64_t lo, int64_t hi, const int32_t* sig, int parts) {
+        int64_t s = hi - lo;
+        if (s <= 1) return;
+        REQUIRE(lo >= 0 && hi <= n);
+        int64_t rows = std::max(s, n - hi), cols = std::max(lo, s);
+        if (rows <= 0 || cols <= 0) return;
+        REQUIRE(rows <= 65535);
+        dim3 g(nblk(cols), (unsigned)rows, 4);
+        hipLaunchKernelGGL(k_perm_gather, g, dim3(256), 0, st, W, ld, n, lo, hi, sig, ws.tmp1, ws.orig, ws.tmpo, parts);
+        hipLaunchKernelGGL(k_perm_scatter, g, dim3(256), 0, st, W, ld, n, lo, hi, ws.tmp1, ws.orig, ws.tmpo, parts);
+    }
+    void rotate(int64_t a, int64_t b, int64_t c) {
+        if (a == b || b == c) return;
+        hipLaunchKernelGGL(k_sigma_rotate, dim3(nblk(c - a)), dim3(256), 0, st, ws.sig, b - a, c - b);
+        perm_sym(a, c, ws.sig, 15);
+    }
+
+    // ---- TRSM (Section 3) ---------------------------------------------------
+    // B (m x r, row-major) <- B T^{-1}, T unit upper (view)
+    void trsm_ru(MatV B, int64_t m, int64_t r, MatV T) {
+        if (m <= 0 || r <= 0) return;
+        if (r <= 64) {
+            hipLaunchKernelGGL(k_trsm_ru_leaf, dim3(nblk(m, 64)), dim3(256), 0, st, B.p, B.rs, m, (int)r, T, F);
+            return;
+        }
+        int64_t r1 = std::max<int64_t>(64, (r / 2) / 64 * 64);
+        trsm_ru(B, m, r1, T);
+        gemm_ld(B.p + r1, B.rs, m, r - r1, GemmSeg{MatV{B.p, B.rs, 1}, MatV{T.p + r1 * T.cs, T.rs, T.cs}, r1});
+        trsm_ru(MatV{B.p + r1, B.rs, 1}, m, r - r1, MatV{T.p + r1 * (T.rs + T.cs), T.rs, T.cs});
+    }
+    // B (r x ncols, row-major) <- T^{-1} B, T unit lower (view)
+    void trsm_ll(MatV B, int64_t r, int64_t ncols, MatV T) {
+        if (r <= 0 || ncols <= 0) return;
+        if (r <= 64) {
+            hipLaunchKernelGGL(k_trsm_ll_leaf, dim3(nblk(ncols, 64)), dim3(256), 0, st, B.p, B.rs, ncols, (int)r, T, F);
+            return;
+        }
+        int64_t r1 = std::max<int64_t>(64, (r / 2) / 64 * 64);
+        trsm_ll(B, r1, ncols, T);
+        gemm_ld(B.p + r1 * B.rs, B.rs, r - r1, ncols, GemmSeg{MatV{T.p + r1 * T.rs, T.rs, T.cs}, MatV{B.p, B.rs, 1}, r1});
+        trsm_ll(MatV{B.p + r1 * B.rs, B.rs, 1}, r - r1, ncols, MatV{T.p + r1 * (T.rs + T.cs), T.rs, T.cs});
+    }
+    void gemm_ld(double* C, int64_t ldc, int64_t m, int64_t nn, GemmSeg s0) {
+        if (m <= 0 || nn <= 0 || s0.k <= 0) return;
+        launch_gemm(st, F, m, nn, C, ldc, &s0, 1, false, false);
+    }
+
+    // ---- base case (Section 5) ------------------------------------------------
+    int64_t bc(int64_t lo, int64_t hi) {
+        int s = (int)(hi - lo);
+        REQUIRE(s >= 1 && s <= 128);
+        hipLaunchKernelGGL(k_bc_leaf, dim3(1), dim3(1024), 0, st, W, ld, lo, s, F, ws.dd, ws.de, ws.info + 1, ws.info);
+        int32_t* h = read_info(1 + s);
+        int64_t r = h[0];
+        bool ident = true;
+        for (int q = 0; q < s; ++q) ident &= (h[1 + q] == q);
+        if (!ident) {
+            HIPCHK(hipMemcpyAsync(ws.sig, ws.info + 1, s * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+            perm_sym(lo, hi, ws.sig, 1 | 4 | 8);
+        }
+        return r;
+    }
+
+    // ---- Algorithm 2 -----------------------------------------------------------
+    int64_t recall(int64_t lo, int64_t hi) {
+        int64_t N = hi - lo;
+        if (N <= 0) return 0;
+        if (N <= t_leaf) return bc(lo, hi);
+        int64_t m = N / 2;
+        if (m >= 128) m = m / 64 * 64;
+        int64_t r1 = recall(lo, lo + m);
+        int64_t s = lo + m, n2 = hi - s;
+        if (r1 > 0 && n2 > 0) {
+            chk(s, lo, n2, m);
+            // X^T = B'1^T L1^{-T}:  right solve with T = L1^T, T[a][b] = W[lo+b][lo+a]
+            trsm_ru(vrow(s, lo), n2, r1, vcol(lo, lo));
+            // Y^T = B'2^T - X^T M1^T, M1 = W[lo+r1 : lo+m, lo : lo+r1]
+            if (m > r1) gemm(W + s * ld + lo + r1, n2, m - r1, GemmSeg{vrow(s, lo), vcol(lo + r1, lo), r1});
+            // SCAL: T <- X^T, G = X^T D1^{-1} in place
+            hipLaunchKernelGGL(k_block_dinv, dim3(nblk(r1)), dim3(256), 0, st, ws.dd, ws.de, lo, r1, F, ws.xinv, ws.yy, ws.kind);
+            hipLaunchKernelGGL(k_scal_dinv, dim3(nblk(r1), (unsigned)n2), dim3(256), 0, st, W + s * ld + lo, ld, n2, r1,
+                               ws.xinv, ws.yy, ws.kind, ws.tmp2, r1, F);
+            // SYRDK: Z = C - G D1 G^T = lower(C - G X)
+            gemm(W + s * ld + s, n2, n2, GemmSeg{vrow(s, lo), MatV{ws.tmp2, 1, r1}, r1}, GemmSeg{MatV{nullptr, 0, 1}, MatV{nullptr, 0, 1}, 0}, true);
+        }
+        return r1 + zlp(lo + r1, m - r1, hi);
+    }
+
+    // ---- Algorithm 3 -----------------------------------------------------------
+    int64_t zlp(int64_t lo, int64_t mz, int64_t hi) {
+        int64_t s0 = lo + mz, nc = hi - s0;
+        if (mz == 0) return recall(lo, hi);
+        if (nc == 0) return 0;
+        int64_t rY = plduq(lo, lo + mz, s0, hi);
+        int64_t nz = nc - rY, nr = mz - rY, N = hi - lo;
+        double* G1 = ws.tmp2;
+        double* G2 = ws.tmp2 + rY * rY;
+        double* UT = G2 + nz * rY;        // characteristic-2 temporaries
+        double* UTD = UT + rY * rY;
+        double* VD = UTD + rY * rY;
+        double* delta = ws.dvec;          // Delta (rY) then the pack diagonal d (rY)
+        if (rY > 0) {
+            HIPCHK(hipMemsetAsync(delta, 0, rY * sizeof(double), st));
+            hipLaunchKernelGGL(k_save_pack_diag, dim3(nblk(rY)), dim3(256), 0, st, W, ld, s0, lo, rY, delta + rY);
+            if (F.ip == 2) {
+                REQUIRE(rY <= 8192);
+                hipLaunchKernelGGL(k_delta, dim3(1), dim3(1024), rY * sizeof(double), st, W, ld, s0, lo, rY, F, delta);
+                hipLaunchKernelGGL(k_u1t_delta, dim3(nblk(rY), (unsigned)rY), dim3(256), 0, st, W, ld, s0, lo, rY, delta, UT, UTD, F);
+                // C'1 <- C'1 - U1^T Delta U1 (lower)
+                gemm(W + s0 * ld + s0, rY, rY, GemmSeg{MatV{UTD, rY, 1}, MatV{UT, 1, rY}, rY},
+                     GemmSeg{MatV{nullptr, 0, 1}, MatV{nullptr, 0, 1}, 0}, true);
+            }
+            trss(s0, rY, lo);
+            // G1 = X^T D1^{-1} (lower)
+            hipLaunchKernelGGL(k_pack_dinv, dim3(nblk(rY)), dim3(256), 0, st, W, ld, s0, lo, rY, F, ws.xinv);
+            hipLaunchKernelGGL(k_mul_cols, dim3(nblk(rY), (unsigned)rY), dim3(256), 0, st, W + s0 * ld + s0, ld, rY, rY, ws.xinv, 1, G1, rY, F);
+            if (F.ip == 2)
+                hipLaunchKernelGGL(k_dadd, dim3(nblk(rY), (unsigned)rY), dim3(256), 0, st, W, ld, s0, lo, rY, delta, F);
+            if (nz > 0) {
+                chk(s0 + rY, lo, nz, mz + rY);
+                // C''2^T = C'2^T - V1^T X   (X upper = transpose of the stored X^T)
+                gemm(W + (s0 + rY) * ld + s0, nz, rY, GemmSeg{vrow(s0 + rY, lo), vcol(s0, s0), rY},
+                     GemmSeg{MatV{nullptr, 0, 1}, MatV{nullptr, 0, 1}, 0}, false, true);
+                // Y2^T = C''2^T U1^{-1},  U1[a][b] = W[s0+b][lo+a]
+                trsm_ru(vrow(s0 + rY, s0), nz, rY, vcol(s0, lo));
+                // Z = C'3 - (Y2^T V1 + V1^T Y2)   (SYRD2K, lower)
+                gemm(W + (s0 + rY) * ld + s0 + rY, nz, nz, GemmSeg{vrow(s0 + rY, s0), vcol(s0 + rY, lo), rY},
+                     GemmSeg{vrow(s0 + rY, lo), vcol(s0 + rY, s0), rY}, true);
+                if (F.ip == 2) {
+                    // Z <- Z - V1^T Delta V1
+                    hipLaunchKernelGGL(k_mul_delta, dim3(nblk(rY), (unsigned)nz), dim3(256), 0, st, W + (s0 + rY) * ld + lo, ld, nz, rY, delta, VD, F);
+                    gemm(W + (s0 + rY) * ld + s0 + rY, nz, nz, GemmSeg{MatV{VD, rY, 1}, vcol(s0 + rY, lo), rY},
+                         GemmSeg{MatV{nullptr, 0, 1}, MatV{nullptr, 0, 1}, 0}, true);
+                }
+                // G2 = Y2^T D1^{-1}
+                hipLaunchKernelGGL(k_mul_cols, dim3(nblk(rY), (unsigned)nz), dim3(256), 0, st, W + (s0 + rY) * ld + s0, ld, nz, rY, ws.xinv, 0, G2, rY, F);
+            }
+        }
+        // ---- assembly: [pairs (P_i interleave) | Z | non-pivot rows of the zero block]
+        REQUIRE(N <= 65535);
+        hipLaunchKernelGGL(k_zlp_assemble, dim3(nblk(N), (unsigned)N), dim3(256), 0, st, W, ld, lo, mz, hi, rY, G1,
+                           std::max<int64_t>(rY, 1), G2, std::max<int64_t>(rY, 1), ws.tmp1);
+        hipLaunchKernelGGL(k_copy2d, dim3(nblk(N), (unsigned)N), dim3(256), 0, st, W + lo * ld + lo, ld, ws.tmp1, N, N, N);
+        // sigma of the assembly for the L part, the rows below and orig
+        hipLaunchKernelGGL(k_zlp_sigma, dim3(nblk(N)), dim3(256), 0, st, ws.sig, mz, nc, rY);
+        perm_sym(lo, hi, ws.sig, 1 | 4 | 8);
+        if (rY > 0)
+            hipLaunchKernelGGL(k_zlp_orig_d, dim3(nblk(N)), dim3(256), 0, st, ws.orig, ws.tmpo, lo, mz, hi, rY, W, ld, delta, ws.dd, ws.de, 2);
+        int64_t rz = recall(lo + 2 * rY, lo + 2 * rY + nz);
+        // non-pivots of Z and of the zero block, merged by original index
+        int64_t a = lo + 2 * rY + rz, n1 = nz - rz;
+        if (n1 > 0 && nr > 0) {
+            hipLaunchKernelGGL(k_sigma_merge, dim3(nblk(n1 + nr)), dim3(256), 0, st, ws.orig, a, n1, nr, ws.sig);
+            perm_sym(a, hi, ws.sig, 1 | 4 | 8);
+        }
+        return 2 * rY + rz;
+    }
+
+    // ---- PLDUQ revealing the rank profile (2-D recursion, tile leaves) --------
+    // rows = positions [a0, a1), columns = positions [c0, c1), Y[i][j] = W[c0+j][a0+i]
+    int64_t plduq(int64_t a0, int64_t a1, int64_t c0, int64_t c1) {
+        int64_t m = a1 - a0, nc = c1 - c0;
+        if (m <= 0 || nc <= 0) return 0;
+        chk(c0, a0, nc, m);
+        if (m <= 32 && nc <= 256) {
+            hipLaunchKernelGGL(k_plduq_leaf, dim3(1), dim3(1024), 0, st, W, ld, a0, (int)m, c0, (int)nc, F, ws.sig,
+                               ws.sig + 32, ws.info);
+            int64_t r = read_info(1)[0];
+            perm_sym(a0, a1, ws.sig, 15);
+            perm_sym(c0, c1, ws.sig + 32, 15);
+            return r;
+        }
+        if (m > 32) {
+            int64_t am = a0 + std::max<int64_t>(32, (m / 2) / 32 * 32);
+            int64_t r1 = plduq(a0, am, c0, c1);
+            if (r1 > 0) {
+                int64_t mb = a1 - am;
+                // Wb^T = U_t^{-T} Y_b1^T : U_t^T unit lower at W[c0.., a0..]
+                trsm_ll(vrow(c0, am), r1, mb, vrow(c0, a0));
+                // Y_b2^T -= V_t^T Wb^T
+                if (nc > r1) gemm(W + (c0 + r1) * ld + am, nc - r1, mb, GemmSeg{vrow(c0 + r1, a0), vrow(c0, am), r1});
+                // L_b^T = D_t^{-1} Wb^T
+                hipLaunchKernelGGL(k_pack_dinv, dim3(nblk(r1)), dim3(256), 0, st, W, ld, c0, a0, r1, F, ws.xinv);
+                hipLaunchKernelGGL(k_scale_by, dim3(nblk(mb), (unsigned)r1), dim3(256), 0, st, W + c0 * ld + am, ld, r1, mb, ws.xinv, 1, F);
+            }
+            int64_t r2 = plduq(am, a1, c0 + r1, c1);
+            rotate(a0 + r1, am, am + r2);
+            return r1 + r2;
+        }
+        int64_t cm = c0 + 256;
+        int64_t r1 = plduq(a0, a1, c0, cm);
+        if (r1 > 0) {
+            int64_t nr_ = c1 - cm;
+            // (D U_R)^T = Y_R[piv]^T L_t^{-T},  L_t^T[a][b] = W[c0+a][a0+b] (a < b)
+            trsm_ru(vrow(cm, a0), nr_, r1, vrow(c0, a0));
+            // Y_R[np]^T -= (D U_R)^T M_t^T
+            if (m > r1) gemm(W + cm * ld + a0 + r1, nr_, m - r1, GemmSeg{vrow(cm, a0), vrow(c0, a0 + r1), r1});
+            hipLaunchKernelGGL(k_pack_dinv, dim3(nblk(r1)), dim3(256), 0, st, W, ld, c0, a0, r1, F, ws.xinv);
+            hipLaunchKernelGGL(k_scale_by, dim3(nblk(r1), (unsigned)nr_), dim3(256), 0, st, W + cm * ld + a0, ld, nr_, r1, ws.xinv, 0, F);
+        }
+        int64_t r2 = plduq(a0 + r1, a1, cm, c1);
+        rotate(c0 + r1, cm, cm + r2);
+        return r1 + r2;
+    }
+
+    // ---- Algorithm 1 (TRSS): C at W[s0..s0+r)^2, U[a][b] = W[s0+b][u0+a] -----
+    void trss(int64_t s0, int64_t r, int64_t u0) {
+        if (r <= 0) return;
+        if (r <= 64) {
+            hipLaunchKernelGGL(k_trss_leaf, dim3(1), dim3(64), 0, st, W, ld, s0, u0, (int)r, F);
+            return;
+        }
+        int64_t h = std::max<int64_t>(64, (r / 2) / 64 * 64);
+        trss(s0, h, u0);
+        // D2^T = C2^T - U2^T X1
+        gemm(W + (s0 + h) * ld + s0, r - h, h, GemmSeg{vrow(s0 + h, u0), vcol(s0, s0), h},
+             GemmSeg{MatV{nullptr, 0, 1}, MatV{nullptr, 0, 1}, 0}, false, true);
+        // X2^T = D2^T U11^{-1}
+        trsm_ru(vrow(s0 + h, s0), r - h, h, vcol(s0, u0));
+        // D3 = C3 - (X2^T U2 + U2^T X2)
+        gemm(W + (s0 + h) * ld + s0 + h, r - h, r - h, GemmSeg{vrow(s0 + h, s0), vcol(s0 + h, u0), h},
+             GemmSeg{vrow(s0 + h, u0), vcol(s0 + h, s0), h}, true);
+        trss(s0 + h, r - h, u0 + h);
+    }
+};
+
+}  // namespace pldl
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+using namespace pldl;
+
+struct pldl_ctx {
+    int device = 0;
+    Workspace ws;
+    std::string err;
+};
+
+namespace {
+int fail(pldl_ctx* c, int code, const std::string& m) {
+    if (c) c->err = m;
+    return code;
+}
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+bool bad_p(uint32_t p) { return p < 2 || p >= (1u << 23); }
+
+template <typename Fn>
+int guarded(pldl_ctx* ctx, Fn&& fn) {
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        fn();
+        ctx->err.clear();
+        return PLDL_OK;
+    } catch (const Err& e) {
+        return fail(ctx, e.code, e.what());
+    } catch (const std::bad_alloc&) {
+        return fail(ctx, PLDL_ENOMEM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(ctx, PLDL_EINTERNAL, e.what());
+    }
+}
+}  // namespace
+
+extern "C" {
+
+int pldl_create(pldl_ctx** ctx, int device) {
+    if (!ctx) return -1;
+    int cnt = 0;
+    if (hipGetDeviceCount(&cnt) != hipSuccess || device < 0 || device >= cnt) return -2;
+    pldl_ctx* c = new (std::nothrow) pldl_ctx();
+    if (!c) return PLDL_ENOMEM;
+    c->device = device;
+    *ctx = c;
+    return PLDL_OK;
+}
+
+int pldl_destroy(pldl_ctx* ctx) {
+    if (!ctx) return PLDL_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->ws.release();
+    delete ctx;
+    return PLDL_OK;
+}
+
+const char* pldl_last_error(const pldl_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int pldl_factor(pldl_ctx* ctx, uint32_t p, int64_t n, void* A, int64_t lda, int32_t dtype, void* e, int32_t* perm,
+                int32_t* rpm, int64_t* rank, const pldl_opts* opts, void* stream) {
+    if (!ctx) return -1;
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (n < 0 || n > 65535) return fail(ctx, -3, "n out of range [0, 65535]");
+    if (n > 0 && !A) return fail(ctx, -4, "A is NULL");
+    if (lda < std::max<int64_t>(1, n)) return fail(ctx, -5, "lda < max(1, n)");
+    if (dtype != PLDL_U32 && dtype != PLDL_F64) return fail(ctx, -6, "unknown dtype");
+    if (n > 0 && !e) return fail(ctx, -7, "e is NULL");
+    if (n > 0 && !perm) return fail(ctx, -8, "perm is NULL");
+    if (n > 0 && !rpm) return fail(ctx, -9, "rpm is NULL");
+    if (!rank) return fail(ctx, -10, "rank is NULL");
+    pldl_opts o{PLDL_PATH_AUTO, 0, 0, 1};
+    if (opts) o = *opts;
+    if (o.path != PLDL_PATH_AUTO && o.path != PLDL_PATH_F64) return fail(ctx, -11, "unknown path");
+    if (o.threshold < 0 || o.threshold > 128) return fail(ctx, -11, "threshold must be in [0, 128]");
+    int t = o.threshold ? o.threshold : 128;
+    if (n == 0) { *rank = 0; return PLDL_OK; }
+    hipStream_t st = as_stream(stream);
+    return guarded(ctx, [&]() {
+        ctx->ws.ensure(n);
+        Engine E(ctx->ws, st, p, n, t);
+        Workspace& ws = ctx->ws;
+        HIPCHK(hipMemsetAsync(ws.info, 0, sizeof(int32_t) * 4, st));
+        dim3 g(nblk(n), (unsigned)n);
+        if (dtype == PLDL_U32)
+            hipLaunchKernelGGL(k_load_input<uint32_t>, g, dim3(256), 0, st, (const uint32_t*)A, lda, ws.W, E.ld, n, E.F, ws.info + 2);
+        else
+            hipLaunchKernelGGL(k_load_input<double>, g, dim3(256), 0, st, (const double*)A, lda, ws.W, E.ld, n, E.F, ws.info + 2);
+        if (o.check_range) {
+            int32_t* h = E.read_info(3);
+            if (h[2]) throw Err(PLDL_ERANGE, "input entry outside [0, p)");
+        }
+        hipLaunchKernelGGL(k_iota, dim3(nblk(n)), dim3(256), 0, st, ws.orig, n);
+        HIPCHK(hipMemsetAsync(ws.dd, 0, sizeof(double) * n, st));
+        HIPCHK(hipMemsetAsync(ws.de, 0, sizeof(double) * n, st));
+        int64_t r = E.recall(0, n);
+        hipLaunchKernelGGL(k_rpm, dim3(nblk(n)), dim3(256), 0, st, ws.orig, ws.de, n, r, rpm);
+        if (o.standard_form && p == 2) {
+            dim3 g2(nblk(n), (unsigned)n);
+            hipLaunchKernelGGL(k_char2_std, g2, dim3(256), 0, st, ws.W, E.ld, n, ws.dd, ws.de, ws.orig, ws.tmp1, 0);
+            hipLaunchKernelGGL(k_char2_std, g2, dim3(256), 0, st, ws.W, E.ld, n, ws.dd, ws.de, ws.orig, ws.tmp1, 1);
+            hipLaunchKernelGGL(k_char2_std, dim3(nblk(n)), dim3(256), 0, st, ws.W, E.ld, n, ws.dd, ws.de, ws.orig, ws.tmp1, 2);
+        }
+        if (dtype == PLDL_U32)
+            hipLaunchKernelGGL(k_store_output<uint32_t>, g, dim3(256), 0, st, (uint32_t*)A, lda, ws.W, E.ld, n, ws.dd, ws.de, (uint32_t*)e, ws.orig, perm);
+        else
+            hipLaunchKernelGGL(k_store_output<double>, g, dim3(256), 0, st, (double*)A, lda, ws.W, E.ld, n, ws.dd, ws.de, (double*)e, ws.orig, perm);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        *rank = r;
+    });
+}
+
+int pldl_gemm(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t transA,
+              const double* B, int64_t ldb, int32_t transB, double* C, int64_t ldc, int32_t lower_only, void* stream) {
+    if (!ctx) return -1;
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (m < 0) return fail(ctx, -3, "m < 0");
+    if (n < 0) return fail(ctx, -4, "n < 0");
+    if (k < 0) return fail(ctx, -5, "k < 0");
+    if (m > 0 && k > 0 && !A) return fail(ctx, -6, "A is NULL");
+    if (lda < std::max<int64_t>(1, transA ? m : k)) return fail(ctx, -7, "lda too small");
+    if (n > 0 && k > 0 && !B) return fail(ctx, -9, "B is NULL");
+    if (ldb < std::max<int64_t>(1, transB ? k : n)) return fail(ctx, -10, "ldb too small");
+    if (m > 0 && n > 0 && !C) return fail(ctx, -12, "C is NULL");
+    if (ldc < std::max<int64_t>(1, n)) return fail(ctx, -13, "ldc too small");
+    if (lower_only && m != n) return fail(ctx, -14, "lower_only needs m == n");
+    hipStream_t st = as_stream(stream);
+    return guarded(ctx, [&]() {
+        Field F = make_field(p);
+        GemmSeg s{transA ? MatV{(double*)A, 1, lda} : MatV{(double*)A, lda, 1},
+                  transB ? MatV{(double*)B, 1, ldb} : MatV{(double*)B, ldb, 1}, k};
+        launch_gemm(st, F, m, n, C, ldc, &s, 1, lower_only != 0, false);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+    });
+}
+
+int pldl_trsm(pldl_ctx* ctx, uint32_t p, int32_t lower, int64_t m, int64_t n, const double* T, int64_t ldt, double* B,
+              int64_t ldb, void* stream) {
+    if (!ctx) return -1;
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (m < 0) return fail(ctx, -4, "m < 0");
+    if (n < 0) return fail(ctx, -5, "n < 0");
+    int64_t tord = lower ? m : n;
+    if (tord > 0 && !T) return fail(ctx, -6, "T is NULL");
+    if (ldt < std::max<int64_t>(1, tord)) return fail(ctx, -7, "ldt too small");
+    if (m > 0 && n > 0 && !B) return fail(ctx, -8, "B is NULL");
+    if (ldb < std::max<int64_t>(1, n)) return fail(ctx, -9, "ldb too small");
+    hipStream_t st = as_stream(stream);
+    return guarded(ctx, [&]() {
+        ctx->ws.ensure(1);
+        Engine E(ctx->ws, st, p, 0, 128);
+        if (lower) E.trsm_ll(MatV{B, ldb, 1}, m, n, MatV{(double*)T, ldt, 1});
+        else E.trsm_ru(MatV{B, ldb, 1}, m, n, MatV{(double*)T, ldt, 1});
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+    });
+}
+
+int pldl_syrdk(pldl_ctx* ctx, uint32_t p, int64_t n, int64_t k, const double* A, int64_t lda, const double* B,
+               int64_t ldb, const double* dd, const double* de, double* C, int64_t ldc, void* stream) {
+    if (!ctx) return -1;
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (n < 0) return fail(ctx, -3, "n < 0");
+    if (k < 0) return fail(ctx, -4, "k < 0");
+    if (n > 0 && k > 0 && !A) return fail(ctx, -5, "A is NULL");
+    if (lda < std::max<int64_t>(1, k)) return fail(ctx, -6, "lda too small");
+    if (B && ldb < std::max<int64_t>(1, k)) return fail(ctx, -8, "ldb too small");
+    if (k > 0 && (!dd || !de)) return fail(ctx, -9, "dd/de is NULL");
+    if (n > 0 && !C) return fail(ctx, -11, "C is NULL");
+    if (ldc < std::max<int64_t>(1, n)) return fail(ctx, -12, "ldc too small");
+    hipStream_t st = as_stream(stream);
+    return guarded(ctx, [&]() {
+        if (n == 0 || k == 0) return;
+        ctx->ws.ensure(std::max(n, k));
+        Field F = make_field(p);
+        double* AD = ctx->ws.tmp2;
+        double* BD = ctx->ws.tmp2 + n * k;
+        hipLaunchKernelGGL(k_apply_d, dim3(nblk(k), (unsigned)n), dim3(256), 0, st, A, lda, n, k, dd, de, AD, F);
+        GemmSeg s0{MatV{AD, k, 1}, B ? MatV{(double*)B, 1, ldb} : MatV{(double*)A, 1, lda}, k};
+        GemmSeg s1{MatV{nullptr, 0, 1}, MatV{nullptr, 0, 1}, 0};
+        if (B) {
+            hipLaunchKernelGGL(k_apply_d, dim3(nblk(k), (unsigned)n), dim3(256), 0, st, B, ldb, n, k, dd, de, BD, F);
+            s1 = GemmSeg{MatV{BD, k, 1}, MatV{(double*)A, 1, lda}, k};
+        }
+        GemmSeg segs[2] = {s0, s1};
+        launch_gemm(st, F, n, n, C, ldc, segs, 2, true, false);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+    });
+}
+
+int pldl_trss(pldl_ctx* ctx, uint32_t p, int64_t n, const double* U, int64_t ldu, const double* C, int64_t ldc,
+              double* X, int64_t ldx, void* stream) {
+    if (!ctx) return -1;
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (n < 0 || 2 * n > 65535) return fail(ctx, -3, "n out of range");
+    if (n > 0 && !U) return fail(ctx, -4, "U is NULL");
+    if (ldu < std::max<int64_t>(1, n)) return fail(ctx, -5, "ldu too small");
+    if (n > 0 && !C) return fail(ctx, -6, "C is NULL");
+    if (ldc < std::max<int64_t>(1, n)) return fail(ctx, -7, "ldc too small");
+    if (n > 0 && !X) return fail(ctx, -8, "X is NULL");
+    if (ldx < std::max<int64_t>(1, n)) return fail(ctx, -9, "ldx too small");
+    hipStream_t st = as_stream(stream);
+    int bad_diag = 0;
+    int rc = guarded(ctx, [&]() {
+        if (n == 0) return;
+        int64_t N2 = 2 * n;
+        ctx->ws.ensure(N2);
+        Engine E(ctx->ws, st, p, N2, 128);
+        Workspace& ws = ctx->ws;
+        HIPCHK(hipMemsetAsync(ws.info, 0, sizeof(int32_t) * 4, st));
+        hipLaunchKernelGGL(k_trss_pack, dim3(nblk(n), (unsigned)n), dim3(256), 0, st, U, ldu, C, ldc, ws.W, N2, n, ws.info, p == 2 ? 1 : 0);
+        if (p == 2) {
+            int32_t* h = E.read_info(1);
+            if (h[0]) { bad_diag = 1; return; }
+        }
+        E.trss(n, n, 0);
+        hipLaunchKernelGGL(k_trss_unpack, dim3(nblk(n), (unsigned)n), dim3(256), 0, st, ws.W, N2, n, X, ldx);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+    });
+    if (rc == PLDL_OK && bad_diag) return fail(ctx, -6, "characteristic 2: C must have a zero diagonal");
+    return rc;
+}
+
+int pldl_plduq(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, double* Y, int64_t ldy, int32_t* rows, int32_t* cols,
+               int64_t* rank, void* stream) {
+    if (!ctx) return -1;
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (m < 0 || m + n > 65535) return fail(ctx, -3, "m out of range");
+    if (n < 0) return fail(ctx, -4, "n < 0");
+    if (m > 0 && n > 0 && !Y) return fail(ctx, -5, "Y is NULL");
+    if (ldy < std::max<int64_t>(1, n)) return fail(ctx, -6, "ldy too small");
+    if (m > 0 && !rows) return fail(ctx, -7, "rows is NULL");
+    if (n > 0 && !cols) return fail(ctx, -8, "cols is NULL");
+    if (!rank) return fail(ctx, -9, "rank is NULL");
+    hipStream_t st = as_stream(stream);
+    return guarded(ctx, [&]() {
+        int64_t N = m + n;
+        if (N == 0) { *rank = 0; return; }
+        ctx->ws.ensure(N);
+        Engine E(ctx->ws, st, p, N, 128);
+        Workspace& ws = ctx->ws;
+        hipLaunchKernelGGL(k_iota, dim3(nblk(N)), dim3(256), 0, st, ws.orig, N);
+        HIPCHK(hipMemsetAsync(ws.W, 0, sizeof(double) * N * N, st));
+        hipLaunchKernelGGL(k_plduq_pack, dim3(nblk(std::max<int64_t>(n, 1)), (unsigned)std::max<int64_t>(m, 1)), dim3(256), 0, st, Y, ldy, m, n, ws.W, N);
+        int64_t r = E.plduq(0, m, m, N);
+        hipLaunchKernelGGL(k_plduq_unpack, dim3(nblk(std::max<int64_t>(n, 1)), (unsigned)std::max<int64_t>(m, 1)), dim3(256), 0, st, ws.W, N, m, n, Y, ldy,
+                           ws.orig, rows, cols);
+        if (n > 0 && m == 0) hipLaunchKernelGGL(k_iota, dim3(nblk(n)), dim3(256), 0, st, cols, n);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        *rank = r;
+    });
+}
+
+}  // extern "C"

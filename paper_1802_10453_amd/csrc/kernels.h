@@ -1,0 +1,60 @@
+// kernels.h -- declarations of the kernels in kernels.hip (see there for semantics).
+#pragma once
+#include "common.h"
+
+namespace pldl {
+
+__global__ void k_bc_leaf(double* W, int64_t ld, int64_t lo, int s, Field F, double* dd, double* de,
+                          int32_t* sig_out, int32_t* rank_out);
+__global__ void k_plduq_leaf(double* W, int64_t ld, int64_t a0, int m, int64_t c0, int nc, Field F,
+                             int32_t* rsig, int32_t* csig, int32_t* rank_out);
+__global__ void k_trss_leaf(double* W, int64_t ld, int64_t s0, int64_t u0, int r, Field F);
+__global__ void k_trsm_ru_leaf(double* B, int64_t ld, int64_t m, int r, MatV T, Field F);
+__global__ void k_trsm_ll_leaf(double* B, int64_t ld, int64_t ncols, int r, MatV T, Field F);
+__global__ void k_perm_gather(const double* W, int64_t ld, int64_t n, int64_t lo, int64_t hi, const int32_t* sig,
+                              double* tmp, const int32_t* orig, int32_t* tmpo, int parts);
+__global__ void k_perm_scatter(double* W, int64_t ld, int64_t n, int64_t lo, int64_t hi, const double* tmp,
+                               int32_t* orig, const int32_t* tmpo, int parts);
+__global__ void k_sigma_rotate(int32_t* sig, int64_t len1, int64_t len2);
+__global__ void k_sigma_merge(const int32_t* orig, int64_t a, int64_t n1, int64_t n2, int32_t* sig);
+__global__ void k_block_dinv(const double* dd, const double* de, int64_t lo, int64_t r, Field F, double* xinv,
+                             double* yy, int8_t* kind);
+__global__ void k_scal_dinv(double* X, int64_t ldx, int64_t rows, int64_t r, const double* xinv, const double* yy,
+                            const int8_t* kind, double* T, int64_t ldt, Field F);
+__global__ void k_pack_dinv(const double* W, int64_t ld, int64_t c0, int64_t a0, int64_t r, Field F, double* dinv);
+__global__ void k_scale_by(double* X, int64_t ld, int64_t rows, int64_t cols, const double* dinv, int by_row, Field F);
+__global__ void k_mul_cols(const double* X, int64_t ldx, int64_t rows, int64_t cols, const double* dinv, int lower,
+                           double* out, int64_t ldo, Field F);
+__global__ void k_copy2d(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t rows, int64_t cols);
+__global__ void k_zlp_assemble(const double* W, int64_t ld, int64_t lo, int64_t mz, int64_t hi, int64_t rY,
+                               const double* G1, int64_t ldg1, const double* G2, int64_t ldg2, double* tmp);
+__global__ void k_zlp_orig_d(int32_t* orig, int32_t* tmpo, int64_t lo, int64_t mz, int64_t hi, int64_t rY,
+                             const double* W, int64_t ld, const double* delta, double* dd, double* de, int phase);
+__global__ void k_save_pack_diag(const double* W, int64_t ld, int64_t s0, int64_t lo, int64_t rY, double* out);
+__global__ void k_delta(const double* W, int64_t ld, int64_t s0, int64_t u0, int64_t r, Field F, double* delta);
+__global__ void k_u1t_delta(const double* W, int64_t ld, int64_t s0, int64_t u0, int64_t r, const double* delta,
+                            double* UT, double* UTD, Field F);
+__global__ void k_dadd(double* W, int64_t ld, int64_t s0, int64_t u0, int64_t r, const double* delta, Field F);
+__global__ void k_mul_delta(const double* V, int64_t ldv, int64_t rows, int64_t r, const double* delta, double* out,
+                            Field F);
+template <typename T>
+__global__ void k_load_input(const T* A, int64_t lda, double* W, int64_t ld, int64_t n, Field F, int32_t* err);
+template <typename T>
+__global__ void k_store_output(T* A, int64_t lda, const double* W, int64_t ld, int64_t n, const double* dd,
+                               const double* de, T* e, const int32_t* orig, int32_t* perm);
+__global__ void k_rpm(const int32_t* orig, const double* de, int64_t n, int64_t r, int32_t* rpm);
+__global__ void k_char2_std(double* W, int64_t ld, int64_t n, double* dd, double* de, int32_t* orig, double* tmp,
+                            int phase);
+
+__global__ void k_iota(int32_t* a, int64_t n);
+__global__ void k_zlp_sigma(int32_t* sig, int64_t mz, int64_t nc, int64_t rY);
+__global__ void k_apply_d(const double* A, int64_t lda, int64_t n, int64_t k, const double* dd, const double* de,
+                          double* out, Field F);
+__global__ void k_trss_pack(const double* U, int64_t ldu, const double* C, int64_t ldc, double* W, int64_t ldw,
+                            int64_t n, int32_t* info, int check_char2);
+__global__ void k_trss_unpack(const double* W, int64_t ldw, int64_t n, double* X, int64_t ldx);
+__global__ void k_plduq_pack(const double* Y, int64_t ldy, int64_t m, int64_t n, double* W, int64_t ldw);
+__global__ void k_plduq_unpack(const double* W, int64_t ldw, int64_t m, int64_t n, double* Y, int64_t ldy,
+                               const int32_t* orig, int32_t* rows, int32_t* cols);
+
+}  // namespace pldl

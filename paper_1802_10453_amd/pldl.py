@@ -1,0 +1,172 @@
+"""Thin ctypes binding of ``libpldl.so`` (the C-ABI of ``include/pldl.h``).
+
+Argument marshalling only: every step of the factorization runs in the HIP
+library.  Tensors are torch tensors on the context's GPU; the current torch
+stream is passed to every call.  If the library is missing this module raises
+at import time -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpldl.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_1802_10453_amd.build.build() "
+                      "(hipcc for gfx950); the library has no CPU fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp, _i64, _i32, _u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32
+
+PLDL_U32, PLDL_F64 = 0, 1
+PLDL_PATH_AUTO, PLDL_PATH_F64 = 0, 1
+ERRORS = {1: "PLDL_ERANGE", 2: "PLDL_EUNSUPPORTED_P", 3: "PLDL_EHIP", 4: "PLDL_ENOMEM", 5: "PLDL_EINTERNAL"}
+
+
+class pldl_opts(ctypes.Structure):
+    _fields_ = [("path", _i32), ("threshold", _i32), ("standard_form", _i32), ("check_range", _i32)]
+
+
+_lib.pldl_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int]
+_lib.pldl_destroy.argtypes = [_vp]
+_lib.pldl_last_error.argtypes = [_vp]
+_lib.pldl_last_error.restype = ctypes.c_char_p
+_lib.pldl_factor.argtypes = [_vp, _u32, _i64, _vp, _i64, _i32, _vp, _vp, _vp, ctypes.POINTER(_i64),
+                             ctypes.POINTER(pldl_opts), _vp]
+_lib.pldl_gemm.argtypes = [_vp, _u32, _i64, _i64, _i64, _vp, _i64, _i32, _vp, _i64, _i32, _vp, _i64, _i32, _vp]
+_lib.pldl_trsm.argtypes = [_vp, _u32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp]
+_lib.pldl_syrdk.argtypes = [_vp, _u32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _i64, _vp]
+_lib.pldl_trss.argtypes = [_vp, _u32, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]
+_lib.pldl_plduq.argtypes = [_vp, _u32, _i64, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(_i64), _vp]
+for _f in ("pldl_create", "pldl_destroy", "pldl_factor", "pldl_gemm", "pldl_trsm", "pldl_syrdk", "pldl_trss",
+           "pldl_plduq"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+EXPORTED = ("pldl_create", "pldl_destroy", "pldl_last_error", "pldl_factor", "pldl_gemm", "pldl_trsm",
+            "pldl_syrdk", "pldl_trss", "pldl_plduq")
+
+
+class PldlError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ld(t):
+    assert t.dim() == 2 and t.stride(1) == 1, "row-major tensor with unit column stride expected"
+    return max(t.stride(0), 1)
+
+
+class Context:
+    """One library context on one GPU (``pldl_create`` / ``pldl_destroy``)."""
+
+    def __init__(self, device: int = 0):
+        h = _vp()
+        rc = _lib.pldl_create(ctypes.byref(h), int(device))
+        if rc != 0:
+            raise PldlError(rc, f"pldl_create(device={device}) failed")
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.pldl_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise PldlError(rc, _lib.pldl_last_error(self._h).decode())
+
+    def last_error(self) -> str:
+        return _lib.pldl_last_error(self._h).decode()
+
+    # ------------------------------------------------------------------ pldl_factor
+    def factor(self, A: torch.Tensor, p: int, threshold: int = 0, standard_form: bool = False,
+               check_range: bool = True):
+        """Factor the symmetric A (lower triangle; int32 holding uint32 residues, or float64)
+        in place.  Returns dict(perm, rpm, e, rank)."""
+        n = A.shape[0]
+        assert A.dim() == 2 and A.shape[1] == n and A.is_cuda
+        if A.dtype == torch.int32:
+            dt = PLDL_U32
+        elif A.dtype == torch.float64:
+            dt = PLDL_F64
+        else:
+            raise TypeError("A must be int32 (uint32 residues) or float64")
+        e = torch.zeros(max(n, 1), dtype=A.dtype, device=A.device)
+        perm = torch.zeros(max(n, 1), dtype=torch.int32, device=A.device)
+        rpm = torch.zeros(max(n, 1), dtype=torch.int32, device=A.device)
+        rank = _i64(0)
+        o = pldl_opts(PLDL_PATH_AUTO, int(threshold), int(bool(standard_form)), int(bool(check_range)))
+        rc = _lib.pldl_factor(self._h, int(p), n, _ptr(A), _ld(A) if n else 1, dt, _ptr(e), _ptr(perm), _ptr(rpm),
+                              ctypes.byref(rank), ctypes.byref(o), _stream())
+        self._check(rc)
+        return dict(perm=perm[:n], rpm=rpm[:n], e=e[:n], rank=int(rank.value))
+
+    def factor_raw(self, p, n, A_ptr, lda, dtype, e_ptr, perm_ptr, rpm_ptr, opts=None):
+        """Direct call with raw device pointers (used by the boundary tests)."""
+        rank = _i64(0)
+        rc = _lib.pldl_factor(self._h, p, n, A_ptr, lda, dtype, e_ptr, perm_ptr, rpm_ptr, ctypes.byref(rank),
+                              ctypes.byref(opts) if opts is not None else None, _stream())
+        return rc, int(rank.value)
+
+    # ------------------------------------------------------------------ building blocks
+    def gemm(self, p, C, A, B, transA=False, transB=False, lower_only=False):
+        m, n = C.shape
+        k = A.shape[0] if transA else A.shape[1]
+        rc = _lib.pldl_gemm(self._h, p, m, n, k, _ptr(A), _ld(A), int(transA), _ptr(B), _ld(B), int(transB),
+                            _ptr(C), _ld(C), int(lower_only), _stream())
+        self._check(rc)
+        return C
+
+    def trsm(self, p, T, B, lower: bool):
+        m, n = B.shape
+        rc = _lib.pldl_trsm(self._h, p, int(lower), m, n, _ptr(T), _ld(T), _ptr(B), _ld(B), _stream())
+        self._check(rc)
+        return B
+
+    def syrdk(self, p, C, A, dd, de, B=None):
+        n, k = A.shape
+        rc = _lib.pldl_syrdk(self._h, p, n, k, _ptr(A), _ld(A), _ptr(B), _ld(B) if B is not None else 1,
+                             _ptr(dd), _ptr(de), _ptr(C), _ld(C), _stream())
+        self._check(rc)
+        return C
+
+    def trss(self, p, U, C):
+        n = U.shape[0]
+        X = torch.zeros_like(C)
+        rc = _lib.pldl_trss(self._h, p, n, _ptr(U), _ld(U), _ptr(C), _ld(C), _ptr(X), _ld(X), _stream())
+        self._check(rc)
+        return X
+
+    def plduq(self, p, Y):
+        m, n = Y.shape
+        rows = torch.zeros(max(m, 1), dtype=torch.int32, device=Y.device)
+        cols = torch.zeros(max(n, 1), dtype=torch.int32, device=Y.device)
+        rank = _i64(0)
+        rc = _lib.pldl_plduq(self._h, p, m, n, _ptr(Y), _ld(Y), _ptr(rows), _ptr(cols), ctypes.byref(rank),
+                             _stream())
+        self._check(rc)
+        return dict(rows=rows[:m], cols=cols[:n], LU=Y, rank=int(rank.value))
+
+
+def lib():
+    return _lib
