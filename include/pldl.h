@@ -146,6 +146,37 @@ int pldl_trss(pldl_ctx *ctx, uint32_t p, int64_t n, const double *U, int64_t ldu
 int pldl_plduq(pldl_ctx *ctx, uint32_t p, int64_t m, int64_t n, double *Y, int64_t ldy,
                int32_t *rows, int32_t *cols, int64_t *rank, void *stream);
 
+/* ---------------- measurement ---------------- */
+
+/* Per-kernel-class totals collected with HIP events recorded around every
+ * launch the library makes on the caller's stream while profiling is on. */
+#define PLDL_NCLASS 8
+#define PLDL_CLASS_GEMM 0        /* mod-p MFMA products (GEMM/TRMM/SYRDK/SYRD2K)   */
+#define PLDL_CLASS_TRSM_LEAF 1   /* triangular-solve leaves                         */
+#define PLDL_CLASS_BASE_CASE 2   /* base case of Section 5                          */
+#define PLDL_CLASS_PLDUQ_LEAF 3  /* PLDUQ tile leaves                               */
+#define PLDL_CLASS_TRSS_LEAF 4   /* TRSS leaves                                     */
+#define PLDL_CLASS_PERM 5        /* symmetric permutations / assembly moves          */
+#define PLDL_CLASS_OTHER 6       /* scaling, bookkeeping, input/output kernels      */
+#define PLDL_CLASS_HOST_SYNC 7   /* host waits for a rank (launches = count, ms = wall) */
+typedef struct {
+    int64_t launches;  /* number of launches (or synchronisations)               */
+    double flops;      /* algorithmic FP64 flops (2 per multiply-add), class 0     */
+    double bytes;      /* algorithmic HBM bytes (read + write), class 5            */
+    double ms;         /* summed GPU duration of the launches (event-timed)        */
+} pldl_kstat;
+typedef struct {
+    pldl_kstat cls[PLDL_NCLASS];
+} pldl_stats;
+
+/*
+ * Profiling control.  mode 1: reset the totals and start recording; mode 0:
+ * stop recording; mode 2: leave the state unchanged.  In every mode `out`
+ * (host, may be NULL) receives the totals gathered so far.  Recording adds two
+ * events per launch; it never changes results.
+ */
+int pldl_profile(pldl_ctx *ctx, int32_t mode, pldl_stats *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,7 +15,9 @@
 #include <cstdio>
 #include <cstring>
 #include <stdexcept>
+#include <chrono>
 #include <string>
+#include <vector>
 
 #include "../../include/pldl.h"
 #include "common.h"
@@ -56,6 +58,69 @@ struct Err : std::runtime_error {
     } while (0)
 
 static inline unsigned nblk(int64_t x, int b = 256) { return (unsigned)((x + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// Profiling: HIP events around each launch, harvested at host synchronisations.
+struct Prof {
+    bool on = false;
+    pldl_stats tot{};
+    struct Rec { hipEvent_t a, b; int cls; double flops, bytes; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t open_a = nullptr;
+    int open_cls = -1;
+    double open_f = 0.0, open_b = 0.0;
+    hipEvent_t ev() {
+        if (pool.empty()) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            return e;
+        }
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    void begin(hipStream_t st, int c, double flops = 0.0, double bytes = 0.0) {
+        if (!on) return;
+        open_a = ev();
+        HIPCHK(hipEventRecord(open_a, st));
+        open_cls = c; open_f = flops; open_b = bytes;
+    }
+    void end(hipStream_t st) {
+        if (!on || open_cls < 0) return;
+        hipEvent_t b = ev();
+        HIPCHK(hipEventRecord(b, st));
+        recs.push_back(Rec{open_a, b, open_cls, open_f, open_b});
+        open_cls = -1;
+    }
+    void harvest() {
+        for (Rec& r : recs) {
+            HIPCHK(hipEventSynchronize(r.b));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+            pldl_kstat& k = tot.cls[r.cls];
+            k.launches += 1; k.flops += r.flops; k.bytes += r.bytes; k.ms += ms;
+            pool.push_back(r.a); pool.push_back(r.b);
+        }
+        recs.clear();
+    }
+    void host_wait(double ms) {
+        if (!on) return;
+        tot.cls[PLDL_CLASS_HOST_SYNC].launches += 1;
+        tot.cls[PLDL_CLASS_HOST_SYNC].ms += ms;
+    }
+    ~Prof() {
+        for (Rec& r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+#define LAUNCH(CLS, KERNEL, GRID, BLOCK, SHM, STREAM, ...)                  \
+    do {                                                                   \
+        prof->begin(STREAM, CLS);                                          \
+        hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, __VA_ARGS__); \
+        prof->end(STREAM);                                                 \
+    } while (0)
 
 // ---------------------------------------------------------------------------
 // Workspace: device buffers sized for order n (grown monotonically).
@@ -119,7 +184,9 @@ struct Engine {
     int t_leaf;
     Workspace& ws;
     double* W;
-    Engine(Workspace& w, hipStream_t s, uint32_t p, int64_t n_, int t) : st(s), F(make_field(p)), n(n_), ld(std::max<int64_t>(n_, 1)), t_leaf(t), ws(w), W(w.W) {}
+    Prof* prof;
+    Engine(Workspace& w, hipStream_t s, uint32_t p, int64_t n_, int t, Prof* pr)
+        : st(s), F(make_field(p)), n(n_), ld(std::max<int64_t>(n_, 1)), t_leaf(t), ws(w), W(w.W), prof(pr) {}
 
     // bounds of a view inside W (every view the algorithms form lies in W's lower triangle)
     void chk(int64_t r0, int64_t c0, int64_t rows, int64_t cols) const {
@@ -129,8 +196,13 @@ struct Engine {
     MatV vcol(int64_t r0, int64_t c0) { return MatV{W + r0 * ld + c0, 1, ld}; }  // W[r0+j][c0+i]
 
     int32_t* read_info(int cnt) {
+        auto t0 = std::chrono::steady_clock::now();
         HIPCHK(hipMemcpyAsync(ws.hinfo, ws.info, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        if (prof->on) {
+            prof->host_wait(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+            prof->harvest();
+        }
         return ws.hinfo;
     }
 
@@ -139,7 +211,11 @@ struct Engine {
         if (m <= 0 || nn <= 0 || (s0.k <= 0 && s1.k <= 0)) return;
         GemmSeg segs[2] = {s0, s1};
         if (s0.k > 0 && s1.k > 0) REQUIRE((s0.A.cs == 1) == (s1.A.cs == 1) && (s0.B.cs == 1) == (s1.B.cs == 1));
+        double kk = (double)std::max<int64_t>(s0.k, 0) + (double)std::max<int64_t>(s1.k, 0);
+        double outs = lower ? (double)m * (double)(m + 1) / 2.0 : (double)m * (double)nn;
+        prof->begin(st, PLDL_CLASS_GEMM, 2.0 * outs * kk);
         launch_gemm(st, F, m, nn, C, ld, segs, 2, lower, b_upper);
+        prof->end(st);
     }
 
     // Symmetric permutation of [lo, hi): new lo+q <- old lo+sig[q].
@@ -152,12 +228,16 @@ struct Engine {
         if (rows <= 0 || cols <= 0) return;
         REQUIRE(rows <= 65535);
         dim3 g(nblk(cols), (unsigned)rows, 4);
+        double elems = ((parts & 1) ? (double)s * lo : 0.0) + ((parts & 2) ? (double)s * (s + 1) / 2.0 : 0.0) +
+                       ((parts & 4) ? (double)s * (n - hi) : 0.0);
+        prof->begin(st, PLDL_CLASS_PERM, 0.0, 16.0 * elems);
         hipLaunchKernelGGL(k_perm_gather, g, dim3(256), 0, st, W, ld, n, lo, hi, sig, ws.tmp1, ws.orig, ws.tmpo, parts);
         hipLaunchKernelGGL(k_perm_scatter, g, dim3(256), 0, st, W, ld, n, lo, hi, ws.tmp1, ws.orig, ws.tmpo, parts);
+        prof->end(st);
     }
     void rotate(int64_t a, int64_t b, int64_t c) {
         if (a == b || b == c) return;
-        hipLaunchKernelGGL(k_sigma_rotate, dim3(nblk(c - a)), dim3(256), 0, st, ws.sig, b - a, c - b);
+        LAUNCH(PLDL_CLASS_OTHER, k_sigma_rotate, dim3(nblk(c - a)), dim3(256), 0, st, ws.sig, b - a, c - b);
         perm_sym(a, c, ws.sig, 15);
     }
 
@@ -166,7 +246,7 @@ struct Engine {
     void trsm_ru(MatV B, int64_t m, int64_t r, MatV T) {
         if (m <= 0 || r <= 0) return;
         if (r <= 64) {
-            hipLaunchKernelGGL(k_trsm_ru_leaf, dim3(nblk(m, 64)), dim3(256), 0, st, B.p, B.rs, m, (int)r, T, F);
+            LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trsm_ru_leaf, dim3(nblk(m, 64)), dim3(256), 0, st, B.p, B.rs, m, (int)r, T, F);
             return;
         }
         int64_t r1 = std::max<int64_t>(64, (r / 2) / 64 * 64);
@@ -178,7 +258,7 @@ struct Engine {
     void trsm_ll(MatV B, int64_t r, int64_t ncols, MatV T) {
         if (r <= 0 || ncols <= 0) return;
         if (r <= 64) {
-            hipLaunchKernelGGL(k_trsm_ll_leaf, dim3(nblk(ncols, 64)), dim3(256), 0, st, B.p, B.rs, ncols, (int)r, T, F);
+            LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trsm_ll_leaf, dim3(nblk(ncols, 64)), dim3(256), 0, st, B.p, B.rs, ncols, (int)r, T, F);
             return;
         }
         int64_t r1 = std::max<int64_t>(64, (r / 2) / 64 * 64);
@@ -188,14 +268,16 @@ struct Engine {
     }
     void gemm_ld(double* C, int64_t ldc, int64_t m, int64_t nn, GemmSeg s0) {
         if (m <= 0 || nn <= 0 || s0.k <= 0) return;
+        prof->begin(st, PLDL_CLASS_GEMM, 2.0 * (double)m * (double)nn * (double)s0.k);
         launch_gemm(st, F, m, nn, C, ldc, &s0, 1, false, false);
+        prof->end(st);
     }
 
     // ---- base case (Section 5) ------------------------------------------------
     int64_t bc(int64_t lo, int64_t hi) {
         int s = (int)(hi - lo);
         REQUIRE(s >= 1 && s <= 128);
-        hipLaunchKernelGGL(k_bc_leaf, dim3(1), dim3(1024), 0, st, W, ld, lo, s, F, ws.dd, ws.de, ws.info + 1, ws.info);
+        LAUNCH(PLDL_CLASS_BASE_CASE, k_bc_leaf, dim3(1), dim3(1024), 0, st, W, ld, lo, s, F, ws.dd, ws.de, ws.info + 1, ws.info);
         int32_t* h = read_info(1 + s);
         int64_t r = h[0];
         bool ident = true;
@@ -223,8 +305,8 @@ struct Engine {
             // Y^T = B'2^T - X^T M1^T, M1 = W[lo+r1 : lo+m, lo : lo+r1]
             if (m > r1) gemm(W + s * ld + lo + r1, n2, m - r1, GemmSeg{vrow(s, lo), vcol(lo + r1, lo), r1});
             // SCAL: T <- X^T, G = X^T D1^{-1} in place
-            hipLaunchKernelGGL(k_block_dinv, dim3(nblk(r1)), dim3(256), 0, st, ws.dd, ws.de, lo, r1, F, ws.xinv, ws.yy, ws.kind);
-            hipLaunchKernelGGL(k_scal_dinv, dim3(nblk(r1), (unsigned)n2), dim3(256), 0, st, W + s * ld + lo, ld, n2, r1,
+            LAUNCH(PLDL_CLASS_OTHER, k_block_dinv, dim3(nblk(r1)), dim3(256), 0, st, ws.dd, ws.de, lo, r1, F, ws.xinv, ws.yy, ws.kind);
+            LAUNCH(PLDL_CLASS_OTHER, k_scal_dinv, dim3(nblk(r1), (unsigned)n2), dim3(256), 0, st, W + s * ld + lo, ld, n2, r1,
                                ws.xinv, ws.yy, ws.kind, ws.tmp2, r1, F);
             // SYRDK: Z = C - G D1 G^T = lower(C - G X)
             gemm(W + s * ld + s, n2, n2, GemmSeg{vrow(s, lo), MatV{ws.tmp2, 1, r1}, r1}, GemmSeg{MatV{nullptr, 0, 1}, MatV{nullptr, 0, 1}, 0}, true);
@@ -247,21 +329,21 @@ struct Engine {
         double* delta = ws.dvec;          // Delta (rY) then the pack diagonal d (rY)
         if (rY > 0) {
             HIPCHK(hipMemsetAsync(delta, 0, rY * sizeof(double), st));
-            hipLaunchKernelGGL(k_save_pack_diag, dim3(nblk(rY)), dim3(256), 0, st, W, ld, s0, lo, rY, delta + rY);
+            LAUNCH(PLDL_CLASS_OTHER, k_save_pack_diag, dim3(nblk(rY)), dim3(256), 0, st, W, ld, s0, lo, rY, delta + rY);
             if (F.ip == 2) {
                 REQUIRE(rY <= 8192);
-                hipLaunchKernelGGL(k_delta, dim3(1), dim3(1024), rY * sizeof(double), st, W, ld, s0, lo, rY, F, delta);
-                hipLaunchKernelGGL(k_u1t_delta, dim3(nblk(rY), (unsigned)rY), dim3(256), 0, st, W, ld, s0, lo, rY, delta, UT, UTD, F);
+                LAUNCH(PLDL_CLASS_OTHER, k_delta, dim3(1), dim3(1024), rY * sizeof(double), st, W, ld, s0, lo, rY, F, delta);
+                LAUNCH(PLDL_CLASS_OTHER, k_u1t_delta, dim3(nblk(rY), (unsigned)rY), dim3(256), 0, st, W, ld, s0, lo, rY, delta, UT, UTD, F);
                 // C'1 <- C'1 - U1^T Delta U1 (lower)
                 gemm(W + s0 * ld + s0, rY, rY, GemmSeg{MatV{UTD, rY, 1}, MatV{UT, 1, rY}, rY},
                      GemmSeg{MatV{nullptr, 0, 1}, MatV{nullptr, 0, 1}, 0}, true);
             }
             trss(s0, rY, lo);
             // G1 = X^T D1^{-1} (lower)
-            hipLaunchKernelGGL(k_pack_dinv, dim3(nblk(rY)), dim3(256), 0, st, W, ld, s0, lo, rY, F, ws.xinv);
-            hipLaunchKernelGGL(k_mul_cols, dim3(nblk(rY), (unsigned)rY), dim3(256), 0, st, W + s0 * ld + s0, ld, rY, rY, ws.xinv, 1, G1, rY, F);
+            LAUNCH(PLDL_CLASS_OTHER, k_pack_dinv, dim3(nblk(rY)), dim3(256), 0, st, W, ld, s0, lo, rY, F, ws.xinv);
+            LAUNCH(PLDL_CLASS_OTHER, k_mul_cols, dim3(nblk(rY), (unsigned)rY), dim3(256), 0, st, W + s0 * ld + s0, ld, rY, rY, ws.xinv, 1, G1, rY, F);
             if (F.ip == 2)
-                hipLaunchKernelGGL(k_dadd, dim3(nblk(rY), (unsigned)rY), dim3(256), 0, st, W, ld, s0, lo, rY, delta, F);
+                LAUNCH(PLDL_CLASS_OTHER, k_dadd, dim3(nblk(rY), (unsigned)rY), dim3(256), 0, st, W, ld, s0, lo, rY, delta, F);
             if (nz > 0) {
                 chk(s0 + rY, lo, nz, mz + rY);
                 // C''2^T = C'2^T - V1^T X   (X upper = transpose of the stored X^T)
@@ -274,29 +356,29 @@ struct Engine {
                      GemmSeg{vrow(s0 + rY, lo), vcol(s0 + rY, s0), rY}, true);
                 if (F.ip == 2) {
                     // Z <- Z - V1^T Delta V1
-                    hipLaunchKernelGGL(k_mul_delta, dim3(nblk(rY), (unsigned)nz), dim3(256), 0, st, W + (s0 + rY) * ld + lo, ld, nz, rY, delta, VD, F);
+                    LAUNCH(PLDL_CLASS_OTHER, k_mul_delta, dim3(nblk(rY), (unsigned)nz), dim3(256), 0, st, W + (s0 + rY) * ld + lo, ld, nz, rY, delta, VD, F);
                     gemm(W + (s0 + rY) * ld + s0 + rY, nz, nz, GemmSeg{MatV{VD, rY, 1}, vcol(s0 + rY, lo), rY},
                          GemmSeg{MatV{nullptr, 0, 1}, MatV{nullptr, 0, 1}, 0}, true);
                 }
                 // G2 = Y2^T D1^{-1}
-                hipLaunchKernelGGL(k_mul_cols, dim3(nblk(rY), (unsigned)nz), dim3(256), 0, st, W + (s0 + rY) * ld + s0, ld, nz, rY, ws.xinv, 0, G2, rY, F);
+                LAUNCH(PLDL_CLASS_OTHER, k_mul_cols, dim3(nblk(rY), (unsigned)nz), dim3(256), 0, st, W + (s0 + rY) * ld + s0, ld, nz, rY, ws.xinv, 0, G2, rY, F);
             }
         }
         // ---- assembly: [pairs (P_i interleave) | Z | non-pivot rows of the zero block]
         REQUIRE(N <= 65535);
-        hipLaunchKernelGGL(k_zlp_assemble, dim3(nblk(N), (unsigned)N), dim3(256), 0, st, W, ld, lo, mz, hi, rY, G1,
+        LAUNCH(PLDL_CLASS_PERM, k_zlp_assemble, dim3(nblk(N), (unsigned)N), dim3(256), 0, st, W, ld, lo, mz, hi, rY, G1,
                            std::max<int64_t>(rY, 1), G2, std::max<int64_t>(rY, 1), ws.tmp1);
-        hipLaunchKernelGGL(k_copy2d, dim3(nblk(N), (unsigned)N), dim3(256), 0, st, W + lo * ld + lo, ld, ws.tmp1, N, N, N);
+        LAUNCH(PLDL_CLASS_PERM, k_copy2d, dim3(nblk(N), (unsigned)N), dim3(256), 0, st, W + lo * ld + lo, ld, ws.tmp1, N, N, N);
         // sigma of the assembly for the L part, the rows below and orig
-        hipLaunchKernelGGL(k_zlp_sigma, dim3(nblk(N)), dim3(256), 0, st, ws.sig, mz, nc, rY);
+        LAUNCH(PLDL_CLASS_OTHER, k_zlp_sigma, dim3(nblk(N)), dim3(256), 0, st, ws.sig, mz, nc, rY);
         perm_sym(lo, hi, ws.sig, 1 | 4 | 8);
         if (rY > 0)
-            hipLaunchKernelGGL(k_zlp_orig_d, dim3(nblk(N)), dim3(256), 0, st, ws.orig, ws.tmpo, lo, mz, hi, rY, W, ld, delta, ws.dd, ws.de, 2);
+            LAUNCH(PLDL_CLASS_OTHER, k_zlp_orig_d, dim3(nblk(N)), dim3(256), 0, st, ws.orig, ws.tmpo, lo, mz, hi, rY, W, ld, delta, ws.dd, ws.de, 2);
         int64_t rz = recall(lo + 2 * rY, lo + 2 * rY + nz);
         // non-pivots of Z and of the zero block, merged by original index
         int64_t a = lo + 2 * rY + rz, n1 = nz - rz;
         if (n1 > 0 && nr > 0) {
-            hipLaunchKernelGGL(k_sigma_merge, dim3(nblk(n1 + nr)), dim3(256), 0, st, ws.orig, a, n1, nr, ws.sig);
+            LAUNCH(PLDL_CLASS_OTHER, k_sigma_merge, dim3(nblk(n1 + nr)), dim3(256), 0, st, ws.orig, a, n1, nr, ws.sig);
             perm_sym(a, hi, ws.sig, 1 | 4 | 8);
         }
         return 2 * rY + rz;
@@ -309,7 +391,7 @@ struct Engine {
         if (m <= 0 || nc <= 0) return 0;
         chk(c0, a0, nc, m);
         if (m <= 32 && nc <= 256) {
-            hipLaunchKernelGGL(k_plduq_leaf, dim3(1), dim3(1024), 0, st, W, ld, a0, (int)m, c0, (int)nc, F, ws.sig,
+            LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_leaf, dim3(1), dim3(1024), 0, st, W, ld, a0, (int)m, c0, (int)nc, F, ws.sig,
                                ws.sig + 32, ws.info);
             int64_t r = read_info(1)[0];
             perm_sym(a0, a1, ws.sig, 15);
@@ -326,8 +408,8 @@ struct Engine {
                 // Y_b2^T -= V_t^T Wb^T
                 if (nc > r1) gemm(W + (c0 + r1) * ld + am, nc - r1, mb, GemmSeg{vrow(c0 + r1, a0), vrow(c0, am), r1});
                 // L_b^T = D_t^{-1} Wb^T
-                hipLaunchKernelGGL(k_pack_dinv, dim3(nblk(r1)), dim3(256), 0, st, W, ld, c0, a0, r1, F, ws.xinv);
-                hipLaunchKernelGGL(k_scale_by, dim3(nblk(mb), (unsigned)r1), dim3(256), 0, st, W + c0 * ld + am, ld, r1, mb, ws.xinv, 1, F);
+                LAUNCH(PLDL_CLASS_OTHER, k_pack_dinv, dim3(nblk(r1)), dim3(256), 0, st, W, ld, c0, a0, r1, F, ws.xinv);
+                LAUNCH(PLDL_CLASS_OTHER, k_scale_by, dim3(nblk(mb), (unsigned)r1), dim3(256), 0, st, W + c0 * ld + am, ld, r1, mb, ws.xinv, 1, F);
             }
             int64_t r2 = plduq(am, a1, c0 + r1, c1);
             rotate(a0 + r1, am, am + r2);
@@ -341,8 +423,8 @@ struct Engine {
             trsm_ru(vrow(cm, a0), nr_, r1, vrow(c0, a0));
             // Y_R[np]^T -= (D U_R)^T M_t^T
             if (m > r1) gemm(W + cm * ld + a0 + r1, nr_, m - r1, GemmSeg{vrow(cm, a0), vrow(c0, a0 + r1), r1});
-            hipLaunchKernelGGL(k_pack_dinv, dim3(nblk(r1)), dim3(256), 0, st, W, ld, c0, a0, r1, F, ws.xinv);
-            hipLaunchKernelGGL(k_scale_by, dim3(nblk(r1), (unsigned)nr_), dim3(256), 0, st, W + cm * ld + a0, ld, nr_, r1, ws.xinv, 0, F);
+            LAUNCH(PLDL_CLASS_OTHER, k_pack_dinv, dim3(nblk(r1)), dim3(256), 0, st, W, ld, c0, a0, r1, F, ws.xinv);
+            LAUNCH(PLDL_CLASS_OTHER, k_scale_by, dim3(nblk(r1), (unsigned)nr_), dim3(256), 0, st, W + cm * ld + a0, ld, nr_, r1, ws.xinv, 0, F);
         }
         int64_t r2 = plduq(a0 + r1, a1, cm, c1);
         rotate(c0 + r1, cm, cm + r2);
@@ -353,7 +435,7 @@ struct Engine {
     void trss(int64_t s0, int64_t r, int64_t u0) {
         if (r <= 0) return;
         if (r <= 64) {
-            hipLaunchKernelGGL(k_trss_leaf, dim3(1), dim3(64), 0, st, W, ld, s0, u0, (int)r, F);
+            LAUNCH(PLDL_CLASS_TRSS_LEAF, k_trss_leaf, dim3(1), dim3(64), 0, st, W, ld, s0, u0, (int)r, F);
             return;
         }
         int64_t h = std::max<int64_t>(64, (r / 2) / 64 * 64);
@@ -380,6 +462,7 @@ using namespace pldl;
 struct pldl_ctx {
     int device = 0;
     Workspace ws;
+    Prof prof;
     std::string err;
 };
 
@@ -396,6 +479,7 @@ int guarded(pldl_ctx* ctx, Fn&& fn) {
     try {
         HIPCHK(hipSetDevice(ctx->device));
         fn();
+        if (ctx->prof.on || !ctx->prof.recs.empty()) ctx->prof.harvest();
         ctx->err.clear();
         return PLDL_OK;
     } catch (const Err& e) {
@@ -453,33 +537,34 @@ int pldl_factor(pldl_ctx* ctx, uint32_t p, int64_t n, void* A, int64_t lda, int3
     hipStream_t st = as_stream(stream);
     return guarded(ctx, [&]() {
         ctx->ws.ensure(n);
-        Engine E(ctx->ws, st, p, n, t);
+        Engine E(ctx->ws, st, p, n, t, &ctx->prof);
+        Prof* prof = &ctx->prof;
         Workspace& ws = ctx->ws;
         HIPCHK(hipMemsetAsync(ws.info, 0, sizeof(int32_t) * 4, st));
         dim3 g(nblk(n), (unsigned)n);
         if (dtype == PLDL_U32)
-            hipLaunchKernelGGL(k_load_input<uint32_t>, g, dim3(256), 0, st, (const uint32_t*)A, lda, ws.W, E.ld, n, E.F, ws.info + 2);
+            LAUNCH(PLDL_CLASS_OTHER, k_load_input<uint32_t>, g, dim3(256), 0, st, (const uint32_t*)A, lda, ws.W, E.ld, n, E.F, ws.info + 2);
         else
-            hipLaunchKernelGGL(k_load_input<double>, g, dim3(256), 0, st, (const double*)A, lda, ws.W, E.ld, n, E.F, ws.info + 2);
+            LAUNCH(PLDL_CLASS_OTHER, k_load_input<double>, g, dim3(256), 0, st, (const double*)A, lda, ws.W, E.ld, n, E.F, ws.info + 2);
         if (o.check_range) {
             int32_t* h = E.read_info(3);
             if (h[2]) throw Err(PLDL_ERANGE, "input entry outside [0, p)");
         }
-        hipLaunchKernelGGL(k_iota, dim3(nblk(n)), dim3(256), 0, st, ws.orig, n);
+        LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(n)), dim3(256), 0, st, ws.orig, n);
         HIPCHK(hipMemsetAsync(ws.dd, 0, sizeof(double) * n, st));
         HIPCHK(hipMemsetAsync(ws.de, 0, sizeof(double) * n, st));
         int64_t r = E.recall(0, n);
-        hipLaunchKernelGGL(k_rpm, dim3(nblk(n)), dim3(256), 0, st, ws.orig, ws.de, n, r, rpm);
+        LAUNCH(PLDL_CLASS_OTHER, k_rpm, dim3(nblk(n)), dim3(256), 0, st, ws.orig, ws.de, n, r, rpm);
         if (o.standard_form && p == 2) {
             dim3 g2(nblk(n), (unsigned)n);
-            hipLaunchKernelGGL(k_char2_std, g2, dim3(256), 0, st, ws.W, E.ld, n, ws.dd, ws.de, ws.orig, ws.tmp1, 0);
-            hipLaunchKernelGGL(k_char2_std, g2, dim3(256), 0, st, ws.W, E.ld, n, ws.dd, ws.de, ws.orig, ws.tmp1, 1);
-            hipLaunchKernelGGL(k_char2_std, dim3(nblk(n)), dim3(256), 0, st, ws.W, E.ld, n, ws.dd, ws.de, ws.orig, ws.tmp1, 2);
+            LAUNCH(PLDL_CLASS_OTHER, k_char2_std, g2, dim3(256), 0, st, ws.W, E.ld, n, ws.dd, ws.de, ws.orig, ws.tmp1, 0);
+            LAUNCH(PLDL_CLASS_OTHER, k_char2_std, g2, dim3(256), 0, st, ws.W, E.ld, n, ws.dd, ws.de, ws.orig, ws.tmp1, 1);
+            LAUNCH(PLDL_CLASS_OTHER, k_char2_std, dim3(nblk(n)), dim3(256), 0, st, ws.W, E.ld, n, ws.dd, ws.de, ws.orig, ws.tmp1, 2);
         }
         if (dtype == PLDL_U32)
-            hipLaunchKernelGGL(k_store_output<uint32_t>, g, dim3(256), 0, st, (uint32_t*)A, lda, ws.W, E.ld, n, ws.dd, ws.de, (uint32_t*)e, ws.orig, perm);
+            LAUNCH(PLDL_CLASS_OTHER, k_store_output<uint32_t>, g, dim3(256), 0, st, (uint32_t*)A, lda, ws.W, E.ld, n, ws.dd, ws.de, (uint32_t*)e, ws.orig, perm);
         else
-            hipLaunchKernelGGL(k_store_output<double>, g, dim3(256), 0, st, (double*)A, lda, ws.W, E.ld, n, ws.dd, ws.de, (double*)e, ws.orig, perm);
+            LAUNCH(PLDL_CLASS_OTHER, k_store_output<double>, g, dim3(256), 0, st, (double*)A, lda, ws.W, E.ld, n, ws.dd, ws.de, (double*)e, ws.orig, perm);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
         *rank = r;
@@ -505,7 +590,11 @@ int pldl_gemm(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, int64_t k, const 
         Field F = make_field(p);
         GemmSeg s{transA ? MatV{(double*)A, 1, lda} : MatV{(double*)A, lda, 1},
                   transB ? MatV{(double*)B, 1, ldb} : MatV{(double*)B, ldb, 1}, k};
+        Prof* prof = &ctx->prof;
+        double outs = lower_only ? (double)m * (double)(m + 1) / 2.0 : (double)m * (double)n;
+        prof->begin(st, PLDL_CLASS_GEMM, 2.0 * outs * (double)k);
         launch_gemm(st, F, m, n, C, ldc, &s, 1, lower_only != 0, false);
+        prof->end(st);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
     });
@@ -525,7 +614,7 @@ int pldl_trsm(pldl_ctx* ctx, uint32_t p, int32_t lower, int64_t m, int64_t n, co
     hipStream_t st = as_stream(stream);
     return guarded(ctx, [&]() {
         ctx->ws.ensure(1);
-        Engine E(ctx->ws, st, p, 0, 128);
+        Engine E(ctx->ws, st, p, 0, 128, &ctx->prof);
         if (lower) E.trsm_ll(MatV{B, ldb, 1}, m, n, MatV{(double*)T, ldt, 1});
         else E.trsm_ru(MatV{B, ldb, 1}, m, n, MatV{(double*)T, ldt, 1});
         HIPCHK(hipGetLastError());
@@ -550,17 +639,20 @@ int pldl_syrdk(pldl_ctx* ctx, uint32_t p, int64_t n, int64_t k, const double* A,
         if (n == 0 || k == 0) return;
         ctx->ws.ensure(std::max(n, k));
         Field F = make_field(p);
+        Prof* prof = &ctx->prof;
         double* AD = ctx->ws.tmp2;
         double* BD = ctx->ws.tmp2 + n * k;
-        hipLaunchKernelGGL(k_apply_d, dim3(nblk(k), (unsigned)n), dim3(256), 0, st, A, lda, n, k, dd, de, AD, F);
+        LAUNCH(PLDL_CLASS_OTHER, k_apply_d, dim3(nblk(k), (unsigned)n), dim3(256), 0, st, A, lda, n, k, dd, de, AD, F);
         GemmSeg s0{MatV{AD, k, 1}, B ? MatV{(double*)B, 1, ldb} : MatV{(double*)A, 1, lda}, k};
         GemmSeg s1{MatV{nullptr, 0, 1}, MatV{nullptr, 0, 1}, 0};
         if (B) {
-            hipLaunchKernelGGL(k_apply_d, dim3(nblk(k), (unsigned)n), dim3(256), 0, st, B, ldb, n, k, dd, de, BD, F);
+            LAUNCH(PLDL_CLASS_OTHER, k_apply_d, dim3(nblk(k), (unsigned)n), dim3(256), 0, st, B, ldb, n, k, dd, de, BD, F);
             s1 = GemmSeg{MatV{BD, k, 1}, MatV{(double*)A, 1, lda}, k};
         }
         GemmSeg segs[2] = {s0, s1};
+        prof->begin(st, PLDL_CLASS_GEMM, 2.0 * (double)n * (double)(n + 1) / 2.0 * (double)(B ? 2 * k : k));
         launch_gemm(st, F, n, n, C, ldc, segs, 2, true, false);
+        prof->end(st);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
     });
@@ -583,16 +675,17 @@ int pldl_trss(pldl_ctx* ctx, uint32_t p, int64_t n, const double* U, int64_t ldu
         if (n == 0) return;
         int64_t N2 = 2 * n;
         ctx->ws.ensure(N2);
-        Engine E(ctx->ws, st, p, N2, 128);
+        Engine E(ctx->ws, st, p, N2, 128, &ctx->prof);
+        Prof* prof = &ctx->prof;
         Workspace& ws = ctx->ws;
         HIPCHK(hipMemsetAsync(ws.info, 0, sizeof(int32_t) * 4, st));
-        hipLaunchKernelGGL(k_trss_pack, dim3(nblk(n), (unsigned)n), dim3(256), 0, st, U, ldu, C, ldc, ws.W, N2, n, ws.info, p == 2 ? 1 : 0);
+        LAUNCH(PLDL_CLASS_OTHER, k_trss_pack, dim3(nblk(n), (unsigned)n), dim3(256), 0, st, U, ldu, C, ldc, ws.W, N2, n, ws.info, p == 2 ? 1 : 0);
         if (p == 2) {
             int32_t* h = E.read_info(1);
             if (h[0]) { bad_diag = 1; return; }
         }
         E.trss(n, n, 0);
-        hipLaunchKernelGGL(k_trss_unpack, dim3(nblk(n), (unsigned)n), dim3(256), 0, st, ws.W, N2, n, X, ldx);
+        LAUNCH(PLDL_CLASS_OTHER, k_trss_unpack, dim3(nblk(n), (unsigned)n), dim3(256), 0, st, ws.W, N2, n, X, ldx);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
     });
@@ -616,18 +709,30 @@ int pldl_plduq(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, double* Y, int64
         int64_t N = m + n;
         if (N == 0) { *rank = 0; return; }
         ctx->ws.ensure(N);
-        Engine E(ctx->ws, st, p, N, 128);
+        Engine E(ctx->ws, st, p, N, 128, &ctx->prof);
+        Prof* prof = &ctx->prof;
         Workspace& ws = ctx->ws;
-        hipLaunchKernelGGL(k_iota, dim3(nblk(N)), dim3(256), 0, st, ws.orig, N);
+        LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(N)), dim3(256), 0, st, ws.orig, N);
         HIPCHK(hipMemsetAsync(ws.W, 0, sizeof(double) * N * N, st));
-        hipLaunchKernelGGL(k_plduq_pack, dim3(nblk(std::max<int64_t>(n, 1)), (unsigned)std::max<int64_t>(m, 1)), dim3(256), 0, st, Y, ldy, m, n, ws.W, N);
+        LAUNCH(PLDL_CLASS_OTHER, k_plduq_pack, dim3(nblk(std::max<int64_t>(n, 1)), (unsigned)std::max<int64_t>(m, 1)), dim3(256), 0, st, Y, ldy, m, n, ws.W, N);
         int64_t r = E.plduq(0, m, m, N);
-        hipLaunchKernelGGL(k_plduq_unpack, dim3(nblk(std::max<int64_t>(n, 1)), (unsigned)std::max<int64_t>(m, 1)), dim3(256), 0, st, ws.W, N, m, n, Y, ldy,
+        LAUNCH(PLDL_CLASS_OTHER, k_plduq_unpack, dim3(nblk(std::max<int64_t>(n, 1)), (unsigned)std::max<int64_t>(m, 1)), dim3(256), 0, st, ws.W, N, m, n, Y, ldy,
                            ws.orig, rows, cols);
-        if (n > 0 && m == 0) hipLaunchKernelGGL(k_iota, dim3(nblk(n)), dim3(256), 0, st, cols, n);
+        if (n > 0 && m == 0) LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(n)), dim3(256), 0, st, cols, n);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
         *rank = r;
+    });
+}
+
+int pldl_profile(pldl_ctx* ctx, int32_t mode, pldl_stats* out) {
+    if (!ctx) return -1;
+    if (mode < 0 || mode > 2) return fail(ctx, -2, "mode must be 0, 1 or 2");
+    return guarded(ctx, [&]() {
+        ctx->prof.harvest();
+        if (mode == 1) { ctx->prof.tot = pldl_stats{}; ctx->prof.on = true; }
+        if (mode == 0) ctx->prof.on = false;
+        if (out) *out = ctx->prof.tot;
     });
 }
 

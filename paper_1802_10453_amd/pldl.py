@@ -27,6 +27,18 @@ PLDL_PATH_AUTO, PLDL_PATH_F64 = 0, 1
 ERRORS = {1: "PLDL_ERANGE", 2: "PLDL_EUNSUPPORTED_P", 3: "PLDL_EHIP", 4: "PLDL_ENOMEM", 5: "PLDL_EINTERNAL"}
 
 
+CLASS_NAMES = ("gemm", "trsm_leaf", "base_case", "plduq_leaf", "trss_leaf", "perm", "other", "host_sync")
+
+
+class pldl_kstat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("ms", ctypes.c_double)]
+
+
+class pldl_stats(ctypes.Structure):
+    _fields_ = [("cls", pldl_kstat * 8)]
+
+
 class pldl_opts(ctypes.Structure):
     _fields_ = [("path", _i32), ("threshold", _i32), ("standard_form", _i32), ("check_range", _i32)]
 
@@ -42,12 +54,13 @@ _lib.pldl_trsm.argtypes = [_vp, _u32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _v
 _lib.pldl_syrdk.argtypes = [_vp, _u32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _i64, _vp]
 _lib.pldl_trss.argtypes = [_vp, _u32, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]
 _lib.pldl_plduq.argtypes = [_vp, _u32, _i64, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(_i64), _vp]
+_lib.pldl_profile.argtypes = [_vp, _i32, ctypes.POINTER(pldl_stats)]
 for _f in ("pldl_create", "pldl_destroy", "pldl_factor", "pldl_gemm", "pldl_trsm", "pldl_syrdk", "pldl_trss",
-           "pldl_plduq"):
+           "pldl_plduq", "pldl_profile"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("pldl_create", "pldl_destroy", "pldl_last_error", "pldl_factor", "pldl_gemm", "pldl_trsm",
-            "pldl_syrdk", "pldl_trss", "pldl_plduq")
+            "pldl_syrdk", "pldl_trss", "pldl_plduq", "pldl_profile")
 
 
 class PldlError(RuntimeError):
@@ -127,6 +140,13 @@ class Context:
         rc = _lib.pldl_factor(self._h, p, n, A_ptr, lda, dtype, e_ptr, perm_ptr, rpm_ptr, ctypes.byref(rank),
                               ctypes.byref(opts) if opts is not None else None, _stream())
         return rc, int(rank.value)
+
+    def profile(self, mode: int) -> dict:
+        """pldl_profile: 1 = reset and start, 0 = stop, 2 = read.  Returns per-class totals."""
+        st = pldl_stats()
+        self._check(_lib.pldl_profile(self._h, int(mode), ctypes.byref(st)))
+        return {name: dict(launches=st.cls[i].launches, flops=st.cls[i].flops, bytes=st.cls[i].bytes,
+                           ms=st.cls[i].ms) for i, name in enumerate(CLASS_NAMES)}
 
     # ------------------------------------------------------------------ building blocks
     def gemm(self, p, C, A, B, transA=False, transB=False, lower_only=False):
