@@ -32,6 +32,13 @@ __device__ __forceinline__ double fred(double v, const Field& F) {
     r = (r >= F.p) ? r - F.p : r;
     return r;
 }
+// Centered reduction in three dependent operations: q = rint(v/p) is the
+// nearest integer quotient up to one unit when v/p lies within rounding error
+// of a half-integer, where both choices leave |r| ~ p/2; hence |r| <= p/2 + 2
+// for every integer-valued |v| < 2^53.  Used on the latency-bound paths.
+__device__ __forceinline__ double fredc(double v, const Field& F) {
+    return fma(-rint(v * F.pinv), F.p, v);
+}
 // centered representative of a canonical residue: (-p/2, p/2]
 __device__ __forceinline__ double fcen(double v, const Field& F) { return v > F.half ? v - F.p : v; }
 // canonical representative of a residue in (-p, p)
@@ -66,7 +73,9 @@ struct GemmSeg {
 };
 // C (row-major, ldc) <- C - sum_seg A_seg B_seg   (mod p)
 //   lower_c: only entries j <= i of C (m == n);  b_upper: B[t][j] taken as 0 for t > j (segment 0)
+//   nzrow (optional): atomicMin(nzrow, nzoff + index of the first row of C holding a nonzero result)
 void launch_gemm(hipStream_t s, const Field& F, int64_t m, int64_t n, double* C, int64_t ldc,
-                 const GemmSeg* segs, int nseg, bool lower_c, bool b_upper);
+                 const GemmSeg* segs, int nseg, bool lower_c, bool b_upper, int32_t* nzrow = nullptr,
+                 int32_t nzoff = 0);
 
 }  // namespace pldl

@@ -129,13 +129,13 @@ struct Workspace {
     double *W = nullptr, *tmp1 = nullptr, *tmp2 = nullptr, *dd = nullptr, *de = nullptr;
     double *xinv = nullptr, *yy = nullptr, *dvec = nullptr;
     int8_t* kind = nullptr;
-    int32_t *orig = nullptr, *sig = nullptr, *tmpo = nullptr, *info = nullptr;
+    int32_t *orig = nullptr, *sig = nullptr, *tmpo = nullptr, *info = nullptr, *pidx = nullptr;
     int32_t* hinfo = nullptr;  // pinned host mirror of info (rank, error flag, sigma)
     void release() {
         double* ds[] = {W, tmp1, tmp2, dd, de, xinv, yy, dvec};
         for (double* p : ds) if (p) (void)hipFree(p);
         if (kind) (void)hipFree(kind);
-        int32_t* is[] = {orig, sig, tmpo, info};
+        int32_t* is[] = {orig, sig, tmpo, info, pidx};
         for (int32_t* p : is) if (p) (void)hipFree(p);
         if (hinfo) (void)hipHostFree(hinfo);
         *this = Workspace();
@@ -161,9 +161,9 @@ struct Workspace {
         dalloc(&yy, m + 1);
         dalloc(&dvec, 2 * m + 2);
         if (hipMalloc((void**)&kind, m + 1) != hipSuccess) { release(); throw Err(PLDL_ENOMEM, "alloc"); }
-        int32_t** ips[] = {&orig, &sig, &tmpo};
+        int32_t** ips[] = {&orig, &sig, &tmpo, &pidx};
         for (int32_t** p : ips)
-            if (hipMalloc((void**)p, std::max<int64_t>(2 * m + 2, 512) * sizeof(int32_t)) != hipSuccess) {
+            if (hipMalloc((void**)p, (2 * m + 1024) * sizeof(int32_t)) != hipSuccess) {
                 release();
                 throw Err(PLDL_ENOMEM, "alloc");
             }
@@ -185,6 +185,7 @@ struct Engine {
     Workspace& ws;
     double* W;
     Prof* prof;
+    const uint32_t* itab = nullptr;  // x -> x^{-1} mod p table (device), or NULL
     Engine(Workspace& w, hipStream_t s, uint32_t p, int64_t n_, int t, Prof* pr)
         : st(s), F(make_field(p)), n(n_), ld(std::max<int64_t>(n_, 1)), t_leaf(t), ws(w), W(w.W), prof(pr) {}
 
@@ -218,27 +219,33 @@ struct Engine {
         prof->end(st);
     }
 
-    // Symmetric permutation of [lo, hi): new lo+q <- old lo+sig[q].
+    // Symmetric permutation of [lo, hi): new lo+q <- old lo+sig[q] (sig NULL: the
+    // rotation moving the first rot1 positions after the others).
     // parts: 1 = rows x [0,lo), 2 = block, 4 = rows below x range, 8 = orig.
-    void perm_sym(int64_t lo, int64_t hi, const int32_t* sig, int parts) {
-        int64_t s = hi - lo;
+    void perm_sym(int64_t lo, int64_t hi, const int32_t* sig, int parts, int64_t rot1 = -1) {
+        const int64_t s = hi - lo;
         if (s <= 1) return;
-        REQUIRE(lo >= 0 && hi <= n);
-        int64_t rows = std::max(s, n - hi), cols = std::max(lo, s);
-        if (rows <= 0 || cols <= 0) return;
-        REQUIRE(rows <= 65535);
-        dim3 g(nblk(cols), (unsigned)rows, 4);
-        double elems = ((parts & 1) ? (double)s * lo : 0.0) + ((parts & 2) ? (double)s * (s + 1) / 2.0 : 0.0) +
-                       ((parts & 4) ? (double)s * (n - hi) : 0.0);
+        REQUIRE(lo >= 0 && hi <= n && (sig || (rot1 > 0 && rot1 < s)));
+        PermGeom g{};
+        g.n = n; g.lo = lo; g.hi = hi; g.s = s; g.parts = parts;
+        g.nb0 = nblk(std::max<int64_t>(lo, 1));
+        g.nb1 = nblk(s);
+        g.B0 = ((parts & 1) && lo > 0) ? s * g.nb0 : 0;
+        g.B1 = (parts & 2) ? s * g.nb1 : 0;
+        g.B2 = ((parts & 4) && n > hi) ? (n - hi) * g.nb1 : 0;
+        g.B3 = (parts & 8) ? g.nb1 : 0;
+        const int64_t blocks = g.B0 + g.B1 + g.B2 + g.B3;
+        if (blocks == 0) return;
+        REQUIRE(blocks < ((int64_t)1 << 31));
+        double elems = (double)(g.B0 ? s * lo : 0) + (double)(g.B1 ? s * (s + 1) / 2 : 0) + (double)(g.B2 ? s * (n - hi) : 0);
         prof->begin(st, PLDL_CLASS_PERM, 0.0, 16.0 * elems);
-        hipLaunchKernelGGL(k_perm_gather, g, dim3(256), 0, st, W, ld, n, lo, hi, sig, ws.tmp1, ws.orig, ws.tmpo, parts);
-        hipLaunchKernelGGL(k_perm_scatter, g, dim3(256), 0, st, W, ld, n, lo, hi, ws.tmp1, ws.orig, ws.tmpo, parts);
+        hipLaunchKernelGGL(k_perm_sym, dim3((unsigned)blocks), dim3(256), 0, st, W, ld, g, sig, rot1, ws.tmp1, ws.orig, ws.tmpo, 0);
+        hipLaunchKernelGGL(k_perm_sym, dim3((unsigned)blocks), dim3(256), 0, st, W, ld, g, sig, rot1, ws.tmp1, ws.orig, ws.tmpo, 1);
         prof->end(st);
     }
     void rotate(int64_t a, int64_t b, int64_t c) {
         if (a == b || b == c) return;
-        LAUNCH(PLDL_CLASS_OTHER, k_sigma_rotate, dim3(nblk(c - a)), dim3(256), 0, st, ws.sig, b - a, c - b);
-        perm_sym(a, c, ws.sig, 15);
+        perm_sym(a, c, nullptr, 15, b - a);
     }
 
     // ---- TRSM (Section 3) ---------------------------------------------------
@@ -246,7 +253,7 @@ struct Engine {
     void trsm_ru(MatV B, int64_t m, int64_t r, MatV T) {
         if (m <= 0 || r <= 0) return;
         if (r <= 64) {
-            LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trsm_ru_leaf, dim3(nblk(m, 64)), dim3(256), 0, st, B.p, B.rs, m, (int)r, T, F);
+            LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trsm_ru_leaf, dim3(nblk(m, 64)), dim3(64), 0, st, B.p, B.rs, m, (int)r, T, F);
             return;
         }
         int64_t r1 = std::max<int64_t>(64, (r / 2) / 64 * 64);
@@ -258,7 +265,7 @@ struct Engine {
     void trsm_ll(MatV B, int64_t r, int64_t ncols, MatV T) {
         if (r <= 0 || ncols <= 0) return;
         if (r <= 64) {
-            LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trsm_ll_leaf, dim3(nblk(ncols, 64)), dim3(256), 0, st, B.p, B.rs, ncols, (int)r, T, F);
+            LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trsm_ll_leaf, dim3(nblk(ncols, 64)), dim3(64), 0, st, B.p, B.rs, ncols, (int)r, T, F);
             return;
         }
         int64_t r1 = std::max<int64_t>(64, (r / 2) / 64 * 64);
@@ -266,10 +273,10 @@ struct Engine {
         gemm_ld(B.p + r1 * B.rs, B.rs, r - r1, ncols, GemmSeg{MatV{T.p + r1 * T.rs, T.rs, T.cs}, MatV{B.p, B.rs, 1}, r1});
         trsm_ll(MatV{B.p + r1 * B.rs, B.rs, 1}, r - r1, ncols, MatV{T.p + r1 * (T.rs + T.cs), T.rs, T.cs});
     }
-    void gemm_ld(double* C, int64_t ldc, int64_t m, int64_t nn, GemmSeg s0) {
+    void gemm_ld(double* C, int64_t ldc, int64_t m, int64_t nn, GemmSeg s0, int32_t* nzrow = nullptr, int32_t nzoff = 0) {
         if (m <= 0 || nn <= 0 || s0.k <= 0) return;
         prof->begin(st, PLDL_CLASS_GEMM, 2.0 * (double)m * (double)nn * (double)s0.k);
-        launch_gemm(st, F, m, nn, C, ldc, &s0, 1, false, false);
+        launch_gemm(st, F, m, nn, C, ldc, &s0, 1, false, false, nzrow, nzoff);
         prof->end(st);
     }
 
@@ -277,7 +284,7 @@ struct Engine {
     int64_t bc(int64_t lo, int64_t hi) {
         int s = (int)(hi - lo);
         REQUIRE(s >= 1 && s <= 128);
-        LAUNCH(PLDL_CLASS_BASE_CASE, k_bc_leaf, dim3(1), dim3(1024), 0, st, W, ld, lo, s, F, ws.dd, ws.de, ws.info + 1, ws.info);
+        LAUNCH(PLDL_CLASS_BASE_CASE, k_bc_leaf, dim3(1), dim3(1024), 0, st, W, ld, lo, s, F, itab, ws.dd, ws.de, ws.info + 1, ws.info);
         int32_t* h = read_info(1 + s);
         int64_t r = h[0];
         bool ident = true;
@@ -319,7 +326,17 @@ struct Engine {
         int64_t s0 = lo + mz, nc = hi - s0;
         if (mz == 0) return recall(lo, hi);
         if (nc == 0) return 0;
-        int64_t rY = plduq(lo, lo + mz, s0, hi);
+        // PLDUQ of Y on a compact copy of Y^T; then C' = Q C Q^T and the pack back into W
+        REQUIRE(nc <= 65535 && mz <= 65535);
+        T = ws.tmp2; ldT = mz; TR = nc; TC = mz; pR = ws.pidx; pC = ws.pidx + mz;
+        LAUNCH(PLDL_CLASS_OTHER, k_copy2d, dim3(nblk(mz), (unsigned)nc), dim3(256), 0, st, T, mz, W + s0 * ld + lo, ld, nc, mz);
+        LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(mz)), dim3(256), 0, st, pR, mz);
+        LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(nc)), dim3(256), 0, st, pC, nc);
+        int64_t rY = plduq_t(0, mz, 0, nc);
+        if (rY > 0) {
+            perm_sym(s0, hi, pC, 2);
+            LAUNCH(PLDL_CLASS_OTHER, k_copy2d, dim3(nblk(mz), (unsigned)nc), dim3(256), 0, st, W + s0 * ld + lo, ld, T, mz, nc, mz);
+        }
         int64_t nz = nc - rY, nr = mz - rY, N = hi - lo;
         double* G1 = ws.tmp2;
         double* G2 = ws.tmp2 + rY * rY;
@@ -369,8 +386,11 @@ struct Engine {
         LAUNCH(PLDL_CLASS_PERM, k_zlp_assemble, dim3(nblk(N), (unsigned)N), dim3(256), 0, st, W, ld, lo, mz, hi, rY, G1,
                            std::max<int64_t>(rY, 1), G2, std::max<int64_t>(rY, 1), ws.tmp1);
         LAUNCH(PLDL_CLASS_PERM, k_copy2d, dim3(nblk(N), (unsigned)N), dim3(256), 0, st, W + lo * ld + lo, ld, ws.tmp1, N, N, N);
-        // sigma of the assembly for the L part, the rows below and orig
-        LAUNCH(PLDL_CLASS_OTHER, k_zlp_sigma, dim3(nblk(N)), dim3(256), 0, st, ws.sig, mz, nc, rY);
+        // the assembly order composed with PLDUQ's maps, for the L part, the rows below and orig
+        if (rY > 0)
+            LAUNCH(PLDL_CLASS_OTHER, k_zlp_sigma_total, dim3(nblk(N)), dim3(256), 0, st, ws.sig, mz, nc, rY, pR, pC);
+        else
+            LAUNCH(PLDL_CLASS_OTHER, k_zlp_sigma, dim3(nblk(N)), dim3(256), 0, st, ws.sig, mz, nc, rY);
         perm_sym(lo, hi, ws.sig, 1 | 4 | 8);
         if (rY > 0)
             LAUNCH(PLDL_CLASS_OTHER, k_zlp_orig_d, dim3(nblk(N)), dim3(256), 0, st, ws.orig, ws.tmpo, lo, mz, hi, rY, W, ld, delta, ws.dd, ws.de, 2);
@@ -384,51 +404,101 @@ struct Engine {
         return 2 * rY + rz;
     }
 
-    // ---- PLDUQ revealing the rank profile (2-D recursion, tile leaves) --------
-    // rows = positions [a0, a1), columns = positions [c0, c1), Y[i][j] = W[c0+j][a0+i]
-    int64_t plduq(int64_t a0, int64_t a1, int64_t c0, int64_t c1) {
-        int64_t m = a1 - a0, nc = c1 - c0;
-        if (m <= 0 || nc <= 0) return 0;
-        chk(c0, a0, nc, m);
-        if (m <= 32 && nc <= 256) {
-            LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_leaf, dim3(1), dim3(1024), 0, st, W, ld, a0, (int)m, c0, (int)nc, F, ws.sig,
-                               ws.sig + 32, ws.info);
-            int64_t r = read_info(1)[0];
-            perm_sym(a0, a1, ws.sig, 15);
-            perm_sym(c0, c1, ws.sig + 32, 15);
-            return r;
-        }
-        if (m > 32) {
-            int64_t am = a0 + std::max<int64_t>(32, (m / 2) / 32 * 32);
-            int64_t r1 = plduq(a0, am, c0, c1);
+    // ---- PLDUQ revealing the rank profile, on a compact transposed copy -------
+    // T (TR x TC, leading dimension ldT) holds Y^T: Y[i][j] = T[j][i].  Row and
+    // column permutations of Y move only T and are recorded in pR / pC (the
+    // caller applies their composition to W once).
+    double* T = nullptr;
+    int64_t ldT = 0, TR = 0, TC = 0;
+    int32_t *pR = nullptr, *pC = nullptr;
+
+    // Y columns [a, b) = rows of T;  Y rows [a, b) = columns of T
+    void t_perm(bool ycols, int64_t a, int64_t b, const int32_t* sg, int64_t rot1 = -1) {
+        const int64_t sz = b - a;
+        if (sz <= 1) return;
+        const int64_t rows = ycols ? sz : TR, cols = ycols ? TC : sz;
+        if (rows <= 0 || cols <= 0) return;
+        REQUIRE(rows + 1 <= 65535);
+        int32_t* idx = ycols ? pC : pR;
+        dim3 g(nblk(std::max(cols, sz)), (unsigned)(rows + 1));
+        prof->begin(st, PLDL_CLASS_PERM, 0.0, 16.0 * (double)rows * (double)cols);
+        hipLaunchKernelGGL(k_tperm, g, dim3(256), 0, st, T, ldT, TR, TC, ycols ? 1 : 0, a, sz, sg, rot1, ws.tmp1, idx, ws.tmpo, 0);
+        hipLaunchKernelGGL(k_tperm, g, dim3(256), 0, st, T, ldT, TR, TC, ycols ? 1 : 0, a, sz, sg, rot1, ws.tmp1, idx, ws.tmpo, 1);
+        prof->end(st);
+    }
+    void t_perm_ycols(int64_t a, int64_t b, const int32_t* sg) { t_perm(true, a, b, sg); }
+    void t_perm_yrows(int64_t a, int64_t b, const int32_t* sg) { t_perm(false, a, b, sg); }
+    void t_rot_ycols(int64_t a, int64_t b, int64_t c) {
+        if (a == b || b == c) return;
+        t_perm(true, a, c, nullptr, b - a);
+    }
+    void t_rot_yrows(int64_t a, int64_t b, int64_t c) {
+        if (a == b || b == c) return;
+        t_perm(false, a, c, nullptr, b - a);
+    }
+
+    // rows [a0, a1) and columns [c0, c1) of Y.  Row slabs of <= 64 rows; within a
+    // slab the leaf finds the pivots of the first column chunk that is not zero on
+    // the slab, the rest of the columns are updated (TRSM, GEMM) and searched again.
+    // hint (device int, may be NULL): a lower bound on the first column of the
+    // slab's rows holding a nonzero, left by the update that preceded the call.
+    int64_t plduq_t(int64_t a0, int64_t a1, int64_t c0, int64_t c1, const int32_t* hint = nullptr) {
+        const int64_t m = a1 - a0;
+        if (m <= 0 || c1 <= c0) return 0;
+        REQUIRE(a1 <= TC && c1 <= TR);
+        int32_t* nzh = ws.info + 8;
+        if (m > 64) {
+            const int64_t am = a0 + std::max<int64_t>(64, (m / 2) / 64 * 64);
+            const int64_t r1 = plduq_t(a0, am, c0, c1, hint);
+            const int32_t* bhint = nullptr;
             if (r1 > 0) {
-                int64_t mb = a1 - am;
-                // Wb^T = U_t^{-T} Y_b1^T : U_t^T unit lower at W[c0.., a0..]
-                trsm_ll(vrow(c0, am), r1, mb, vrow(c0, a0));
-                // Y_b2^T -= V_t^T Wb^T
-                if (nc > r1) gemm(W + (c0 + r1) * ld + am, nc - r1, mb, GemmSeg{vrow(c0 + r1, a0), vrow(c0, am), r1});
+                const int64_t mb = a1 - am, ncr = c1 - c0 - r1;
+                // Wb^T = U_t^{-T} Y_b1^T  (U_t^T unit lower at T[c0.., a0..])
+                trsm_ll(MatV{T + c0 * ldT + am, ldT, 1}, r1, mb, MatV{T + c0 * ldT + a0, ldT, 1});
+                // Y_b2^T -= V_t^T Wb^T, recording the first column left nonzero on the bottom rows
+                if (ncr > 0) {
+                    HIPCHK(hipMemsetAsync(nzh, 0x7F, sizeof(int32_t), st));
+                    gemm_ld(T + (c0 + r1) * ldT + am, ldT, ncr, mb,
+                            GemmSeg{MatV{T + (c0 + r1) * ldT + a0, ldT, 1}, MatV{T + c0 * ldT + am, ldT, 1}, r1}, nzh,
+                            (int32_t)(c0 + r1));
+                    bhint = nzh;
+                }
                 // L_b^T = D_t^{-1} Wb^T
-                LAUNCH(PLDL_CLASS_OTHER, k_pack_dinv, dim3(nblk(r1)), dim3(256), 0, st, W, ld, c0, a0, r1, F, ws.xinv);
-                LAUNCH(PLDL_CLASS_OTHER, k_scale_by, dim3(nblk(mb), (unsigned)r1), dim3(256), 0, st, W + c0 * ld + am, ld, r1, mb, ws.xinv, 1, F);
+                LAUNCH(PLDL_CLASS_OTHER, k_scale_pack, dim3(nblk(mb), (unsigned)r1), dim3(256), 0, st, T + c0 * ldT + am, ldT, r1, mb,
+                       T + c0 * ldT + a0, ldT, 1, itab, F);
             }
-            int64_t r2 = plduq(am, a1, c0 + r1, c1);
-            rotate(a0 + r1, am, am + r2);
+            const int64_t r2 = plduq_t(am, a1, c0 + r1, c1, bhint);
+            t_rot_yrows(a0 + r1, am, am + r2);
             return r1 + r2;
         }
-        int64_t cm = c0 + 256;
-        int64_t r1 = plduq(a0, a1, c0, cm);
-        if (r1 > 0) {
-            int64_t nr_ = c1 - cm;
-            // (D U_R)^T = Y_R[piv]^T L_t^{-T},  L_t^T[a][b] = W[c0+a][a0+b] (a < b)
-            trsm_ru(vrow(cm, a0), nr_, r1, vrow(c0, a0));
-            // Y_R[np]^T -= (D U_R)^T M_t^T
-            if (m > r1) gemm(W + cm * ld + a0 + r1, nr_, m - r1, GemmSeg{vrow(cm, a0), vrow(c0, a0 + r1), r1});
-            LAUNCH(PLDL_CLASS_OTHER, k_pack_dinv, dim3(nblk(r1)), dim3(256), 0, st, W, ld, c0, a0, r1, F, ws.xinv);
-            LAUNCH(PLDL_CLASS_OTHER, k_scale_by, dim3(nblk(r1), (unsigned)nr_), dim3(256), 0, st, W + cm * ld + a0, ld, nr_, r1, ws.xinv, 0, F);
+        LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_leaf, dim3(1), dim3(1024), 0, st, T, ldT, a0, (int)m, c0, c1, F, itab, hint,
+               ws.sig, ws.sig + 64, ws.info);
+        const int32_t* h = read_info(3);
+        const int64_t r = h[0], cs = h[1], w = h[2];
+        if (r == 0) return 0;  // the slab is zero on [c0, c1)
+        t_perm_yrows(a0, a1, ws.sig);
+        t_perm_ycols(cs, cs + w, ws.sig + 64);
+        if (cs > c0) t_rot_ycols(c0, cs, cs + r);
+        const int64_t ce = cs + w;
+        int64_t r2 = 0;
+        if (ce < c1) {
+            const int64_t nr = c1 - ce;
+            // (D U_R)^T = Y_R[piv]^T L_t^{-T},  L_t^T[a][b] = T[c0+a][a0+b] (a < b)
+            trsm_ru(MatV{T + ce * ldT + a0, ldT, 1}, nr, r, MatV{T + c0 * ldT + a0, ldT, 1});
+            // Y_R[np]^T -= (D U_R)^T M_t^T, recording the first column left nonzero on those rows
+            const int32_t* rhint = nullptr;
+            if (m > r) {
+                HIPCHK(hipMemsetAsync(nzh, 0x7F, sizeof(int32_t), st));
+                gemm_ld(T + ce * ldT + a0 + r, ldT, nr, m - r,
+                        GemmSeg{MatV{T + ce * ldT + a0, ldT, 1}, MatV{T + c0 * ldT + a0 + r, ldT, 1}, r}, nzh, (int32_t)ce);
+                rhint = nzh;
+            }
+            LAUNCH(PLDL_CLASS_OTHER, k_scale_pack, dim3(nblk(r), (unsigned)nr), dim3(256), 0, st, T + ce * ldT + a0, ldT, nr, r,
+                   T + c0 * ldT + a0, ldT, 0, itab, F);
+            r2 = plduq_t(a0 + r, a1, ce, c1, rhint);
+            t_rot_ycols(c0 + r, ce, ce + r2);
         }
-        int64_t r2 = plduq(a0 + r1, a1, cm, c1);
-        rotate(c0 + r1, cm, cm + r2);
-        return r1 + r2;
+        return r + r2;
     }
 
     // ---- Algorithm 1 (TRSS): C at W[s0..s0+r)^2, U[a][b] = W[s0+b][u0+a] -----
@@ -464,6 +534,23 @@ struct pldl_ctx {
     Workspace ws;
     Prof prof;
     std::string err;
+    uint32_t* itab = nullptr;  // inverse table of modulus itab_p
+    uint32_t itab_p = 0;
+    // table x -> x^{-1} mod p, built on the device the first time p is used
+    const uint32_t* inv_table(uint32_t p, hipStream_t st) {
+        if (itab_p == p && itab) return itab;
+        if (itab) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(itab)); itab = nullptr; itab_p = 0; }
+        if (hipMalloc((void**)&itab, (size_t)p * sizeof(uint32_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            itab = nullptr;
+            throw Err(PLDL_ENOMEM, "inverse table allocation failed");
+        }
+        Field F = make_field(p);
+        hipLaunchKernelGGL(k_inv_table, dim3(nblk(p)), dim3(256), 0, st, itab, F);
+        HIPCHK(hipGetLastError());
+        itab_p = p;
+        return itab;
+    }
 };
 
 namespace {
@@ -510,6 +597,7 @@ int pldl_destroy(pldl_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     ctx->ws.release();
+    if (ctx->itab) (void)hipFree(ctx->itab);
     delete ctx;
     return PLDL_OK;
 }
@@ -538,6 +626,7 @@ int pldl_factor(pldl_ctx* ctx, uint32_t p, int64_t n, void* A, int64_t lda, int3
     return guarded(ctx, [&]() {
         ctx->ws.ensure(n);
         Engine E(ctx->ws, st, p, n, t, &ctx->prof);
+        E.itab = ctx->inv_table(p, st);
         Prof* prof = &ctx->prof;
         Workspace& ws = ctx->ws;
         HIPCHK(hipMemsetAsync(ws.info, 0, sizeof(int32_t) * 4, st));
@@ -697,8 +786,8 @@ int pldl_plduq(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, double* Y, int64
                int64_t* rank, void* stream) {
     if (!ctx) return -1;
     if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
-    if (m < 0 || m + n > 65535) return fail(ctx, -3, "m out of range");
-    if (n < 0) return fail(ctx, -4, "n < 0");
+    if (m < 0 || m > 65535) return fail(ctx, -3, "m out of range");
+    if (n < 0 || n > 65535) return fail(ctx, -4, "n out of range");
     if (m > 0 && n > 0 && !Y) return fail(ctx, -5, "Y is NULL");
     if (ldy < std::max<int64_t>(1, n)) return fail(ctx, -6, "ldy too small");
     if (m > 0 && !rows) return fail(ctx, -7, "rows is NULL");
@@ -706,19 +795,27 @@ int pldl_plduq(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, double* Y, int64
     if (!rank) return fail(ctx, -9, "rank is NULL");
     hipStream_t st = as_stream(stream);
     return guarded(ctx, [&]() {
-        int64_t N = m + n;
-        if (N == 0) { *rank = 0; return; }
-        ctx->ws.ensure(N);
-        Engine E(ctx->ws, st, p, N, 128, &ctx->prof);
+        if (m == 0 || n == 0) {
+            Prof* prof = &ctx->prof;
+            if (m > 0) LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(m)), dim3(256), 0, st, rows, m);
+            if (n > 0) LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(n)), dim3(256), 0, st, cols, n);
+            HIPCHK(hipStreamSynchronize(st));
+            *rank = 0;
+            return;
+        }
+        ctx->ws.ensure(std::max(m, n));
+        Engine E(ctx->ws, st, p, std::max(m, n), 128, &ctx->prof);
+        E.itab = ctx->inv_table(p, st);
         Prof* prof = &ctx->prof;
         Workspace& ws = ctx->ws;
-        LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(N)), dim3(256), 0, st, ws.orig, N);
-        HIPCHK(hipMemsetAsync(ws.W, 0, sizeof(double) * N * N, st));
-        LAUNCH(PLDL_CLASS_OTHER, k_plduq_pack, dim3(nblk(std::max<int64_t>(n, 1)), (unsigned)std::max<int64_t>(m, 1)), dim3(256), 0, st, Y, ldy, m, n, ws.W, N);
-        int64_t r = E.plduq(0, m, m, N);
-        LAUNCH(PLDL_CLASS_OTHER, k_plduq_unpack, dim3(nblk(std::max<int64_t>(n, 1)), (unsigned)std::max<int64_t>(m, 1)), dim3(256), 0, st, ws.W, N, m, n, Y, ldy,
-                           ws.orig, rows, cols);
-        if (n > 0 && m == 0) LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(n)), dim3(256), 0, st, cols, n);
+        E.T = ws.tmp2; E.ldT = m; E.TR = n; E.TC = m; E.pR = ws.pidx; E.pC = ws.pidx + m;
+        LAUNCH(PLDL_CLASS_OTHER, k_transpose, dim3(nblk(n), (unsigned)m), dim3(256), 0, st, E.T, m, Y, ldy, m, n);
+        LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(m)), dim3(256), 0, st, E.pR, m);
+        LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(n)), dim3(256), 0, st, E.pC, n);
+        int64_t r = E.plduq_t(0, m, 0, n);
+        LAUNCH(PLDL_CLASS_OTHER, k_transpose, dim3(nblk(m), (unsigned)n), dim3(256), 0, st, Y, ldy, E.T, m, n, m);
+        HIPCHK(hipMemcpyAsync(rows, E.pR, m * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(cols, E.pC, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
         *rank = r;

@@ -25,6 +25,8 @@ struct GemmKArgs {
     int64_t K[2];
     Field F;
     int tiles_n;
+    int32_t* nzrow;   // optional: atomicMin(nzrow, nzoff + first row of C with a nonzero result)
+    int32_t nzoff;
 };
 
 template <bool A_ROW, bool B_ROW, bool LOWER_C, bool B_UPPER>
@@ -131,6 +133,7 @@ __global__ __launch_bounds__(NT) void k_gemm(GemmKArgs g) {
         }
     }
     // epilogue: output element (row, col) of MFMA block (x, y), register r
+    int first_nz = 1 << 30;
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
@@ -142,9 +145,23 @@ __global__ __launch_bounds__(NT) void k_gemm(GemmKArgs g) {
                 int64_t col = j0 + wn * 64 + y * 16 + lr;
                 if (row < g.m && col < g.n && (!LOWER_C || col <= row)) {
                     double* c = g.C + row * g.ldc + col;
-                    *c = fred(*c - fred(acc[x][y][r], F), F);
+                    double v = fred(*c - fred(acc[x][y][r], F), F);
+                    *c = v;
+                    if (v != 0.0 && row < first_nz) first_nz = (int)row;
                 }
             }
+    if (g.nzrow) {
+        // block minimum, then one atomic per block
+        for (int off = 32; off > 0; off >>= 1) first_nz = min(first_nz, __shfl_xor(first_nz, off));
+        __syncthreads();
+        int* red = (int*)&As[0][0];
+        if (lane == 0) red[wave] = first_nz;
+        __syncthreads();
+        if (tid == 0) {
+            int v = min(min(red[0], red[1]), min(red[2], red[3]));
+            if (v < (1 << 30)) atomicMin(g.nzrow, g.nzoff + v);
+        }
+    }
 }
 
 template <bool AR, bool BR>
@@ -160,10 +177,11 @@ void dispatch(hipStream_t s, const GemmKArgs& g, int blocks, bool lower_c, bool 
 }  // namespace
 
 void launch_gemm(hipStream_t s, const Field& F, int64_t m, int64_t n, double* C, int64_t ldc,
-                 const GemmSeg* segs, int nseg, bool lower_c, bool b_upper) {
+                 const GemmSeg* segs, int nseg, bool lower_c, bool b_upper, int32_t* nzrow, int32_t nzoff) {
     if (m <= 0 || n <= 0) return;
     GemmKArgs g{};
     g.m = m; g.n = n; g.C = C; g.ldc = ldc; g.F = F;
+    g.nzrow = nzrow; g.nzoff = nzoff;
     bool any = false;
     for (int i = 0; i < 2; ++i) {
         if (i < nseg && segs[i].k > 0) {

@@ -4,17 +4,28 @@
 
 namespace pldl {
 
-__global__ void k_bc_leaf(double* W, int64_t ld, int64_t lo, int s, Field F, double* dd, double* de,
-                          int32_t* sig_out, int32_t* rank_out);
-__global__ void k_plduq_leaf(double* W, int64_t ld, int64_t a0, int m, int64_t c0, int nc, Field F,
-                             int32_t* rsig, int32_t* csig, int32_t* rank_out);
+__global__ void k_bc_leaf(double* W, int64_t ld, int64_t lo, int s, Field F, const uint32_t* itab, double* dd,
+                          double* de, int32_t* sig_out, int32_t* rank_out);
+__global__ void k_plduq_leaf(double* T, int64_t ld, int64_t a0, int m, int64_t c0, int64_t c1, Field F,
+                             const uint32_t* itab, const int32_t* hint, int32_t* rsig, int32_t* csig, int32_t* info);
+__global__ void k_inv_table(uint32_t* tab, Field F);
+__global__ void k_mat_gather(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t rows, int64_t cols,
+                             const int32_t* rsig, int64_t roff, const int32_t* csig, int64_t coff);
+__global__ void k_transpose(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t rows, int64_t cols);
+__global__ void k_idx_gather(const int32_t* idx, int64_t a, int64_t len, const int32_t* sig, int32_t* tmp);
+__global__ void k_idx_copy(int32_t* idx, int64_t a, int64_t len, const int32_t* tmp);
+__global__ void k_zlp_sigma_total(int32_t* sig, int64_t mz, int64_t nc, int64_t rY, const int32_t* pR,
+                                  const int32_t* pC);
 __global__ void k_trss_leaf(double* W, int64_t ld, int64_t s0, int64_t u0, int r, Field F);
 __global__ void k_trsm_ru_leaf(double* B, int64_t ld, int64_t m, int r, MatV T, Field F);
 __global__ void k_trsm_ll_leaf(double* B, int64_t ld, int64_t ncols, int r, MatV T, Field F);
-__global__ void k_perm_gather(const double* W, int64_t ld, int64_t n, int64_t lo, int64_t hi, const int32_t* sig,
-                              double* tmp, const int32_t* orig, int32_t* tmpo, int parts);
-__global__ void k_perm_scatter(double* W, int64_t ld, int64_t n, int64_t lo, int64_t hi, const double* tmp,
-                               int32_t* orig, const int32_t* tmpo, int parts);
+struct PermGeom { int64_t n, lo, hi, s, nb0, nb1, B0, B1, B2, B3; int parts; };
+__global__ void k_perm_sym(double* W, int64_t ld, PermGeom g, const int32_t* sig, int64_t rot1, double* tmp,
+                           int32_t* orig, int32_t* tmpo, int dir);
+__global__ void k_tperm(double* T, int64_t ldT, int64_t R, int64_t C, int by_rows, int64_t a, int64_t sz,
+                        const int32_t* sig, int64_t rot1, double* tmp, int32_t* idx, int32_t* tmpi, int dir);
+__global__ void k_scale_pack(double* X, int64_t ld, int64_t rows, int64_t cols, const double* P, int64_t ldp,
+                             int by_row, const uint32_t* itab, Field F);
 __global__ void k_sigma_rotate(int32_t* sig, int64_t len1, int64_t len2);
 __global__ void k_sigma_merge(const int32_t* orig, int64_t a, int64_t n1, int64_t n2, int32_t* sig);
 __global__ void k_block_dinv(const double* dd, const double* de, int64_t lo, int64_t r, Field F, double* xinv,
@@ -53,8 +64,6 @@ __global__ void k_apply_d(const double* A, int64_t lda, int64_t n, int64_t k, co
 __global__ void k_trss_pack(const double* U, int64_t ldu, const double* C, int64_t ldc, double* W, int64_t ldw,
                             int64_t n, int32_t* info, int check_char2);
 __global__ void k_trss_unpack(const double* W, int64_t ldw, int64_t n, double* X, int64_t ldx);
-__global__ void k_plduq_pack(const double* Y, int64_t ldy, int64_t m, int64_t n, double* W, int64_t ldw);
-__global__ void k_plduq_unpack(const double* W, int64_t ldw, int64_t m, int64_t n, double* Y, int64_t ldy,
-                               const int32_t* orig, int32_t* rows, int32_t* cols);
+
 
 }  // namespace pldl

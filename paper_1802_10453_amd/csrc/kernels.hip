@@ -26,18 +26,15 @@ namespace pldl {
 // column), which computes the same unique (P, L, D).
 // ===========================================================================
 __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t lo, int s, Field F,
-                                                  double* dd, double* de, int32_t* sig_out,
-                                                  int32_t* rank_out) {
-    __shared__ double colI[128], colJ[128];
-    __shared__ double vb[128], vc[128], va[128], ve[128], vf[128];
-    __shared__ int alive[128], order[128], zeros[128], sig[128];
+                                                  const uint32_t* itab, double* dd, double* de,
+                                                  int32_t* sig_out, int32_t* rank_out) {
+    __shared__ double colI[2][128], colJ[2][128];  // centered reduced columns, 0 on eliminated rows
+    __shared__ int order[128], zeros[128], sig[128];
     __shared__ double bx[128], by[128];
     __shared__ int bt[128];
-    __shared__ int sh_j;
-    __shared__ double sh_xi, sh_w, sh_d22, sh_lji;
     __shared__ uint32_t Mo[128][129];
 
-    const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
+    const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31, lane = tid & 63;
     const int r0 = ty * 4, c0 = tx * 4;
     double m[4][4];
 #pragma unroll
@@ -49,68 +46,77 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
             if (i < s && j < s) v = (i >= j) ? W[(lo + i) * ld + lo + j] : W[(lo + j) * ld + lo + i];
             m[a][b] = v;
         }
-    if (tid < 128) { alive[tid] = tid < s ? 1 : 0; bt[tid] = 0; bx[tid] = 0.0; by[tid] = 0.0; }
-    __syncthreads();
+    // alive set, identical in every thread (all threads take the same decisions)
+    uint64_t al0 = (s >= 64) ? ~0ull : ((1ull << s) - 1ull);
+    uint64_t al1 = (s >= 128) ? ~0ull : (s > 64 ? ((1ull << (s - 64)) - 1ull) : 0ull);
+    auto alive = [&](int k) -> bool { return k < 64 ? ((al0 >> k) & 1ull) : ((al1 >> (k - 64)) & 1ull); };
+    auto kill = [&](int k) { if (k < 64) al0 &= ~(1ull << k); else al1 &= ~(1ull << (k - 64)); };
 
-    int r = 0, nz = 0;
+    int r = 0, nz = 0, step = 0;
     for (int i = 0; i < s; ++i) {
-        if (!alive[i]) continue;
-        // owners of column i publish the reduced column (0 on eliminated rows)
+        if (!alive(i)) continue;
+        const int bI = step & 1;
+        ++step;
+        // owners of column i publish the reduced column
         if (tx == (i >> 2)) {
+            double colv[4];
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
                 int k = r0 + a;
                 double v = 0.0;
 #pragma unroll
                 for (int b = 0; b < 4; ++b) v = (b == (i & 3)) ? m[a][b] : v;
-                colI[k] = (k < s && alive[k]) ? fred(v, F) : 0.0;
+                v = alive(k) ? fredc(v, F) : 0.0;
+                colv[a] = v;
             }
+#pragma unroll
+            for (int a = 0; a < 4; ++a) colI[bI][r0 + a] = colv[a];
         }
         __syncthreads();
-        if (tid < 64) {
-            int j = -1;
-            for (int base = i; base < s; base += 64) {
-                int c = base + tid;
-                bool pr = (c < s) && colI[c] != 0.0;
-                unsigned long long bal = __ballot(pr);
-                if (bal) { j = base + __ffsll((long long)bal) - 1; break; }
+        // every wave: first k >= i with a nonzero (row i of the Schur complement = column i)
+        int j = -1;
+        {
+            unsigned long long b0 = __ballot(lane >= i && colI[bI][lane] != 0.0);
+            if (b0) j = __ffsll((long long)b0) - 1;
+            else {
+                unsigned long long b1 = __ballot(64 + lane >= i && colI[bI][64 + lane] != 0.0);
+                if (b1) j = 64 + __ffsll((long long)b1) - 1;
             }
-            if (tid == 0) sh_j = j;
         }
-        __syncthreads();
-        const int j = sh_j;
-        if (j < 0) {  // zero row
-            if (tid == 0) { alive[i] = 0; zeros[nz] = i; }
+        if (j < 0) {  // zero row: set aside, precedence kept
+            if (tid == 0) zeros[nz] = i;
             ++nz;
-            __syncthreads();
+            kill(i);
             continue;
         }
-        if (j == i) {  // 1x1 pivot
-            if (tid == 0) {
-                double x = colI[i];
-                sh_xi = finv(x, F);
-                bx[r] = x; bt[r] = 1; order[r] = i; alive[i] = 0;
+        if (j == i) {  // 1x1 pivot x: S -= c c^T / x
+            const double x = fcan(colI[bI][i], F);
+            const double xi = itab ? (double)itab[(int)x] : finv(x, F);
+            if (tid == 0) { bx[r] = x; bt[r] = 1; order[r] = i; }
+            kill(i);
+            double vb[4], vc[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                int k = r0 + a;
+                vb[a] = alive(k) ? fredc(colI[bI][k] * xi, F) : 0.0;
             }
-            __syncthreads();
-            if (tid < 128) {
-                double c = (tid < s && alive[tid]) ? colI[tid] : 0.0;
-                vb[tid] = fcen(fmulm(c, sh_xi, F), F);
-                vc[tid] = fcen(c, F);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                int l = c0 + b;
+                vc[b] = alive(l) ? colI[bI][l] : 0.0;
             }
-            __syncthreads();
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) m[a][b] = fma(-vb[r0 + a], vc[c0 + b], m[a][b]);
+                for (int b = 0; b < 4; ++b) m[a][b] = fma(-vb[a], vc[b], m[a][b]);
             if (tx == (i >> 2)) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
-                        if (b == (i & 3)) m[a][b] = fcan(vb[r0 + a], F);
+                        if (b == (i & 3)) m[a][b] = fcan(vb[a], F);
             }
             r += 1;
-            __syncthreads();
         } else {  // 2x2 pivot on (i, j)
             if (tx == (j >> 2)) {
 #pragma unroll
@@ -118,41 +124,54 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
                     int k = r0 + a;
                     double v = 0.0;
 #pragma unroll
-                for (int b = 0; b < 4; ++b) v = (b == (j & 3)) ? m[a][b] : v;
-                colJ[k] = (k < s && alive[k]) ? fred(v, F) : 0.0;
+                    for (int b = 0; b < 4; ++b) v = (b == (j & 3)) ? m[a][b] : v;
+                    colJ[bI][k] = alive(k) ? fredc(v, F) : 0.0;
                 }
             }
             __syncthreads();
-            if (tid == 0) {
-                double x = colI[j], y = colJ[j];
-                double xi = finv(x, F);
-                double w, d22, lji;
-                if (F.ip == 2) { w = y; d22 = y; lji = 0.0; }
-                else { w = fmulm(y, F.inv2, F); d22 = 0.0; lji = fmulm(w, xi, F); }
-                sh_xi = xi; sh_w = w; sh_d22 = d22; sh_lji = lji;
-                bx[r] = x; by[r] = (F.ip == 2) ? y : 0.0; bt[r] = 2;
-                order[r] = i; order[r + 1] = j; alive[i] = 0; alive[j] = 0;
+            const double x = fcan(colI[bI][j], F), y = fcan(colJ[bI][j], F);
+            const double xi = itab ? (double)itab[(int)x] : finv(x, F);
+            double w, d22, lji;
+            if (F.ip == 2) { w = y; d22 = y; lji = 0.0; }
+            else { w = fmulm(y, F.inv2, F); d22 = 0.0; lji = fmulm(w, xi, F); }
+            if (tid == 0) { bx[r] = x; by[r] = (F.ip == 2) ? y : 0.0; bt[r] = 2; order[r] = i; order[r + 1] = j; }
+            kill(i);
+            kill(j);
+            // row coefficients e_k = x a_k, c_k = x b_k, f_k = d22 b_k; column coefficients b_l, a_l
+            double re[4], rc[4], rf[4], ra[4], cb[4], ca[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                int k = r0 + a;
+                bool al = alive(k);
+                double ci = al ? colI[bI][k] : 0.0, cj = al ? colJ[bI][k] : 0.0;
+                double bk = fredc(ci * xi, F);
+                double ek = fredc(cj - fredc(w * bk, F), F);
+                ra[a] = fredc(ek * xi, F);
+                re[a] = ek;
+                rc[a] = ci;
+                rf[a] = fredc(d22 * bk, F);
+                cb[a] = bk;  // reused below for this thread's rows when writing L
             }
-            __syncthreads();
-            if (tid < 128) {
-                bool al = tid < s && alive[tid];
-                double ci = al ? colI[tid] : 0.0, cj = al ? colJ[tid] : 0.0;
-                double b = fmulm(ci, sh_xi, F);                 // S[k][i] / x
-                double e = fcan(cj - fmulm(sh_w, b, F), F);      // x a_k = S[k][j] - w b_k
-                double av = fmulm(e, sh_xi, F);                  // a_k
-                vb[tid] = fcen(b, F); va[tid] = fcen(av, F); vc[tid] = fcen(ci, F);
-                ve[tid] = fcen(e, F); vf[tid] = fcen(fmulm(sh_d22, b, F), F);
+            double lb[4], la[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                int l = c0 + b;
+                bool al = alive(l);
+                double ci = al ? colI[bI][l] : 0.0, cj = al ? colJ[bI][l] : 0.0;
+                double bl = fredc(ci * xi, F);
+                double el = fredc(cj - fredc(w * bl, F), F);
+                lb[b] = bl;
+                la[b] = fredc(el * xi, F);
             }
-            __syncthreads();
             // S[k][l] -= x (a_k b_l + b_k a_l) + d22 b_k b_l = e_k b_l + c_k a_l + f_k b_l
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     double t = m[a][b];
-                    t = fma(-ve[r0 + a], vb[c0 + b], t);
-                    t = fma(-vc[r0 + a], va[c0 + b], t);
-                    t = fma(-vf[r0 + a], vb[c0 + b], t);
+                    t = fma(-re[a], lb[b], t);
+                    t = fma(-rc[a], la[b], t);
+                    t = fma(-rf[a], lb[b], t);
                     m[a][b] = t;
                 }
             if (tx == (i >> 2)) {
@@ -160,35 +179,32 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
-                        if (b == (i & 3)) m[a][b] = fcan(va[r0 + a], F);
+                        if (b == (i & 3)) m[a][b] = fcan(ra[a], F);
             }
             if (tx == (j >> 2)) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
-                        if (b == (j & 3)) m[a][b] = fcan(vb[r0 + a], F);
+                        if (b == (j & 3)) m[a][b] = fcan(cb[a], F);
             }
             if (tx == (i >> 2) && ty == (j >> 2)) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
-                        if (a == (j & 3) && b == (i & 3)) m[a][b] = sh_lji;
+                        if (a == (j & 3) && b == (i & 3)) m[a][b] = lji;
             }
             r += 2;
-            __syncthreads();
         }
     }
+    __syncthreads();
     // ---- write out: order = pivots then zero rows (their precedence kept)
     if (tid < s) sig[tid] = tid < r ? order[tid] : zeros[tid - r];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            int i = r0 + a, j = c0 + b;
-            if (i < 128 && j < 128) Mo[i][j] = (uint32_t)fred(m[a][b], F);
-        }
+        for (int b = 0; b < 4; ++b) Mo[r0 + a][c0 + b] = (uint32_t)fred(m[a][b], F);
     __syncthreads();
     for (int e = tid; e < s * s; e += 1024) {
         int q = e / s, c = e - q * s;
@@ -218,121 +234,189 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
 }
 
 // ===========================================================================
-// Rank-profile-revealing PLDUQ of one tile (Sections 4.2 and 5 pivoting):
-// rows = positions [a0, a0+m) (m <= 32), columns = positions [c0, c0+nc)
-// (nc <= 256), Y[i][j] = W[c0+j][a0+i] (Y is stored transposed below the
-// diagonal of W).  Rows are processed in order; a row's pivot is the first
-// nonzero of its reduced row among non-pivot columns; a zero row is skipped.
-// Right-looking over the tile's rows with delayed reduction (the tile sits in
-// registers: thread t owns column t%256 of rows 8*(t/256) .. +8).
-// The LU pack is written back in the ORIGINAL (unpermuted) coordinates; the
-// driver then applies the row permutation rsig and column permutation csig.
+// Rank-profile-revealing PLDUQ leaf (Sections 4.2 and 5 pivoting) on the
+// compact transposed copy T of Y (Y[i][j] = T[j][i], leading dimension ld):
+// rows [a0, a0+m) of Y (m <= 64), columns [c0, c1).  The kernel scans 256-wide
+// column chunks (from max(c0, *hint) when a hint is given: the first column a
+// preceding update found nonzero on these rows) until one holds a nonzero in
+// one of the rows, then eliminates that chunk row by row: a row's pivot is the
+// first nonzero of its reduced row among the chunk's non-pivot columns; an
+// all-zero row is skipped.  Right-looking with delayed reduction, the chunk in
+// registers: thread t owns row t%64 and columns t/64 + 16k (k < 16).  Every
+// wave runs the pivot search itself (no serial thread), the row and multiplier
+// vectors are double buffered: two barriers per row.
+// Output: the LU pack of the chunk in the ORIGINAL (unpermuted) coordinates,
+// rsig (m) / csig (chunk width) and info = {rank, chunk start, chunk width}.
 // ===========================================================================
-__global__ __launch_bounds__(1024) void k_plduq_leaf(double* W, int64_t ld, int64_t a0, int m, int64_t c0,
-                                                     int nc, Field F, int32_t* rsig, int32_t* csig,
-                                                     int32_t* rank_out) {
-    __shared__ double rowI[256];
-    __shared__ double fvec[32];
-    __shared__ int ispc[256];
-    __shared__ int prow[32], pcol[32];
-    __shared__ double pinvx[32];
-    __shared__ int wmin[4];
-    __shared__ int sh_c;
-    __shared__ double sh_xi;
-    const int tid = threadIdx.x, col = tid & 255, rg = tid >> 8;  // rows rg*8 .. rg*8+7
-    double y[8];
+__global__ __launch_bounds__(1024) void k_plduq_leaf(double* T, int64_t ld, int64_t a0, int m, int64_t c0,
+                                                     int64_t c1, Field F, const uint32_t* itab,
+                                                     const int32_t* hint, int32_t* rsig, int32_t* csig,
+                                                     int32_t* info) {
+    __shared__ double rowI[2][256];   // centered reduced row (0 on pivot columns)
+    __shared__ double fvec[2][64];    // centered multipliers of the rows below
+    __shared__ int ispc[256], cpiv[256];
+    __shared__ int rpiv[64];
+    __shared__ double pinvx[64];
+    __shared__ int wcnt[4];
+    __shared__ int rord[64], cord[256], rposs[64], cposs[256];
+    const int tid = threadIdx.x, row = tid & 63, cg = tid >> 6, lane = tid & 63;
+    double y[16];
+    int64_t cs = c0;
+    if (hint) cs = max(c0, (int64_t)*hint);
+    int w = 0;
+    // ---- scan for the first chunk with a nonzero on these rows
+    for (;;) {
+        w = (int)min((int64_t)256, c1 - cs);
+        if (w <= 0) break;
+        int nzf = 0;
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
-        int i = rg * 8 + a;
-        y[a] = (i < m && col < nc) ? W[(c0 + col) * ld + a0 + i] : 0.0;
+        for (int k = 0; k < 16; ++k) {
+            int col = cg + 16 * k;
+            double v = (row < m && col < w) ? T[(cs + col) * ld + a0 + row] : 0.0;
+            y[k] = v;
+            nzf |= (v != 0.0);
+        }
+        if (__syncthreads_or(nzf)) break;
+        cs += 256;
     }
-    if (tid < 256) ispc[tid] = 0;
+    if (w <= 0) {  // all rows are zero on [c0, c1)
+        if (tid == 0) { info[0] = 0; info[1] = (int32_t)c1; info[2] = 0; }
+        return;
+    }
+    if (tid < 256) { ispc[tid] = 0; cpiv[tid] = -1; }
+    if (tid < 64) rpiv[tid] = -1;
+    // live (not yet pivot) columns among this lane's 16, as a register bit mask
+    uint32_t live = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        if (cg + 16 * k < w) live |= 1u << k;
     __syncthreads();
     int r = 0;
     for (int i = 0; i < m; ++i) {
-        if (rg == (i >> 3)) rowI[col] = (col < nc && !ispc[col]) ? fred(y[i & 7], F) : 0.0;
-        __syncthreads();
-        if (tid < 256) {
-            bool pr = rowI[tid] != 0.0;
-            unsigned long long bal = __ballot(pr);
-            if ((tid & 63) == 0) wmin[tid >> 6] = bal ? (tid + __ffsll((long long)bal) - 1) : 1 << 30;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            int c = min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3]));
-            if (c >= (1 << 30)) c = -1;
-            sh_c = c;
-            if (c >= 0) {
-                double x = rowI[c];
-                double xi = finv(x, F);
-                sh_xi = xi;
-                prow[r] = i; pcol[r] = c; pinvx[r] = xi; ispc[c] = 1;
-            }
-        }
-        __syncthreads();
-        const int c = sh_c;
-        if (c < 0) continue;
-        // multipliers of the rows below for this pivot: f = Y[i'][c] / x
-        if (col == c) {
+        const int b = i & 1;
+        if (row == i) {
+            double rv[16];
 #pragma unroll
-            for (int a = 0; a < 8; ++a) {
-                int ii = rg * 8 + a;
-                if (ii < 32) fvec[ii] = (ii > i && ii < m) ? fcen(fmulm(fred(y[a], F), sh_xi, F), F) : 0.0;
-            }
+            for (int k = 0; k < 16; ++k) rv[k] = ((live >> k) & 1u) ? fredc(y[k], F) : 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) rowI[b][cg + 16 * k] = rv[k];
         }
         __syncthreads();
-        const double rv = fcen(rowI[col], F);
+        // every wave finds the first nonzero of the row (lowest column index)
+        int c = -1;
+        for (int q = 0; q < 4 && c < 0; ++q) {
+            unsigned long long bal = __ballot(rowI[b][q * 64 + lane] != 0.0);
+            if (bal) c = q * 64 + __ffsll((long long)bal) - 1;
+        }
+        if (c < 0) continue;  // zero row: nothing changes
+        const double x = fcan(rowI[b][c], F);
+        const double xi = itab ? (double)itab[(int)x] : finv(x, F);
+        // this lane's columns: the pivot column leaves the live set
 #pragma unroll
-        for (int a = 0; a < 8; ++a) y[a] = fma(-fvec[rg * 8 + a], rv, y[a]);
+        for (int k = 0; k < 16; ++k)
+            if (cg + 16 * k == c) live &= ~(1u << k);
+        if (tid == 0) { rpiv[i] = r; cpiv[c] = r; pinvx[r] = xi; ispc[c] = 1; }
+        // multipliers of the rows below: f = Y[i'][c] / x  (owners of column c)
+        if (cg == (c & 15)) {
+            double v = 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v = (k == (c >> 4)) ? y[k] : v;
+            fvec[b][row] = (row > i && row < m) ? fredc(fredc(v, F) * xi, F) : 0.0;
+        }
+        __syncthreads();
+        const double f = fvec[b][row];
+        double rw[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) rw[k] = rowI[b][cg + 16 * k];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) y[k] = fma(-f, rw[k], y[k]);
         // the pivot column now stores the multipliers (L) of the rows below
-        if (col == c) {
+        if (cg == (c & 15) && row > i && row < m) {
 #pragma unroll
-            for (int a = 0; a < 8; ++a) {
-                int ii = rg * 8 + a;
-                if (ii > i && ii < m) y[a] = fcan(fvec[ii], F);
-            }
+            for (int k = 0; k < 16; ++k)
+                if (k == (c >> 4)) y[k] = fcan(f, F);
         }
         ++r;
-        __syncthreads();
-    }
-    // ---- output orders
-    __shared__ int rord[32], cord[256], rpos[32], cpos[256];
-    if (tid == 0) {
-        int a = 0;
-        for (int t = 0; t < r; ++t) rord[a++] = prow[t];
-        for (int i = 0; i < m; ++i) {
-            bool piv = false;
-            for (int t = 0; t < r; ++t) piv |= (prow[t] == i);
-            if (!piv) rord[a++] = i;
-        }
-        int b = 0;
-        for (int t = 0; t < r; ++t) cord[b++] = pcol[t];
-        for (int j = 0; j < nc; ++j)
-            if (!ispc[j]) cord[b++] = j;
-        for (int t = 0; t < m; ++t) rpos[rord[t]] = t;
-        for (int t = 0; t < nc; ++t) cpos[cord[t]] = t;
-        *rank_out = r;
     }
     __syncthreads();
-    if (tid < m) rsig[tid] = rord[tid];
-    if (tid < nc) csig[tid] = cord[tid];
-    // pack entry LU[a][b] (a = rpos[i], b = cpos[j]) at W[c0 + j][a0 + i] (old coordinates)
-    if (col < nc) {
-        const int b = cpos[col];
-#pragma unroll
-        for (int aa = 0; aa < 8; ++aa) {
-            int i = rg * 8 + aa;
-            if (i >= m) continue;
-            int a = rpos[i];
-            double v = fred(y[aa], F);
-            double out;
-            if (a == b && a < r) out = v;                          // D
-            else if (b < a && b < r) out = v;                      // L / M (stored multipliers)
-            else if (a < b && a < r) out = fmulm(v, pinvx[a], F);  // U / V
-            else out = 0.0;
-            W[(c0 + col) * ld + a0 + i] = out;
+    // ---- orders: pivots first (pivot order), then the rest increasing (ballot prefix counts)
+    if (tid < 64) {
+        bool np = (tid < m) && rpiv[tid] < 0;
+        unsigned long long bal = __ballot(np);
+        int before = __popcll(bal & ((1ull << tid) - 1ull));
+        if (tid < m) {
+            int pos = np ? r + before : rpiv[tid];
+            rord[pos] = tid;
+            rposs[tid] = pos;
         }
     }
+    const bool npc = (tid < 256) && (tid < w) && cpiv[tid] < 0;
+    const unsigned long long balc = __ballot(npc);
+    if (tid < 256 && lane == 0) wcnt[tid >> 6] = __popcll(balc);
+    __syncthreads();
+    if (tid < w) {
+        int off = 0;
+        for (int q = 0; q < (tid >> 6); ++q) off += wcnt[q];
+        int pos = npc ? r + off + __popcll(balc & ((1ull << lane) - 1ull)) : cpiv[tid];
+        cord[pos] = tid;
+        cposs[tid] = pos;
+    }
+    __syncthreads();
+    if (tid == 0) { info[0] = r; info[1] = (int32_t)cs; info[2] = w; }
+    if (tid < m) rsig[tid] = rord[tid];
+    if (tid < w) csig[tid] = cord[tid];
+    if (row < m) {
+        const int a = rposs[row];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            int col = cg + 16 * k;
+            if (col >= w) continue;
+            const int bpos = cposs[col];
+            double v = fred(y[k], F);
+            double out;
+            if (a == bpos && a < r) out = v;                           // D
+            else if (bpos < a && bpos < r) out = v;                    // L / M (stored multipliers)
+            else if (a < bpos && a < r) out = fmulm(v, pinvx[a], F);   // U / V
+            else out = 0.0;
+            T[(cs + col) * ld + a0 + row] = out;
+        }
+    }
+}
+
+// inverse table: tab[x] = x^{-1} mod p (tab[0] = 0), built once per modulus
+__global__ void k_inv_table(uint32_t* tab, Field F) {
+    int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (x >= F.ip) return;
+    tab[x] = (uint32_t)finv((double)x, F);
+}
+
+// dst[j][i] = src[i][j] for the rows x cols matrix src
+__global__ void k_transpose(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t rows, int64_t cols) {
+    int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int64_t i = blockIdx.y;
+    if (j >= cols || i >= rows) return;
+    dst[j * ldd + i] = src[i * lds + j];
+}
+
+// dst[i][j] = src[roff + rsig[i]][coff + csig[j]] (a NULL sigma is the identity)
+__global__ void k_mat_gather(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t rows, int64_t cols,
+                             const int32_t* rsig, int64_t roff, const int32_t* csig, int64_t coff) {
+    int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int64_t i = blockIdx.y;
+    if (j >= cols || i >= rows) return;
+    int64_t si = rsig ? roff + rsig[i] : i;
+    int64_t sj = csig ? coff + csig[j] : j;
+    dst[i * ldd + j] = src[si * lds + sj];
+}
+
+// idx[a+q] <- idx[a+sig[q]] for q < len (through tmp)
+__global__ void k_idx_gather(const int32_t* idx, int64_t a, int64_t len, const int32_t* sig, int32_t* tmp) {
+    int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q < len) tmp[q] = idx[a + sig[q]];
+}
+__global__ void k_idx_copy(int32_t* idx, int64_t a, int64_t len, const int32_t* tmp) {
+    int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q < len) idx[a + q] = tmp[q];
 }
 
 // ===========================================================================
@@ -389,126 +473,158 @@ __global__ __launch_bounds__(64) void k_trss_leaf(double* W, int64_t ld, int64_t
 
 // ===========================================================================
 // Triangular solve leaves (Section 3, TRSM) with unit triangular T of order
-// r <= 64, delayed reduction over at most 63 products.
+// r <= 64: one thread per right-hand side, its 64 unknowns in registers (fully
+// unrolled substitution, T broadcast from LDS), delayed reduction over at most
+// 63 products.
 // ===========================================================================
-// B (m x r, row-major) <- B T^{-1}, T unit upper; one workgroup per 64 rows.
-__global__ __launch_bounds__(256) void k_trsm_ru_leaf(double* B, int64_t ld, int64_t m, int r, MatV T, Field F) {
-    __shared__ double Ts[64][65];
+// B (m x r, row-major) <- B T^{-1}, T unit upper; 64 rows per workgroup of 64 threads.
+__global__ __launch_bounds__(64) void k_trsm_ru_leaf(double* B, int64_t ld, int64_t m, int r, MatV T, Field F) {
+    __shared__ double Ts[64][64];
     __shared__ double Bs[64][65];
     const int tid = threadIdx.x;
     const int64_t i0 = (int64_t)blockIdx.x * 64;
     const int rows = (int)min((int64_t)64, m - i0);
-    for (int e = tid; e < r * r; e += 256) {
-        int a = e / r, b = e - a * r;
-        Ts[a][b] = (a < b) ? fcen(T.p[a * T.rs + b * T.cs], F) : 0.0;
+    // T: thread tid loads column tid of T (64 independent loads in flight)
+    {
+        double tv[64];
+#pragma unroll
+        for (int a = 0; a < 64; ++a) tv[a] = (a < tid && tid < r) ? T.p[a * T.rs + tid * T.cs] : 0.0;
+#pragma unroll
+        for (int a = 0; a < 64; ++a) Ts[a][tid] = fcen(tv[a], F);
     }
-    for (int e = tid; e < rows * r; e += 256) {
-        int i = e / r, j = e - i * r;
-        Bs[i][j] = B[(i0 + i) * ld + j];
-    }
+    // B tile: 64 rows, each row read by consecutive threads
+#pragma unroll 4
+    for (int i = 0; i < rows; ++i) Bs[i][tid] = (tid < r) ? B[(i0 + i) * ld + tid] : 0.0;
     __syncthreads();
-    for (int j = 0; j < r; ++j) {
-        if (tid < rows) Bs[tid][j] = fcen(fred(Bs[tid][j], F), F);
-        __syncthreads();
-        const int w = r - j - 1;
-        if (w > 0)
-            for (int e = tid; e < rows * w; e += 256) {
-                int i = e / w, jj = j + 1 + (e - (e / w) * w);
-                Bs[i][jj] = fma(-Bs[i][j], Ts[j][jj], Bs[i][jj]);
-            }
-        __syncthreads();
+    double z[64];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) z[j] = (j < r && tid < rows) ? Bs[tid][j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 64; ++j) {
+        if (j < r) {
+            const double zj = fredc(z[j], F);
+            z[j] = zj;
+#pragma unroll
+            for (int jj = j + 1; jj < 64; ++jj) z[jj] = fma(-zj, Ts[j][jj], z[jj]);
+        }
     }
-    for (int e = tid; e < rows * r; e += 256) {
-        int i = e / r, j = e - i * r;
-        B[(i0 + i) * ld + j] = fcan(Bs[i][j], F);
-    }
+#pragma unroll
+    for (int j = 0; j < 64; ++j)
+        if (tid < rows && j < r) Bs[tid][j] = fcan(z[j], F);
+    __syncthreads();
+#pragma unroll 4
+    for (int i = 0; i < rows; ++i)
+        if (tid < r) B[(i0 + i) * ld + tid] = Bs[i][tid];
 }
 
-// B (r x ncols, row-major) <- T^{-1} B, T unit lower; one workgroup per 64 columns.
-__global__ __launch_bounds__(256) void k_trsm_ll_leaf(double* B, int64_t ld, int64_t ncols, int r, MatV T, Field F) {
-    __shared__ double Ts[64][65];
-    __shared__ double Bs[64][65];
+// B (r x ncols, row-major) <- T^{-1} B, T unit lower; one thread per column, 64 columns per workgroup.
+__global__ __launch_bounds__(64) void k_trsm_ll_leaf(double* B, int64_t ld, int64_t ncols, int r, MatV T, Field F) {
+    __shared__ double Ts[64][64];
     const int tid = threadIdx.x;
-    const int64_t j0 = (int64_t)blockIdx.x * 64;
-    const int cols = (int)min((int64_t)64, ncols - j0);
-    for (int e = tid; e < r * r; e += 256) {
-        int a = e / r, b = e - a * r;
-        Ts[a][b] = (a > b) ? fcen(T.p[a * T.rs + b * T.cs], F) : 0.0;
-    }
-    for (int e = tid; e < r * cols; e += 256) {
-        int i = e / cols, c = e - i * cols;
-        Bs[i][c] = B[i * ld + j0 + c];
+    const int64_t col = (int64_t)blockIdx.x * 64 + tid;
+    // T: thread tid loads column tid of T (64 independent loads in flight)
+    {
+        double tv[64];
+#pragma unroll
+        for (int a = 0; a < 64; ++a) tv[a] = (a > tid && a < r) ? T.p[a * T.rs + tid * T.cs] : 0.0;
+#pragma unroll
+        for (int a = 0; a < 64; ++a) Ts[a][tid] = fcen(tv[a], F);
     }
     __syncthreads();
-    for (int i = 0; i < r; ++i) {
-        if (tid < cols) Bs[i][tid] = fcen(fred(Bs[i][tid], F), F);
-        __syncthreads();
-        const int h = r - i - 1;
-        if (h > 0)
-            for (int e = tid; e < h * cols; e += 256) {
-                int ii = i + 1 + e / cols, c = e - (e / cols) * cols;
-                Bs[ii][c] = fma(-Ts[ii][i], Bs[i][c], Bs[ii][c]);
-            }
-        __syncthreads();
+    const bool ok = col < ncols;
+    double z[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) z[i] = (i < r && ok) ? B[i * ld + col] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+        if (i < r) {
+            const double zi = fredc(z[i], F);
+            z[i] = zi;
+#pragma unroll
+            for (int ii = i + 1; ii < 64; ++ii) z[ii] = fma(-Ts[ii][i], zi, z[ii]);
+        }
     }
-    for (int e = tid; e < r * cols; e += 256) {
-        int i = e / cols, c = e - i * cols;
-        B[i * ld + j0 + c] = fcan(Bs[i][c], F);
-    }
+#pragma unroll
+    for (int i = 0; i < 64; ++i)
+        if (i < r && ok) B[i * ld + col] = fcan(z[i], F);
 }
 
 // ===========================================================================
-// Symmetric permutation of the position range [lo, hi) (new lo+q <- old
-// lo+sig[q]), through a temporary: part 0 rows [lo,hi) x cols [0,lo);
-// part 1 the lower block; part 2 rows [hi,n) x cols [lo,hi); part 3 orig.
-// Gather into tmp (blockIdx.z = part), then scatter back.
+// Permutations.  A sigma maps new local position q to old local position
+// sig[q]; a NULL sigma with rot1 >= 0 stands for the rotation that moves the
+// first rot1 positions after the others.  Out-of-range sigma entries (a bug
+// upstream) are clamped so that no access leaves the range.
 // ===========================================================================
-__global__ __launch_bounds__(256) void k_perm_gather(const double* W, int64_t ld, int64_t n, int64_t lo,
-                                                     int64_t hi, const int32_t* sig, double* tmp,
-                                                     const int32_t* orig, int32_t* tmpo, int parts) {
-    const int64_t s = hi - lo;
-    const int part = blockIdx.z;
-    if (!((parts >> part) & 1)) return;
-    const int64_t row = blockIdx.y;
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    // a sigma entry outside [0, s) is a bug upstream: clamp it so no access leaves the range
-    auto sg = [&](int64_t q) -> int64_t { int64_t v = sig[q]; return (v < 0 || v >= s) ? 0 : v; };
+__device__ __forceinline__ int64_t sigma_at(const int32_t* sig, int64_t q, int64_t sz, int64_t rot1) {
+    int64_t v;
+    if (sig) v = sig[q];
+    else { int64_t len2 = sz - rot1; v = q < len2 ? rot1 + q : q - len2; }
+    return (v < 0 || v >= sz) ? 0 : v;
+}
+
+// Symmetric permutation of the position range [lo, hi) of W, through tmp:
+// part 0 rows [lo,hi) x cols [0,lo); part 1 the lower block; part 2 rows
+// [hi,n) x cols [lo,hi); part 3 orig.  One flat grid: block b is decoded into
+// (part, row, column block); `dir` 0 gathers into tmp, 1 scatters back.
+__global__ __launch_bounds__(256) void k_perm_sym(double* W, int64_t ld, PermGeom g, const int32_t* sig, int64_t rot1,
+                                                 double* tmp, int32_t* orig, int32_t* tmpo, int dir) {
+    int64_t b = blockIdx.x;
+    const int64_t s = g.s, lo = g.lo, hi = g.hi;
+    int part;
+    if (b < g.B0) part = 0;
+    else if ((b -= g.B0) < g.B1) part = 1;
+    else if ((b -= g.B1) < g.B2) part = 2;
+    else { b -= g.B2; part = 3; }
     if (part == 0) {
-        if (row >= s || c >= lo) return;
-        tmp[row * lo + c] = W[(lo + sg(row)) * ld + c];
+        int64_t row = b / g.nb0, c = (b - row * g.nb0) * 256 + threadIdx.x;
+        if (c >= lo) return;
+        if (dir == 0) tmp[row * lo + c] = W[(lo + sigma_at(sig, row, s, rot1)) * ld + c];
+        else W[(lo + row) * ld + c] = tmp[row * lo + c];
     } else if (part == 1) {
-        if (row >= s || c > row) return;
-        int64_t a = lo + sg(row), b = lo + sg(c);
-        tmp[s * lo + row * s + c] = (a >= b) ? W[a * ld + b] : W[b * ld + a];
+        int64_t row = b / g.nb1, c = (b - row * g.nb1) * 256 + threadIdx.x;
+        if (c > row) return;
+        if (dir == 0) {
+            int64_t x = lo + sigma_at(sig, row, s, rot1), y = lo + sigma_at(sig, c, s, rot1);
+            tmp[s * lo + row * s + c] = (x >= y) ? W[x * ld + y] : W[y * ld + x];
+        } else {
+            W[(lo + row) * ld + lo + c] = tmp[s * lo + row * s + c];
+        }
     } else if (part == 2) {
-        if (row >= n - hi || c >= s) return;
-        tmp[s * lo + s * s + row * s + c] = W[(hi + row) * ld + lo + sg(c)];
+        int64_t row = b / g.nb1, c = (b - row * g.nb1) * 256 + threadIdx.x;
+        if (c >= s) return;
+        if (dir == 0) tmp[s * lo + s * s + row * s + c] = W[(hi + row) * ld + lo + sigma_at(sig, c, s, rot1)];
+        else W[(hi + row) * ld + lo + c] = tmp[s * lo + s * s + row * s + c];
     } else {
-        if (row != 0 || c >= s) return;
-        tmpo[c] = orig[lo + sg(c)];
+        int64_t c = b * 256 + threadIdx.x;
+        if (c >= s) return;
+        if (dir == 0) tmpo[c] = orig[lo + sigma_at(sig, c, s, rot1)];
+        else orig[lo + c] = tmpo[c];
     }
 }
 
-__global__ __launch_bounds__(256) void k_perm_scatter(double* W, int64_t ld, int64_t n, int64_t lo, int64_t hi,
-                                                      const double* tmp, int32_t* orig, const int32_t* tmpo,
-                                                      int parts) {
-    const int64_t s = hi - lo;
-    const int part = blockIdx.z;
-    if (!((parts >> part) & 1)) return;
-    const int64_t row = blockIdx.y;
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (part == 0) {
-        if (row >= s || c >= lo) return;
-        W[(lo + row) * ld + c] = tmp[row * lo + c];
-    } else if (part == 1) {
-        if (row >= s || c > row) return;
-        W[(lo + row) * ld + lo + c] = tmp[s * lo + row * s + c];
-    } else if (part == 2) {
-        if (row >= n - hi || c >= s) return;
-        W[(hi + row) * ld + lo + c] = tmp[s * lo + s * s + row * s + c];
+// Row (by_rows = 1) or column permutation of the window [a, a+sz) of the
+// compact matrix T (R x C, leading dimension ldT), with the index map idx
+// composed alongside (idx[a+q] <- idx[a+sig[q]]).  Grid y = rows of the
+// gathered block + 1 (the extra row handles idx); dir 0 gathers, 1 scatters.
+__global__ __launch_bounds__(256) void k_tperm(double* T, int64_t ldT, int64_t R, int64_t C, int by_rows, int64_t a,
+                                              int64_t sz, const int32_t* sig, int64_t rot1, double* tmp, int32_t* idx,
+                                              int32_t* tmpi, int dir) {
+    const int64_t rows = by_rows ? sz : R, cols = by_rows ? C : sz;
+    const int64_t i = blockIdx.y, j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i == rows) {
+        if (j >= sz) return;
+        if (dir == 0) tmpi[j] = idx[a + sigma_at(sig, j, sz, rot1)];
+        else idx[a + j] = tmpi[j];
+        return;
+    }
+    if (j >= cols) return;
+    if (dir == 0) {
+        int64_t si = by_rows ? a + sigma_at(sig, i, sz, rot1) : i;
+        int64_t sj = by_rows ? j : a + sigma_at(sig, j, sz, rot1);
+        tmp[i * cols + j] = T[si * ldT + sj];
     } else {
-        if (row != 0 || c >= s) return;
-        orig[lo + c] = tmpo[c];
+        int64_t di = by_rows ? a + i : i, dj = by_rows ? j : a + j;
+        T[di * ldT + dj] = tmp[i * cols + j];
     }
 }
 
@@ -589,6 +705,19 @@ __global__ void k_pack_dinv(const double* W, int64_t ld, int64_t c0, int64_t a0,
     int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= r) return;
     dinv[k] = finv(W[(c0 + k) * ld + a0 + k], F);
+}
+
+// X[k][j] *= 1/P[k][k] (by_row = 1) or X[j][k] *= 1/P[k][k] (by_row = 0), with the
+// pivots read from the diagonal of a PLDUQ pack P (leading dimension ldp)
+__global__ void k_scale_pack(double* X, int64_t ld, int64_t rows, int64_t cols, const double* P, int64_t ldp,
+                             int by_row, const uint32_t* itab, Field F) {
+    int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int64_t i = blockIdx.y;
+    if (j >= cols || i >= rows) return;
+    int64_t k = by_row ? i : j;
+    double d = P[k * ldp + k];
+    double di = itab ? (double)itab[(int)d] : finv(d, F);
+    X[i * ld + j] = fmulm(X[i * ld + j], di, F);
 }
 
 // X[k][j] *= dinv[k]  (rows x cols block, row k scaled)   -- by_row = 1
@@ -841,6 +970,20 @@ __global__ void k_zlp_sigma(int32_t* sig, int64_t mz, int64_t nc, int64_t rY) {
     sig[q] = (int32_t)o;
 }
 
+// sigma of the Algorithm 3 assembly composed with PLDUQ's row map pR (zero block)
+// and column map pC: the permutation applied once to the L part and the rows below
+__global__ void k_zlp_sigma_total(int32_t* sig, int64_t mz, int64_t nc, int64_t rY, const int32_t* pR,
+                                  const int32_t* pC) {
+    const int64_t N = mz + nc, nz = nc - rY;
+    int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= N) return;
+    int64_t o;
+    if (q < 2 * rY) o = (q & 1) ? mz + (q >> 1) : (q >> 1);
+    else if (q < 2 * rY + nz) o = mz + rY + (q - 2 * rY);
+    else o = rY + (q - 2 * rY - nz);
+    sig[q] = (int32_t)(o < mz ? pR[o] : mz + pC[o - mz]);
+}
+
 // out = A D (n x k), D block diagonal given by (dd, de)
 __global__ void k_apply_d(const double* A, int64_t lda, int64_t n, int64_t k, const double* dd, const double* de,
                           double* out, Field F) {
@@ -869,23 +1012,6 @@ __global__ void k_trss_unpack(const double* W, int64_t ldw, int64_t n, double* X
     int64_t a = blockIdx.y;
     if (a >= n || b >= n) return;
     X[a * ldx + b] = (a <= b) ? W[(n + b) * ldw + n + a] : 0.0;
-}
-
-// PLDUQ standalone layout in an (m+n) x (m+n) W: Y^T at W[m.., 0..m)
-__global__ void k_plduq_pack(const double* Y, int64_t ldy, int64_t m, int64_t n, double* W, int64_t ldw) {
-    int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    int64_t i = blockIdx.y;
-    if (i >= m || j >= n) return;
-    W[(m + j) * ldw + i] = Y[i * ldy + j];
-}
-__global__ void k_plduq_unpack(const double* W, int64_t ldw, int64_t m, int64_t n, double* Y, int64_t ldy,
-                               const int32_t* orig, int32_t* rows, int32_t* cols) {
-    int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    int64_t a = blockIdx.y;
-    if (a >= m) return;
-    if (b < n) Y[a * ldy + b] = W[(m + b) * ldw + a];
-    if (b == 0) rows[a] = orig[a];
-    if (a == 0 && b < n) cols[b] = orig[m + b] - (int32_t)m;
 }
 
 // ===========================================================================
