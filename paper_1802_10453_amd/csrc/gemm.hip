@@ -9,12 +9,17 @@
 // v_mfma_f64_16x16x4f64 products and sums are integers below 2^53 and hence
 // exact in any order; the accumulators are reduced mod p every F.kred products
 // (delayed reduction), and once more in the epilogue.
+//
+// Structure: workgroup tile BM x BN (128x128, or 64x64 when the big tiles would
+// leave CUs idle), 4 waves in a 2x2 grid, K tiles of 16 staged through
+// double-buffered LDS (one barrier per K tile), the next K tile's global loads
+// in flight while the current one feeds the matrix cores.
 #include "common.h"
 
 namespace pldl {
 
 namespace {
-constexpr int BM = 128, BN = 128, BK = 16, NT = 256, PAD = 4;
+constexpr int BK = 16, NT = 256, PAD = 16;
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 struct GemmKArgs {
@@ -29,12 +34,15 @@ struct GemmKArgs {
     int32_t nzoff;
 };
 
-template <bool A_ROW, bool B_ROW, bool LOWER_C, bool B_UPPER>
+template <int BM, int BN, bool A_ROW, bool B_ROW, bool LOWER_C, bool B_UPPER>
 __global__ __launch_bounds__(NT) void k_gemm(GemmKArgs g) {
-    __shared__ double As[BK][BM + PAD];
-    __shared__ double Bs[BK][BN + PAD];
+    constexpr int WM = BM / 2, WN = BN / 2;      // wave tile
+    constexpr int FM = WM / 16, FN = WN / 16;    // 16x16 MFMA blocks per wave
+    constexpr int AE = BM * BK / NT, BE = BN * BK / NT;
+    __shared__ double As[2][BK][BM + PAD];
+    __shared__ double Bs[2][BK][BN + PAD];
     const Field F = g.F;
-    int bid = blockIdx.x;
+    const int bid = blockIdx.x;
     int ti, tj;
     if (LOWER_C) {
         ti = (int)((sqrt(8.0 * (double)bid + 1.0) - 1.0) * 0.5);
@@ -50,99 +58,105 @@ __global__ __launch_bounds__(NT) void k_gemm(GemmKArgs g) {
     const int wm = wave >> 1, wn = wave & 1;
     const int lr = lane & 15, lk = lane >> 4;
 
-    d4 acc[4][4];
+    // per-thread load coordinates inside a tile (element e adds a fixed step)
+    //   A row-major:  row tid/16 + 16e, col tid%16     A col-major: row tid%BM, col tid/BM + (NT/BM)e
+    //   B row-major:  k tid/BN + (NT/BN)e, col tid%BN  B col-major: k tid%16, col tid/16 + 16e
+    const int a_r0 = A_ROW ? tid / BK : tid % BM, a_c0 = A_ROW ? tid % BK : tid / BM;
+    const int a_dr = A_ROW ? NT / BK : 0, a_dc = A_ROW ? 0 : NT / BM;
+    const int b_k0 = B_ROW ? tid / BN : tid % BK, b_c0 = B_ROW ? tid % BN : tid / BK;
+    const int b_dk = B_ROW ? NT / BN : 0, b_dc = B_ROW ? 0 : NT / BK;
+
+    d4 acc[FM][FN];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
     int since = 0;
-    double ra[8], rb[8];
+    double ra[AE], rb[BE];
 #pragma unroll 1
     for (int seg = 0; seg < 2; ++seg) {
         const int64_t K = g.K[seg];
         if (K <= 0) continue;
         const MatV A = g.A[seg], B = g.B[seg];
         const bool mask_b = B_UPPER && seg == 0;
+        // Loads are unconditional (out-of-range coordinates are clamped to the last
+        // valid row/column) so that all of them are in flight together; the
+        // validity masks are applied when the values are written to LDS.
+        const int64_t mlast = g.m - 1, nlast = g.n - 1, klast = K - 1;
+        uint32_t va = 0, vb = 0;
         auto load = [&](int64_t kt) {
+            va = 0; vb = 0;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                int idx = tid + e * NT;
-                int r, c;
-                if (A_ROW) { r = idx / BK; c = idx % BK; } else { r = idx % BM; c = idx / BM; }
-                int64_t gi = i0 + r, gk = kt + c;
-                double v = 0.0;
-                if (gi < g.m && gk < K) v = fcen(A.p[gi * A.rs + gk * A.cs], F);
-                ra[e] = v;
+            for (int e = 0; e < AE; ++e) {
+                const int64_t gi = i0 + a_r0 + a_dr * e, gk = kt + a_c0 + a_dc * e;
+                const bool ok = gi <= mlast && gk <= klast;
+                va |= (ok ? 1u : 0u) << e;
+                ra[e] = A.p[min(gi, mlast) * A.rs + min(gk, klast) * A.cs];
             }
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                int idx = tid + e * NT;
-                int c, r;
-                if (B_ROW) { c = idx / BN; r = idx % BN; } else { c = idx % BK; r = idx / BK; }
-                int64_t gk = kt + c, gj = j0 + r;
-                double v = 0.0;
-                if (gk < K && gj < g.n && !(mask_b && gk > gj)) v = fcen(B.p[gk * B.rs + gj * B.cs], F);
-                rb[e] = v;
+            for (int e = 0; e < BE; ++e) {
+                const int64_t gk = kt + b_k0 + b_dk * e, gj = j0 + b_c0 + b_dc * e;
+                const bool ok = gk <= klast && gj <= nlast && !(mask_b && gk > gj);
+                vb |= (ok ? 1u : 0u) << e;
+                rb[e] = B.p[min(gk, klast) * B.rs + min(gj, nlast) * B.cs];
             }
         };
+        auto store = [&](int buf) {
+#pragma unroll
+            for (int e = 0; e < AE; ++e)
+                As[buf][a_c0 + a_dc * e][a_r0 + a_dr * e] = ((va >> e) & 1u) ? fcen(ra[e], F) : 0.0;
+#pragma unroll
+            for (int e = 0; e < BE; ++e)
+                Bs[buf][b_k0 + b_dk * e][b_c0 + b_dc * e] = ((vb >> e) & 1u) ? fcen(rb[e], F) : 0.0;
+        };
+        __syncthreads();   // LDS of a previous segment fully consumed
         load(0);
+        store(0);
+        __syncthreads();
+        int cur = 0;
 #pragma unroll 1
         for (int64_t kt = 0; kt < K; kt += BK) {
-            __syncthreads();
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                int idx = tid + e * NT;
-                int r, c;
-                if (A_ROW) { r = idx / BK; c = idx % BK; } else { r = idx % BM; c = idx / BM; }
-                As[c][r] = ra[e];
-            }
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                int idx = tid + e * NT;
-                int c, r;
-                if (B_ROW) { c = idx / BN; r = idx % BN; } else { c = idx % BK; r = idx / BK; }
-                Bs[c][r] = rb[e];
-            }
-            __syncthreads();
-            if (kt + BK < K) load(kt + BK);
+            const bool more = kt + BK < K;
+            if (more) load(kt + BK);
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 4) {
-                double a[4], b[4];
+                double a[FM], b[FN];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    a[t] = As[kk + lk][wm * 64 + t * 16 + lr];
-                    b[t] = Bs[kk + lk][wn * 64 + t * 16 + lr];
-                }
+                for (int t = 0; t < FM; ++t) a[t] = As[cur][kk + lk][wm * WM + t * 16 + lr];
 #pragma unroll
-                for (int x = 0; x < 4; ++x)
+                for (int t = 0; t < FN; ++t) b[t] = Bs[cur][kk + lk][wn * WN + t * 16 + lr];
 #pragma unroll
-                    for (int y = 0; y < 4; ++y)
+                for (int x = 0; x < FM; ++x)
+#pragma unroll
+                    for (int y = 0; y < FN; ++y)
                         acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
             }
+            if (more) store(cur ^ 1);
+            __syncthreads();
+            cur ^= 1;
             since += BK;
             if (since >= F.kred) {
 #pragma unroll
-                for (int x = 0; x < 4; ++x)
+                for (int x = 0; x < FM; ++x)
 #pragma unroll
-                    for (int y = 0; y < 4; ++y)
+                    for (int y = 0; y < FN; ++y)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) acc[x][y][r] = fred(acc[x][y][r], F);
                 since = 0;
             }
         }
     }
-    // epilogue: output element (row, col) of MFMA block (x, y), register r
+    // epilogue: v_mfma_f64_16x16x4f64 result layout: lane l, register r holds D[l/16 + 4r][l%16]
     int first_nz = 1 << 30;
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < FM; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y)
+        for (int y = 0; y < FN; ++y)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                // v_mfma_f64_16x16x4f64 result layout: lane l, register r holds D[l/16 + 4r][l%16]
-                int64_t row = i0 + wm * 64 + x * 16 + lk + 4 * r;
-                int64_t col = j0 + wn * 64 + y * 16 + lr;
+                const int64_t row = i0 + wm * WM + x * 16 + lk + 4 * r;
+                const int64_t col = j0 + wn * WN + y * 16 + lr;
                 if (row < g.m && col < g.n && (!LOWER_C || col <= row)) {
                     double* c = g.C + row * g.ldc + col;
                     double v = fred(*c - fred(acc[x][y][r], F), F);
@@ -154,7 +168,7 @@ __global__ __launch_bounds__(NT) void k_gemm(GemmKArgs g) {
         // block minimum, then one atomic per block
         for (int off = 32; off > 0; off >>= 1) first_nz = min(first_nz, __shfl_xor(first_nz, off));
         __syncthreads();
-        int* red = (int*)&As[0][0];
+        int* red = (int*)&As[0][0][0];
         if (lane == 0) red[wave] = first_nz;
         __syncthreads();
         if (tid == 0) {
@@ -164,15 +178,26 @@ __global__ __launch_bounds__(NT) void k_gemm(GemmKArgs g) {
     }
 }
 
-template <bool AR, bool BR>
+template <int BM, int BN, bool AR, bool BR>
 void dispatch(hipStream_t s, const GemmKArgs& g, int blocks, bool lower_c, bool b_upper) {
     if (lower_c) {
-        if (b_upper) hipLaunchKernelGGL((k_gemm<AR, BR, true, true>), dim3(blocks), dim3(NT), 0, s, g);
-        else hipLaunchKernelGGL((k_gemm<AR, BR, true, false>), dim3(blocks), dim3(NT), 0, s, g);
+        if (b_upper) hipLaunchKernelGGL((k_gemm<BM, BN, AR, BR, true, true>), dim3(blocks), dim3(NT), 0, s, g);
+        else hipLaunchKernelGGL((k_gemm<BM, BN, AR, BR, true, false>), dim3(blocks), dim3(NT), 0, s, g);
     } else {
-        if (b_upper) hipLaunchKernelGGL((k_gemm<AR, BR, false, true>), dim3(blocks), dim3(NT), 0, s, g);
-        else hipLaunchKernelGGL((k_gemm<AR, BR, false, false>), dim3(blocks), dim3(NT), 0, s, g);
+        if (b_upper) hipLaunchKernelGGL((k_gemm<BM, BN, AR, BR, false, true>), dim3(blocks), dim3(NT), 0, s, g);
+        else hipLaunchKernelGGL((k_gemm<BM, BN, AR, BR, false, false>), dim3(blocks), dim3(NT), 0, s, g);
     }
+}
+
+template <int BM, int BN>
+void dispatch_layout(hipStream_t s, GemmKArgs& g, bool ar, bool br, bool lower_c, bool b_upper) {
+    const int tm = (int)((g.m + BM - 1) / BM), tn = (int)((g.n + BN - 1) / BN);
+    g.tiles_n = tn;
+    const int blocks = lower_c ? tm * (tm + 1) / 2 : tm * tn;
+    if (ar && br) dispatch<BM, BN, true, true>(s, g, blocks, lower_c, b_upper);
+    else if (ar && !br) dispatch<BM, BN, true, false>(s, g, blocks, lower_c, b_upper);
+    else if (!ar && br) dispatch<BM, BN, false, true>(s, g, blocks, lower_c, b_upper);
+    else dispatch<BM, BN, false, false>(s, g, blocks, lower_c, b_upper);
 }
 }  // namespace
 
@@ -193,15 +218,12 @@ void launch_gemm(hipStream_t s, const Field& F, int64_t m, int64_t n, double* C,
     }
     if (!any) return;
     // both segments share operand layouts (checked by the caller)
-    int first = g.K[0] > 0 ? 0 : 1;
-    bool ar = g.A[first].cs == 1, br = g.B[first].cs == 1;
-    int tm = (int)((m + BM - 1) / BM), tn = (int)((n + BN - 1) / BN);
-    g.tiles_n = tn;
-    int blocks = lower_c ? tm * (tm + 1) / 2 : tm * tn;
-    if (ar && br) dispatch<true, true>(s, g, blocks, lower_c, b_upper);
-    else if (ar && !br) dispatch<true, false>(s, g, blocks, lower_c, b_upper);
-    else if (!ar && br) dispatch<false, true>(s, g, blocks, lower_c, b_upper);
-    else dispatch<false, false>(s, g, blocks, lower_c, b_upper);
+    const int first = g.K[0] > 0 ? 0 : 1;
+    const bool ar = g.A[first].cs == 1, br = g.B[first].cs == 1;
+    // big tiles unless they would leave most of the 256 CUs idle
+    const int64_t t128 = ((m + 127) / 128) * ((n + 127) / 128) / (lower_c ? 2 : 1);
+    if (t128 >= 192) dispatch_layout<128, 128>(s, g, ar, br, lower_c, b_upper);
+    else dispatch_layout<64, 64>(s, g, ar, br, lower_c, b_upper);
 }
 
 }  // namespace pldl
