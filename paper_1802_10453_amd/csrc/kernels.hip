@@ -239,12 +239,16 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
 // rows [a0, a0+m) of Y (m <= 64), columns [c0, c1).  The kernel scans 256-wide
 // column chunks (from max(c0, *hint) when a hint is given: the first column a
 // preceding update found nonzero on these rows) until one holds a nonzero in
-// one of the rows, then eliminates that chunk row by row: a row's pivot is the
-// first nonzero of its reduced row among the chunk's non-pivot columns; an
-// all-zero row is skipped.  Right-looking with delayed reduction, the chunk in
-// registers: thread t owns row t%64 and columns t/64 + 16k (k < 16).  Every
-// wave runs the pivot search itself (no serial thread), the row and multiplier
-// vectors are double buffered: two barriers per row.
+// one of the rows, then eliminates that chunk in row order: a row's pivot is
+// the first nonzero of its reduced row among the chunk's non-pivot columns.
+// Elimination only adds multiples of pivot rows to a row in proportion to its
+// own entries on the pivot columns, so a row that is zero on the live columns
+// stays zero: the loop visits only the rows of an exact nonzero-row mask,
+// i.e. one iteration per pivot.  Right-looking, the chunk in registers, kept
+// reduced (centered) after every update so that the zero tests are exact:
+// thread t owns row t%64 and columns t/64 + 16k (k < 16).  Every wave runs the
+// pivot search itself (no serial thread); row, multiplier and mask vectors
+// are double buffered: three barriers per pivot.
 // Output: the LU pack of the chunk in the ORIGINAL (unpermuted) coordinates,
 // rsig (m) / csig (chunk width) and info = {rank, chunk start, chunk width}.
 // ===========================================================================
@@ -259,6 +263,7 @@ __global__ __launch_bounds__(1024) void k_plduq_leaf(double* T, int64_t ld, int6
     __shared__ double pinvx[64];
     __shared__ int wcnt[4];
     __shared__ int rord[64], cord[256], rposs[64], cposs[256];
+    __shared__ unsigned long long wmask[2][16];
     const int tid = threadIdx.x, row = tid & 63, cg = tid >> 6, lane = tid & 63;
     double y[16];
     int64_t cs = c0;
@@ -273,7 +278,7 @@ __global__ __launch_bounds__(1024) void k_plduq_leaf(double* T, int64_t ld, int6
         for (int k = 0; k < 16; ++k) {
             int col = cg + 16 * k;
             double v = (row < m && col < w) ? T[(cs + col) * ld + a0 + row] : 0.0;
-            y[k] = v;
+            y[k] = fcen(v, F);
             nzf |= (v != 0.0);
         }
         if (__syncthreads_or(nzf)) break;
@@ -290,25 +295,39 @@ __global__ __launch_bounds__(1024) void k_plduq_leaf(double* T, int64_t ld, int6
 #pragma unroll
     for (int k = 0; k < 16; ++k)
         if (cg + 16 * k < w) live |= 1u << k;
+    // rows (bits) holding a nonzero on the live columns: per-wave ballots, OR-ed
+    auto row_nz = [&]() {
+        bool nz = false;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) nz |= ((live >> k) & 1u) && y[k] != 0.0;
+        return nz;
+    };
+    {
+        const unsigned long long bal = __ballot(row_nz());
+        if (lane == 0) wmask[0][cg] = bal;
+    }
     __syncthreads();
-    int r = 0;
-    for (int i = 0; i < m; ++i) {
-        const int b = i & 1;
+    int r = 0, i = -1, mb = 0;
+    for (;;) {
+        unsigned long long rows_nz = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) rows_nz |= wmask[mb][q];
+        rows_nz &= (i >= 63) ? 0ull : (~0ull << (i + 1));
+        if (rows_nz == 0) break;
+        i = __ffsll((long long)rows_nz) - 1;
+        const int b = r & 1;
         if (row == i) {
-            double rv[16];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) rv[k] = ((live >> k) & 1u) ? fredc(y[k], F) : 0.0;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) rowI[b][cg + 16 * k] = rv[k];
+            for (int k = 0; k < 16; ++k) rowI[b][cg + 16 * k] = ((live >> k) & 1u) ? y[k] : 0.0;
         }
         __syncthreads();
-        // every wave finds the first nonzero of the row (lowest column index)
+        // every wave finds the first nonzero of the row (lowest column index); the
+        // mask guarantees there is one
         int c = -1;
         for (int q = 0; q < 4 && c < 0; ++q) {
             unsigned long long bal = __ballot(rowI[b][q * 64 + lane] != 0.0);
             if (bal) c = q * 64 + __ffsll((long long)bal) - 1;
         }
-        if (c < 0) continue;  // zero row: nothing changes
         const double x = fcan(rowI[b][c], F);
         const double xi = itab ? (double)itab[(int)x] : finv(x, F);
         // this lane's columns: the pivot column leaves the live set
@@ -321,7 +340,7 @@ __global__ __launch_bounds__(1024) void k_plduq_leaf(double* T, int64_t ld, int6
             double v = 0.0;
 #pragma unroll
             for (int k = 0; k < 16; ++k) v = (k == (c >> 4)) ? y[k] : v;
-            fvec[b][row] = (row > i && row < m) ? fredc(fredc(v, F) * xi, F) : 0.0;
+            fvec[b][row] = (row > i && row < m) ? fredc(v * xi, F) : 0.0;
         }
         __syncthreads();
         const double f = fvec[b][row];
@@ -329,16 +348,19 @@ __global__ __launch_bounds__(1024) void k_plduq_leaf(double* T, int64_t ld, int6
 #pragma unroll
         for (int k = 0; k < 16; ++k) rw[k] = rowI[b][cg + 16 * k];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) y[k] = fma(-f, rw[k], y[k]);
+        for (int k = 0; k < 16; ++k) y[k] = fredc(fma(-f, rw[k], y[k]), F);
         // the pivot column now stores the multipliers (L) of the rows below
         if (cg == (c & 15) && row > i && row < m) {
 #pragma unroll
             for (int k = 0; k < 16; ++k)
-                if (k == (c >> 4)) y[k] = fcan(f, F);
+                if (k == (c >> 4)) y[k] = f;
         }
         ++r;
+        mb ^= 1;
+        const unsigned long long bal = __ballot(row_nz());
+        if (lane == 0) wmask[mb][cg] = bal;
+        __syncthreads();
     }
-    __syncthreads();
     // ---- orders: pivots first (pivot order), then the rest increasing (ballot prefix counts)
     if (tid < 64) {
         bool np = (tid < m) && rpiv[tid] < 0;
