@@ -58,6 +58,12 @@ __device__ __forceinline__ double finv(double a, const Field& F) {
 }
 
 // ---------------------------------------------------------------------------
+// "No nonzero seen" value of the first-nonzero slots (a column index above any n).
+constexpr int32_t NZ_NONE = 0x7F7F7F7F;
+// Most workgroups of a PLDUQ right-part update (one first-nonzero candidate each).
+constexpr int NZB_MAX = 2048;
+
+// ---------------------------------------------------------------------------
 // Strided matrix view: element (i, j) at p[i*rs + j*cs].  One of the strides
 // is 1 for every view the library forms (row-major: cs = 1; column-major: rs = 1).
 struct MatV {

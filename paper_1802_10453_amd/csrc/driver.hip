@@ -167,7 +167,7 @@ struct Workspace {
                 release();
                 throw Err(PLDL_ENOMEM, "alloc");
             }
-        if (hipMalloc((void**)&info, 1024 * sizeof(int32_t)) != hipSuccess) { release(); throw Err(PLDL_ENOMEM, "alloc"); }
+        if (hipMalloc((void**)&info, (1024 + NZB_MAX) * sizeof(int32_t)) != hipSuccess) { release(); throw Err(PLDL_ENOMEM, "alloc"); }
         if (hipHostMalloc((void**)&hinfo, 1024 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
             release();
             throw Err(PLDL_ENOMEM, "pinned alloc");
@@ -440,16 +440,16 @@ struct Engine {
     // rows [a0, a1) and columns [c0, c1) of Y.  Row slabs of <= 64 rows; within a
     // slab the leaf finds the pivots of the first column chunk that is not zero on
     // the slab, the rest of the columns are updated (TRSM, GEMM) and searched again.
-    // hint (device int, may be NULL): a lower bound on the first column of the
+    // hint (device ints, may be NULL; the minimum of nhint entries): a lower bound on the first column of the
     // slab's rows holding a nonzero, left by the update that preceded the call.
-    int64_t plduq_t(int64_t a0, int64_t a1, int64_t c0, int64_t c1, const int32_t* hint = nullptr) {
+    int64_t plduq_t(int64_t a0, int64_t a1, int64_t c0, int64_t c1, const int32_t* hint = nullptr, int nhint = 0) {
         const int64_t m = a1 - a0;
         if (m <= 0 || c1 <= c0) return 0;
         REQUIRE(a1 <= TC && c1 <= TR);
         int32_t* nzh = ws.info + 8;
         if (m > 64) {
             const int64_t am = a0 + std::max<int64_t>(64, (m / 2) / 64 * 64);
-            const int64_t r1 = plduq_t(a0, am, c0, c1, hint);
+            const int64_t r1 = plduq_t(a0, am, c0, c1, hint, nhint);
             const int32_t* bhint = nullptr;
             if (r1 > 0) {
                 const int64_t mb = a1 - am, ncr = c1 - c0 - r1;
@@ -467,12 +467,12 @@ struct Engine {
                 LAUNCH(PLDL_CLASS_OTHER, k_scale_pack, dim3(nblk(mb), (unsigned)r1), dim3(256), 0, st, T + c0 * ldT + am, ldT, r1, mb,
                        T + c0 * ldT + a0, ldT, 1, itab, F);
             }
-            const int64_t r2 = plduq_t(am, a1, c0 + r1, c1, bhint);
+            const int64_t r2 = plduq_t(am, a1, c0 + r1, c1, bhint, 1);
             t_rot_yrows(a0 + r1, am, am + r2);
             return r1 + r2;
         }
         LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_leaf, dim3(1), dim3(1024), 0, st, T, ldT, a0, (int)m, c0, c1, F, itab, hint,
-               ws.sig, ws.sig + 64, ws.info);
+               nhint, ws.sig, ws.sig + 64, ws.info);
         const int32_t* h = read_info(3);
         const int64_t r = h[0], cs = h[1], w = h[2];
         if (r == 0) return 0;  // the slab is zero on [c0, c1)
@@ -483,19 +483,13 @@ struct Engine {
         int64_t r2 = 0;
         if (ce < c1) {
             const int64_t nr = c1 - ce;
-            // (D U_R)^T = Y_R[piv]^T L_t^{-T},  L_t^T[a][b] = T[c0+a][a0+b] (a < b)
-            trsm_ru(MatV{T + ce * ldT + a0, ldT, 1}, nr, r, MatV{T + c0 * ldT + a0, ldT, 1});
-            // Y_R[np]^T -= (D U_R)^T M_t^T, recording the first column left nonzero on those rows
-            const int32_t* rhint = nullptr;
-            if (m > r) {
-                HIPCHK(hipMemsetAsync(nzh, 0x7F, sizeof(int32_t), st));
-                gemm_ld(T + ce * ldT + a0 + r, ldT, nr, m - r,
-                        GemmSeg{MatV{T + ce * ldT + a0, ldT, 1}, MatV{T + c0 * ldT + a0 + r, ldT, 1}, r}, nzh, (int32_t)ce);
-                rhint = nzh;
-            }
-            LAUNCH(PLDL_CLASS_OTHER, k_scale_pack, dim3(nblk(r), (unsigned)nr), dim3(256), 0, st, T + ce * ldT + a0, ldT, nr, r,
-                   T + c0 * ldT + a0, ldT, 0, itab, F);
-            r2 = plduq_t(a0 + r, a1, ce, c1, rhint);
+            // (D U_R)^T = Y_R[piv]^T L_t^{-T}, Y_R[np]^T -= (D U_R)^T M_t^T, U_R = D^{-1} (D U_R), in one
+            // pass; each workgroup leaves the first column it found nonzero on the rows below in nzb
+            int32_t* nzb = ws.info + 1024;
+            const int64_t nb = std::min<int64_t>((nr + 3) / 4, NZB_MAX);
+            LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_rupdate, dim3((unsigned)nb), dim3(256), 0, st, T, ldT, a0, (int)m, (int)r,
+                   c0, ce, nr, F, itab, (m > r) ? nzb : nullptr);
+            r2 = plduq_t(a0 + r, a1, ce, c1, (m > r) ? nzb : nullptr, (int)nb);
             t_rot_ycols(c0 + r, ce, ce + r2);
         }
         return r + r2;

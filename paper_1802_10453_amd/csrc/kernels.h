@@ -7,7 +7,10 @@ namespace pldl {
 __global__ void k_bc_leaf(double* W, int64_t ld, int64_t lo, int s, Field F, const uint32_t* itab, double* dd,
                           double* de, int32_t* sig_out, int32_t* rank_out);
 __global__ void k_plduq_leaf(double* T, int64_t ld, int64_t a0, int m, int64_t c0, int64_t c1, Field F,
-                             const uint32_t* itab, const int32_t* hint, int32_t* rsig, int32_t* csig, int32_t* info);
+                             const uint32_t* itab, const int32_t* hint, int nhint, int32_t* rsig, int32_t* csig,
+                             int32_t* info);
+__global__ void k_plduq_rupdate(double* T, int64_t ld, int64_t a0, int m, int r, int64_t cp, int64_t ce, int64_t nr,
+                                Field F, const uint32_t* itab, int32_t* nzblk);
 __global__ void k_inv_table(uint32_t* tab, Field F);
 __global__ void k_mat_gather(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t rows, int64_t cols,
                              const int32_t* rsig, int64_t roff, const int32_t* csig, int64_t coff);

@@ -254,8 +254,8 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
 // ===========================================================================
 __global__ __launch_bounds__(1024) void k_plduq_leaf(double* T, int64_t ld, int64_t a0, int m, int64_t c0,
                                                      int64_t c1, Field F, const uint32_t* itab,
-                                                     const int32_t* hint, int32_t* rsig, int32_t* csig,
-                                                     int32_t* info) {
+                                                     const int32_t* hint, int nhint, int32_t* rsig,
+                                                     int32_t* csig, int32_t* info) {
     __shared__ double rowI[2][256];   // centered reduced row (0 on pivot columns)
     __shared__ double fvec[2][64];    // centered multipliers of the rows below
     __shared__ int ispc[256], cpiv[256];
@@ -267,7 +267,17 @@ __global__ __launch_bounds__(1024) void k_plduq_leaf(double* T, int64_t ld, int6
     const int tid = threadIdx.x, row = tid & 63, cg = tid >> 6, lane = tid & 63;
     double y[16];
     int64_t cs = c0;
-    if (hint) cs = max(c0, (int64_t)*hint);
+    if (hint) {   // the minimum of the nhint candidates left by the preceding update
+        __shared__ int hred[16];
+        int v = NZ_NONE;
+        for (int k = tid; k < nhint; k += 1024) v = min(v, hint[k]);
+        for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
+        if (lane == 0) hred[cg] = v;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v = min(v, hred[q]);
+        cs = max(c0, (int64_t)v);
+    }
     int w = 0;
     // ---- scan for the first chunk with a nonzero on these rows
     for (;;) {
@@ -402,6 +412,60 @@ __global__ __launch_bounds__(1024) void k_plduq_leaf(double* T, int64_t ld, int6
             else out = 0.0;
             T[(cs + col) * ld + a0 + row] = out;
         }
+    }
+}
+
+// ===========================================================================
+// Right-part update of a PLDUQ tile (the step after a leaf, Sections 4.2 and 3:
+// TRSM with the tile's unit lower L, GEMM with its multipliers M, scaling by
+// D^{-1}), fused into one pass over the columns to the right of the tile.  In
+// the compact transposed copy T, Y column j is T row j and the slab's rows
+// a0 .. a0+m-1 are m contiguous entries of it, so one wave takes one column
+// with lane t on slab row t.  The tile's pivot columns sit at T rows
+// cp .. cp+r-1 (pivot rows first in the slab): entry (s, t > s) of those rows
+// is the multiplier of slab row t for pivot s, entry (s, s) is D_s.  For each
+// column: u_s = y_s - sum_{s' < s} L[s][s'] u_s' (column elimination, one wave
+// shuffle per pivot), the other rows y_t -= M[t][s] u_s, then u_s <- u_s / D_s.
+// At most 64 products accumulate before the final reduction (below 2^53 for
+// p < 2^23).  With nzblk, workgroup b writes to nzblk[b] the first of its
+// columns left nonzero on rows r .. m-1 (NZ_NONE if none): the next leaf's scan
+// starts at the minimum (no atomics on one address from thousands of waves).
+// ===========================================================================
+__global__ __launch_bounds__(256) void k_plduq_rupdate(double* T, int64_t ld, int64_t a0, int m, int r, int64_t cp,
+                                                       int64_t ce, int64_t nr, Field F, const uint32_t* itab,
+                                                       int32_t* nzblk) {
+    __shared__ double Lc[64][64];   // Lc[s][t]: multiplier of row t > s for pivot s, 0 for t <= s
+    __shared__ double dinv[64];
+    __shared__ int wfirst[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < r * 64; e += 256) {
+        const int sp = e >> 6, t = e & 63;
+        Lc[sp][t] = (t > sp && t < m) ? fcen(T[(cp + sp) * ld + a0 + t], F) : 0.0;
+    }
+    if (tid < r) {
+        const double d = T[(cp + tid) * ld + a0 + tid];
+        dinv[tid] = itab ? (double)itab[(int)d] : finv(d, F);
+    }
+    __syncthreads();
+    int first = NZ_NONE;
+    const int64_t stride = (int64_t)gridDim.x * 4;
+    for (int64_t jj = (int64_t)blockIdx.x * 4 + wave; jj < nr; jj += stride) {
+        double* col = T + (ce + jj) * ld + a0;
+        double y = (lane < m) ? fcen(col[lane], F) : 0.0;
+        for (int sp = 0; sp < r; ++sp) {
+            const double us = fredc(__shfl(y, sp), F);
+            y = (lane == sp) ? us : fma(-Lc[sp][lane], us, y);
+        }
+        double out;
+        if (lane < r) out = fmulm(y, dinv[lane], F);
+        else out = fred(y, F);
+        if (lane < m) col[lane] = out;
+        if (first == NZ_NONE && __ballot(lane >= r && lane < m && out != 0.0)) first = (int)(ce + jj);
+    }
+    if (nzblk) {
+        if (lane == 0) wfirst[wave] = first;
+        __syncthreads();
+        if (tid == 0) nzblk[blockIdx.x] = min(min(wfirst[0], wfirst[1]), min(wfirst[2], wfirst[3]));
     }
 }
 
