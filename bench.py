@@ -9,6 +9,7 @@ Default workload: n = 16384 over F_8388593 with a uniformly random rank profile 
 rank 12288 (A = L R L^T, L random unit lower, R a seeded symmetric rook placement).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,6 +22,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
 PEAK_HBM_GBS = 8000.0
+METRIC = "effective mod-p GOPS (n\u00b2r-normalized), exact"
+# HBM traffic of the GEMM kernel per launch, from two rocprofv3 --pmc passes (FETCH_SIZE,
+# WRITE_SIZE) scaled by a plain copy of known size; valid only for the kernel sources it
+# was measured on (their SHA-256 is recorded beside the figure).
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm.n16384_p8388593_rank12288.traffic.txt")
+GEMM_SOURCES = ("paper_1802_10453_amd/csrc/gemm.hip", "paper_1802_10453_amd/csrc/common.h")
 
 
 def log(*a):
@@ -49,6 +56,31 @@ def cpu_baseline(workload_p):
                 sample=f"oracle search on n={n} p={p} rank={r} random-RPM input (same generator), {dt:.2f} s")
 
 
+def gemm_source_hash():
+    h = hashlib.sha256()
+    for rel in GEMM_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """Bytes per k_gemm launch from the committed counter summary, or None when it is
+    missing, was taken on another workload, or the kernel sources changed since."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if "=" in line and not line.startswith("#"):
+                    k, v = line.split("=", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("workload") != workload or kv.get("gemm_sources_sha256") != gemm_source_hash():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,6 +90,9 @@ def main():
     ap.add_argument("--threshold", type=int, default=0)
     ap.add_argument("--no-profile", action="store_true", help="time without per-launch events (no roofline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="before the timed steps, run one plain device copy of BYTES bytes (an elementwise "
+                         "kernel reading and writing BYTES each): the reference for the HBM counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this library runs one factorization per GPU and has no "
@@ -75,7 +110,7 @@ def main():
     log(f"[bench] input ready in {time.perf_counter() - t0:.1f} s")
     A0 = torch.from_numpy(A_np.astype(np.int32)).cuda()
     del A_np
-    nrun = args.warmup + args.steps
+    nrun = args.warmup + args.steps + (0 if args.no_profile else 1)
     copies = [A0.clone() for _ in range(nrun)]
     ctx = pldl.Context(0)
     out = None
@@ -88,9 +123,17 @@ def main():
         log(f"[bench] rank/rpm vs generator: {'ok' if ok else 'MISMATCH'}")
         if not ok:
             sys.exit(1)
+    if args.calibrate_copy > 0:
+        src = torch.ones(args.calibrate_copy // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {args.calibrate_copy} bytes read, {args.calibrate_copy} bytes written")
+        del src, dst
     torch.cuda.synchronize()
     if not args.no_profile:
-        ctx.profile(1)
+        ctx.profile(3)   # events around the GEMM launches only: the roofline kernel
     t0 = time.perf_counter()
     for k in range(args.steps):
         out = ctx.factor(copies[args.warmup + k], p, threshold=args.threshold)
@@ -99,6 +142,13 @@ def main():
     t1 = time.perf_counter()
     stats = ctx.profile(0) if not args.no_profile else None
     ms = (t1 - t0) * 1e3 / args.steps
+    full = None
+    if not args.no_profile:
+        # per-class breakdown from one more, untimed step with every launch recorded
+        ctx.profile(1)
+        ctx.factor(copies[-1], p, threshold=args.threshold)
+        torch.cuda.synchronize()
+        full = ctx.profile(0)
     r = out["rank"]
     value = eff_ops(n, r) / (ms / 1e3) / 1e9
     roofline = None
@@ -106,22 +156,24 @@ def main():
         g = stats["gemm"]
         achieved = g["flops"] / (g["ms"] / 1e3) / 1e12 if g["ms"] > 0 else 0.0
         roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                        frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=None,
+                        frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=measured_traffic(cfg["name"]),
                         kernel="k_gemm (FP64 MFMA mod-p product)",
                         avg_launch_ms=round(g["ms"] / max(g["launches"], 1), 4))
-        tot_ms = sum(v["ms"] for k2, v in stats.items() if k2 != "host_sync")
-        log("[bench] per-class GPU time per step (ms):")
-        for k2, v in stats.items():
-            log(f"    {k2:11s} launches {v['launches'] / args.steps:8.0f}  ms {v['ms'] / args.steps:9.3f}"
+    if full is not None:
+        tot_ms = sum(v["ms"] for k2, v in full.items() if k2 != "host_sync")
+        log("[bench] per-class GPU time of one extra step with every launch event-timed (ms; the events "
+            "themselves add queue time):")
+        for k2, v in full.items():
+            log(f"    {k2:11s} launches {v['launches']:8.0f}  ms {v['ms']:9.3f}"
                 + (f"  {v['flops'] / v['ms'] / 1e9:8.2f} TFLOP/s" if v["flops"] and v["ms"] else "")
                 + (f"  {v['bytes'] / v['ms'] / 1e6:8.1f} GB/s" if v["bytes"] and v["ms"] else ""))
-        log(f"    sum of kernel time {tot_ms / args.steps:.3f} ms/step vs wall {ms:.3f} ms/step")
+        log(f"    sum of kernel time {tot_ms:.3f} ms; timed steps {ms:.3f} ms/step")
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         cpu = cpu_baseline(p)
     line = {
-        "metric": "effective mod-p GOPS (n^2 r-normalized, exact)",
+        "metric": METRIC,
         "value": round(value, 2), "unit": "GOPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",

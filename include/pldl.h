@@ -170,10 +170,13 @@ typedef struct {
 } pldl_stats;
 
 /*
- * Profiling control.  mode 1: reset the totals and start recording; mode 0:
- * stop recording; mode 2: leave the state unchanged.  In every mode `out`
- * (host, may be NULL) receives the totals gathered so far.  Recording adds two
- * events per launch; it never changes results.
+ * Profiling control.  mode 1: reset the totals and start recording every
+ * class; mode 3: reset and record the GEMM class only (two events per GEMM
+ * launch, the other launches untouched: the light mode a timed run uses);
+ * mode 0: stop recording; mode 2: leave the state unchanged.  In every mode
+ * `out` (host, may be NULL) receives the totals gathered so far.  Recording
+ * adds two events per recorded launch (a few microseconds of queue time each);
+ * it never changes results.
  */
 int pldl_profile(pldl_ctx *ctx, int32_t mode, pldl_stats *out);
 

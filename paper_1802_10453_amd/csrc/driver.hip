@@ -63,6 +63,7 @@ static inline unsigned nblk(int64_t x, int b = 256) { return (unsigned)((x + b -
 // Profiling: HIP events around each launch, harvested at host synchronisations.
 struct Prof {
     bool on = false;
+    uint32_t mask = 0xFFu;   // classes recorded while on
     pldl_stats tot{};
     struct Rec { hipEvent_t a, b; int cls; double flops, bytes; };
     std::vector<Rec> recs;
@@ -81,7 +82,7 @@ struct Prof {
         return e;
     }
     void begin(hipStream_t st, int c, double flops = 0.0, double bytes = 0.0) {
-        if (!on) return;
+        if (!on || !((mask >> c) & 1u)) return;
         open_a = ev();
         HIPCHK(hipEventRecord(open_a, st));
         open_cls = c; open_f = flops; open_b = bytes;
@@ -105,7 +106,7 @@ struct Prof {
         recs.clear();
     }
     void host_wait(double ms) {
-        if (!on) return;
+        if (!on || !((mask >> PLDL_CLASS_HOST_SYNC) & 1u)) return;
         tot.cls[PLDL_CLASS_HOST_SYNC].launches += 1;
         tot.cls[PLDL_CLASS_HOST_SYNC].ms += ms;
     }
@@ -818,10 +819,14 @@ int pldl_plduq(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, double* Y, int64
 
 int pldl_profile(pldl_ctx* ctx, int32_t mode, pldl_stats* out) {
     if (!ctx) return -1;
-    if (mode < 0 || mode > 2) return fail(ctx, -2, "mode must be 0, 1 or 2");
+    if (mode < 0 || mode > 3) return fail(ctx, -2, "mode must be 0, 1, 2 or 3");
     return guarded(ctx, [&]() {
         ctx->prof.harvest();
-        if (mode == 1) { ctx->prof.tot = pldl_stats{}; ctx->prof.on = true; }
+        if (mode == 1 || mode == 3) {
+            ctx->prof.tot = pldl_stats{};
+            ctx->prof.on = true;
+            ctx->prof.mask = (mode == 1) ? 0xFFu : (1u << PLDL_CLASS_GEMM);
+        }
         if (mode == 0) ctx->prof.on = false;
         if (out) *out = ctx->prof.tot;
     });

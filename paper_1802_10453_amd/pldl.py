@@ -142,7 +142,8 @@ class Context:
         return rc, int(rank.value)
 
     def profile(self, mode: int) -> dict:
-        """pldl_profile: 1 = reset and start, 0 = stop, 2 = read.  Returns per-class totals."""
+        """pldl_profile: 1 = reset and start (all classes), 3 = reset and start (GEMM class only),
+        0 = stop, 2 = read.  Returns per-class totals."""
         st = pldl_stats()
         self._check(_lib.pldl_profile(self._h, int(mode), ctypes.byref(st)))
         return {name: dict(launches=st.cls[i].launches, flops=st.cls[i].flops, bytes=st.cls[i].bytes,
