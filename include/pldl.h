@@ -38,8 +38,10 @@ extern "C" {
 #define PLDL_U32 0             /* uint32 residues */
 #define PLDL_F64 1             /* FP64 residues   */
 
-#define PLDL_PATH_AUTO 0       /* FP64 MFMA                                      */
-#define PLDL_PATH_F64 1        /* products on FP64 MFMA with delayed reduction   */
+#define PLDL_PATH_AUTO 0       /* the context's path (pldl_set_path; FP64 at creation) */
+#define PLDL_PATH_F64 1        /* products on FP64 MFMA with delayed reduction         */
+#define PLDL_PATH_I8 2         /* products on INT8 MFMA: residues split into 1-3 signed
+                                  bytes, INT32 accumulation, mod-p recombination         */
 
 typedef struct pldl_ctx pldl_ctx;
 
@@ -145,6 +147,19 @@ int pldl_trss(pldl_ctx *ctx, uint32_t p, int64_t n, const double *U, int64_t ldu
  */
 int pldl_plduq(pldl_ctx *ctx, uint32_t p, int64_t m, int64_t n, double *Y, int64_t ldy,
                int32_t *rows, int32_t *cols, int64_t *rank, void *stream);
+
+/*
+ * Matrix cores used by the products (GEMM, TRMM, SYRDK, SYRD2K of Section 3)
+ * of every later call on this context whose options say PLDL_PATH_AUTO, and of
+ * the building-block calls above.  path: PLDL_PATH_F64 (default) or
+ * PLDL_PATH_I8.  The INT8 path writes each operand as L signed-byte digit
+ * planes (L = 1 for p < 2^8, 2 for p < 2^15, else 3) into a context buffer
+ * grown on demand, and runs the L^2 byte products on v_mfma_i32_16x16x64_i8;
+ * results are identical to the FP64 path (both are exact).  Inside
+ * pldl_factor, products below 2^26 flops and those that detect the first
+ * nonzero row of their result stay on FP64.  Returns -2 for another value.
+ */
+int pldl_set_path(pldl_ctx *ctx, int32_t path);
 
 /* ---------------- measurement ---------------- */
 

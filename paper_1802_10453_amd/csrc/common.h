@@ -84,4 +84,15 @@ void launch_gemm(hipStream_t s, const Field& F, int64_t m, int64_t n, double* C,
                  const GemmSeg* segs, int nseg, bool lower_c, bool b_upper, int32_t* nzrow = nullptr,
                  int32_t nzoff = 0);
 
+// The same product on the INT8 matrix cores with residues split into signed
+// bytes (gemm_i8.hip).  ws (ws_bytes) receives the limb planes; returns false,
+// having queued nothing, when the workspace is too small or a K exceeds the
+// INT32 accumulation bound (the caller then uses launch_gemm).
+int i8_limbs(uint32_t p);
+size_t i8_workspace_bytes(uint32_t p, int64_t m, int64_t n, const GemmSeg* segs, int nseg);
+bool launch_gemm_i8(hipStream_t s, const Field& F, int64_t m, int64_t n, double* C, int64_t ldc, const GemmSeg* segs,
+                    int nseg, bool lower_c, bool b_upper, int8_t* ws, size_t ws_bytes);
+// Products below this many flops stay on FP64 inside a factorization.
+constexpr double I8_MIN_FLOPS = 67108864.0;
+
 }  // namespace pldl

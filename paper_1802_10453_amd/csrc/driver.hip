@@ -178,6 +178,29 @@ struct Workspace {
 };
 
 // ---------------------------------------------------------------------------
+// Limb planes of the INT8-split products (grown on demand; see gemm_i8.hip).
+struct I8Space {
+    int8_t* p = nullptr;
+    size_t cap = 0;
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    void ensure(size_t bytes, hipStream_t st) {
+        if (bytes <= cap) return;
+        HIPCHK(hipStreamSynchronize(st));   // the old planes may still be read
+        release();
+        size_t want = std::max(bytes, cap + cap / 2);
+        if (hipMalloc((void**)&p, want) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            throw Err(PLDL_ENOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
+        }
+        cap = want;
+    }
+};
+
 struct Engine {
     hipStream_t st;
     Field F;
@@ -187,6 +210,9 @@ struct Engine {
     double* W;
     Prof* prof;
     const uint32_t* itab = nullptr;  // x -> x^{-1} mod p table (device), or NULL
+    int path = PLDL_PATH_F64;         // products on FP64 or INT8-split matrix cores
+    I8Space* i8 = nullptr;
+    double i8_min_flops = 0.0;        // smaller products stay on FP64 (split passes would dominate)
     Engine(Workspace& w, hipStream_t s, uint32_t p, int64_t n_, int t, Prof* pr)
         : st(s), F(make_field(p)), n(n_), ld(std::max<int64_t>(n_, 1)), t_leaf(t), ws(w), W(w.W), prof(pr) {}
 
@@ -215,8 +241,18 @@ struct Engine {
         if (s0.k > 0 && s1.k > 0) REQUIRE((s0.A.cs == 1) == (s1.A.cs == 1) && (s0.B.cs == 1) == (s1.B.cs == 1));
         double kk = (double)std::max<int64_t>(s0.k, 0) + (double)std::max<int64_t>(s1.k, 0);
         double outs = lower ? (double)m * (double)(m + 1) / 2.0 : (double)m * (double)nn;
-        prof->begin(st, PLDL_CLASS_GEMM, 2.0 * outs * kk);
-        launch_gemm(st, F, m, nn, C, ld, segs, 2, lower, b_upper);
+        mm(C, ld, m, nn, segs, 2, lower, b_upper, nullptr, 0, 2.0 * outs * kk);
+    }
+    // one product on the selected matrix cores (INT8 split needs no first-nonzero detection)
+    void mm(double* C, int64_t ldc, int64_t m, int64_t nn, const GemmSeg* segs, int nseg, bool lower, bool b_upper,
+            int32_t* nzrow, int32_t nzoff, double flops) {
+        prof->begin(st, PLDL_CLASS_GEMM, flops);
+        bool done = false;
+        if (path == PLDL_PATH_I8 && !nzrow && flops >= i8_min_flops) {
+            i8->ensure(i8_workspace_bytes((uint32_t)F.ip, m, nn, segs, nseg), st);
+            done = launch_gemm_i8(st, F, m, nn, C, ldc, segs, nseg, lower, b_upper, i8->p, i8->cap);
+        }
+        if (!done) launch_gemm(st, F, m, nn, C, ldc, segs, nseg, lower, b_upper, nzrow, nzoff);
         prof->end(st);
     }
 
@@ -276,9 +312,7 @@ struct Engine {
     }
     void gemm_ld(double* C, int64_t ldc, int64_t m, int64_t nn, GemmSeg s0, int32_t* nzrow = nullptr, int32_t nzoff = 0) {
         if (m <= 0 || nn <= 0 || s0.k <= 0) return;
-        prof->begin(st, PLDL_CLASS_GEMM, 2.0 * (double)m * (double)nn * (double)s0.k);
-        launch_gemm(st, F, m, nn, C, ldc, &s0, 1, false, false, nzrow, nzoff);
-        prof->end(st);
+        mm(C, ldc, m, nn, &s0, 1, false, false, nzrow, nzoff, 2.0 * (double)m * (double)nn * (double)s0.k);
     }
 
     // ---- base case (Section 5) ------------------------------------------------
@@ -531,6 +565,14 @@ struct pldl_ctx {
     std::string err;
     uint32_t* itab = nullptr;  // inverse table of modulus itab_p
     uint32_t itab_p = 0;
+    int path = PLDL_PATH_F64;  // matrix cores of the products (pldl_set_path)
+    I8Space i8;
+    // an Engine on this context's workspace, products on `path`
+    void setup(Engine& E, int pth, double i8_min) {
+        E.path = pth;
+        E.i8 = &i8;
+        E.i8_min_flops = i8_min;
+    }
     // table x -> x^{-1} mod p, built on the device the first time p is used
     const uint32_t* inv_table(uint32_t p, hipStream_t st) {
         if (itab_p == p && itab) return itab;
@@ -592,6 +634,7 @@ int pldl_destroy(pldl_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     ctx->ws.release();
+    ctx->i8.release();
     if (ctx->itab) (void)hipFree(ctx->itab);
     delete ctx;
     return PLDL_OK;
@@ -613,7 +656,8 @@ int pldl_factor(pldl_ctx* ctx, uint32_t p, int64_t n, void* A, int64_t lda, int3
     if (!rank) return fail(ctx, -10, "rank is NULL");
     pldl_opts o{PLDL_PATH_AUTO, 0, 0, 1};
     if (opts) o = *opts;
-    if (o.path != PLDL_PATH_AUTO && o.path != PLDL_PATH_F64) return fail(ctx, -11, "unknown path");
+    if (o.path != PLDL_PATH_AUTO && o.path != PLDL_PATH_F64 && o.path != PLDL_PATH_I8)
+        return fail(ctx, -11, "unknown path");
     if (o.threshold < 0 || o.threshold > 128) return fail(ctx, -11, "threshold must be in [0, 128]");
     int t = o.threshold ? o.threshold : 128;
     if (n == 0) { *rank = 0; return PLDL_OK; }
@@ -621,6 +665,7 @@ int pldl_factor(pldl_ctx* ctx, uint32_t p, int64_t n, void* A, int64_t lda, int3
     return guarded(ctx, [&]() {
         ctx->ws.ensure(n);
         Engine E(ctx->ws, st, p, n, t, &ctx->prof);
+        ctx->setup(E, o.path == PLDL_PATH_AUTO ? ctx->path : o.path, I8_MIN_FLOPS);
         E.itab = ctx->inv_table(p, st);
         Prof* prof = &ctx->prof;
         Workspace& ws = ctx->ws;
@@ -671,14 +716,12 @@ int pldl_gemm(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, int64_t k, const 
     if (lower_only && m != n) return fail(ctx, -14, "lower_only needs m == n");
     hipStream_t st = as_stream(stream);
     return guarded(ctx, [&]() {
-        Field F = make_field(p);
         GemmSeg s{transA ? MatV{(double*)A, 1, lda} : MatV{(double*)A, lda, 1},
                   transB ? MatV{(double*)B, 1, ldb} : MatV{(double*)B, ldb, 1}, k};
-        Prof* prof = &ctx->prof;
+        Engine E(ctx->ws, st, p, 0, 128, &ctx->prof);
+        ctx->setup(E, ctx->path, 0.0);
         double outs = lower_only ? (double)m * (double)(m + 1) / 2.0 : (double)m * (double)n;
-        prof->begin(st, PLDL_CLASS_GEMM, 2.0 * outs * (double)k);
-        launch_gemm(st, F, m, n, C, ldc, &s, 1, lower_only != 0, false);
-        prof->end(st);
+        if (m > 0 && n > 0 && k > 0) E.mm(C, ldc, m, n, &s, 1, lower_only != 0, false, nullptr, 0, 2.0 * outs * (double)k);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
     });
@@ -699,6 +742,7 @@ int pldl_trsm(pldl_ctx* ctx, uint32_t p, int32_t lower, int64_t m, int64_t n, co
     return guarded(ctx, [&]() {
         ctx->ws.ensure(1);
         Engine E(ctx->ws, st, p, 0, 128, &ctx->prof);
+        ctx->setup(E, ctx->path, 0.0);
         if (lower) E.trsm_ll(MatV{B, ldb, 1}, m, n, MatV{(double*)T, ldt, 1});
         else E.trsm_ru(MatV{B, ldb, 1}, m, n, MatV{(double*)T, ldt, 1});
         HIPCHK(hipGetLastError());
@@ -734,9 +778,9 @@ int pldl_syrdk(pldl_ctx* ctx, uint32_t p, int64_t n, int64_t k, const double* A,
             s1 = GemmSeg{MatV{BD, k, 1}, MatV{(double*)A, 1, lda}, k};
         }
         GemmSeg segs[2] = {s0, s1};
-        prof->begin(st, PLDL_CLASS_GEMM, 2.0 * (double)n * (double)(n + 1) / 2.0 * (double)(B ? 2 * k : k));
-        launch_gemm(st, F, n, n, C, ldc, segs, 2, true, false);
-        prof->end(st);
+        Engine E(ctx->ws, st, p, 0, 128, &ctx->prof);
+        ctx->setup(E, ctx->path, 0.0);
+        E.mm(C, ldc, n, n, segs, 2, true, false, nullptr, 0, 2.0 * (double)n * (double)(n + 1) / 2.0 * (double)(B ? 2 * k : k));
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
     });
@@ -760,6 +804,7 @@ int pldl_trss(pldl_ctx* ctx, uint32_t p, int64_t n, const double* U, int64_t ldu
         int64_t N2 = 2 * n;
         ctx->ws.ensure(N2);
         Engine E(ctx->ws, st, p, N2, 128, &ctx->prof);
+        ctx->setup(E, ctx->path, 0.0);
         Prof* prof = &ctx->prof;
         Workspace& ws = ctx->ws;
         HIPCHK(hipMemsetAsync(ws.info, 0, sizeof(int32_t) * 4, st));
@@ -800,6 +845,7 @@ int pldl_plduq(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, double* Y, int64
         }
         ctx->ws.ensure(std::max(m, n));
         Engine E(ctx->ws, st, p, std::max(m, n), 128, &ctx->prof);
+        ctx->setup(E, ctx->path, 0.0);
         E.itab = ctx->inv_table(p, st);
         Prof* prof = &ctx->prof;
         Workspace& ws = ctx->ws;
@@ -815,6 +861,13 @@ int pldl_plduq(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, double* Y, int64
         HIPCHK(hipStreamSynchronize(st));
         *rank = r;
     });
+}
+
+int pldl_set_path(pldl_ctx* ctx, int32_t path) {
+    if (!ctx) return -1;
+    if (path != PLDL_PATH_F64 && path != PLDL_PATH_I8) return fail(ctx, -2, "path must be PLDL_PATH_F64 or PLDL_PATH_I8");
+    ctx->path = path;
+    return PLDL_OK;
 }
 
 int pldl_profile(pldl_ctx* ctx, int32_t mode, pldl_stats* out) {

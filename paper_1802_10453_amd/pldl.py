@@ -23,7 +23,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 _vp, _i64, _i32, _u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32
 
 PLDL_U32, PLDL_F64 = 0, 1
-PLDL_PATH_AUTO, PLDL_PATH_F64 = 0, 1
+PLDL_PATH_AUTO, PLDL_PATH_F64, PLDL_PATH_I8 = 0, 1, 2
 ERRORS = {1: "PLDL_ERANGE", 2: "PLDL_EUNSUPPORTED_P", 3: "PLDL_EHIP", 4: "PLDL_ENOMEM", 5: "PLDL_EINTERNAL"}
 
 
@@ -55,12 +55,13 @@ _lib.pldl_syrdk.argtypes = [_vp, _u32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _v
 _lib.pldl_trss.argtypes = [_vp, _u32, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]
 _lib.pldl_plduq.argtypes = [_vp, _u32, _i64, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(_i64), _vp]
 _lib.pldl_profile.argtypes = [_vp, _i32, ctypes.POINTER(pldl_stats)]
+_lib.pldl_set_path.argtypes = [_vp, _i32]
 for _f in ("pldl_create", "pldl_destroy", "pldl_factor", "pldl_gemm", "pldl_trsm", "pldl_syrdk", "pldl_trss",
-           "pldl_plduq", "pldl_profile"):
+           "pldl_plduq", "pldl_profile", "pldl_set_path"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("pldl_create", "pldl_destroy", "pldl_last_error", "pldl_factor", "pldl_gemm", "pldl_trsm",
-            "pldl_syrdk", "pldl_trss", "pldl_plduq", "pldl_profile")
+            "pldl_syrdk", "pldl_trss", "pldl_plduq", "pldl_profile", "pldl_set_path")
 
 
 class PldlError(RuntimeError):
@@ -112,8 +113,12 @@ class Context:
         return _lib.pldl_last_error(self._h).decode()
 
     # ------------------------------------------------------------------ pldl_factor
+    def set_path(self, path: int):
+        """pldl_set_path: PLDL_PATH_F64 or PLDL_PATH_I8 for the products of later calls."""
+        self._check(_lib.pldl_set_path(self._h, int(path)))
+
     def factor(self, A: torch.Tensor, p: int, threshold: int = 0, standard_form: bool = False,
-               check_range: bool = True):
+               check_range: bool = True, path: int = PLDL_PATH_AUTO):
         """Factor the symmetric A (lower triangle; int32 holding uint32 residues, or float64)
         in place.  Returns dict(perm, rpm, e, rank)."""
         n = A.shape[0]
@@ -128,7 +133,7 @@ class Context:
         perm = torch.zeros(max(n, 1), dtype=torch.int32, device=A.device)
         rpm = torch.zeros(max(n, 1), dtype=torch.int32, device=A.device)
         rank = _i64(0)
-        o = pldl_opts(PLDL_PATH_AUTO, int(threshold), int(bool(standard_form)), int(bool(check_range)))
+        o = pldl_opts(int(path), int(threshold), int(bool(standard_form)), int(bool(check_range)))
         rc = _lib.pldl_factor(self._h, int(p), n, _ptr(A), _ld(A) if n else 1, dt, _ptr(e), _ptr(perm), _ptr(rpm),
                               ctypes.byref(rank), ctypes.byref(o), _stream())
         self._check(rc)
