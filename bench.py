@@ -21,13 +21,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+PEAK_INT8_TOPS = 5000.0   # MI355X dense INT8 matrix peak
 PEAK_HBM_GBS = 8000.0
 METRIC = "effective mod-p GOPS (n\u00b2r-normalized), exact"
-# HBM traffic of the GEMM kernel per launch, from two rocprofv3 --pmc passes (FETCH_SIZE,
+# HBM traffic of the product kernel per launch, from two rocprofv3 --pmc passes (FETCH_SIZE,
 # WRITE_SIZE) scaled by a plain copy of known size; valid only for the kernel sources it
 # was measured on (their SHA-256 is recorded beside the figure).
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm.n16384_p8388593_rank12288.traffic.txt")
-GEMM_SOURCES = ("paper_1802_10453_amd/csrc/gemm.hip", "paper_1802_10453_amd/csrc/common.h")
+PRODUCT = {
+    "f64": dict(kernel="k_gemm", cls="gemm", sources=("paper_1802_10453_amd/csrc/gemm.hip",
+                                                      "paper_1802_10453_amd/csrc/common.h")),
+    "i8": dict(kernel="k_gemm_i8", cls="gemm_i8", sources=("paper_1802_10453_amd/csrc/gemm_i8.hip",
+                                                           "paper_1802_10453_amd/csrc/common.h")),
+}
 
 
 def log(*a):
@@ -56,25 +61,27 @@ def cpu_baseline(workload_p):
                 sample=f"oracle search on n={n} p={p} rank={r} random-RPM input (same generator), {dt:.2f} s")
 
 
-def gemm_source_hash():
+def source_hash(sources):
     h = hashlib.sha256()
-    for rel in GEMM_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic(workload):
-    """Bytes per k_gemm launch from the committed counter summary, or None when it is
-    missing, was taken on another workload, or the kernel sources changed since."""
+def measured_traffic(path, workload, n, p, r):
+    """Bytes per product-kernel launch from the committed counter summary, or None when
+    it is missing, was taken on another workload, or the kernel sources changed since."""
+    pr = PRODUCT[path]
+    fn = os.path.join(ROOT, "profiles", f"{pr['kernel']}.n{n}_p{p}_rank{r}.traffic.txt")
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as f:
+        with open(fn) as f:
             for line in f:
                 if "=" in line and not line.startswith("#"):
                     k, v = line.split("=", 1)
                     kv[k.strip()] = v.strip()
-        if kv.get("workload") != workload or kv.get("gemm_sources_sha256") != gemm_source_hash():
+        if kv.get("workload") != workload or kv.get("sources_sha256") != source_hash(pr["sources"]):
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -88,6 +95,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4"])
     ap.add_argument("--threshold", type=int, default=0)
+    ap.add_argument("--path", default="f64", choices=["f64", "i8"],
+                    help="matrix cores of the products: FP64 with delayed reduction, or INT8 with residues "
+                         "split into signed bytes")
     ap.add_argument("--no-profile", action="store_true", help="time without per-launch events (no roofline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -113,6 +123,7 @@ def main():
     nrun = args.warmup + args.steps + (0 if args.no_profile else 1)
     copies = [A0.clone() for _ in range(nrun)]
     ctx = pldl.Context(0)
+    ctx.set_path(pldl.PLDL_PATH_I8 if args.path == "i8" else pldl.PLDL_PATH_F64)
     out = None
     for w in range(args.warmup):
         out = ctx.factor(copies[w], p, threshold=args.threshold)
@@ -153,19 +164,30 @@ def main():
     value = eff_ops(n, r) / (ms / 1e3) / 1e9
     roofline = None
     if stats is not None:
-        g = stats["gemm"]
-        achieved = g["flops"] / (g["ms"] / 1e3) / 1e12 if g["ms"] > 0 else 0.0
-        roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                        frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=measured_traffic(cfg["name"]),
-                        kernel="k_gemm (FP64 MFMA mod-p product)",
-                        avg_launch_ms=round(g["ms"] / max(g["launches"], 1), 4))
+        pr = PRODUCT[args.path]
+        g = stats[pr["cls"]]
+        traffic = measured_traffic(args.path, cfg["name"], n, p, r)
+        if args.path == "f64":
+            achieved = g["flops"] / (g["ms"] / 1e3) / 1e12 if g["ms"] > 0 else 0.0
+            roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                            frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=traffic,
+                            kernel="k_gemm (FP64 MFMA mod-p product)")
+        else:
+            achieved = g["ops8"] / (g["ms"] / 1e3) / 1e12 if g["ms"] > 0 else 0.0
+            roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=PEAK_INT8_TOPS, unit="TOP/s",
+                            frac=round(achieved / PEAK_INT8_TOPS, 4), traffic=traffic,
+                            kernel="k_gemm_i8 (INT8 MFMA on signed-byte limbs)",
+                            modp_tflops=round(g["flops"] / (g["ms"] / 1e3) / 1e12, 3) if g["ms"] > 0 else 0.0)
+        roofline["launches"] = g["launches"]
+        roofline["avg_launch_ms"] = round(g["ms"] / max(g["launches"], 1), 4)
     if full is not None:
         tot_ms = sum(v["ms"] for k2, v in full.items() if k2 != "host_sync")
         log("[bench] per-class GPU time of one extra step with every launch event-timed (ms; the events "
             "themselves add queue time):")
         for k2, v in full.items():
             log(f"    {k2:11s} launches {v['launches']:8.0f}  ms {v['ms']:9.3f}"
-                + (f"  {v['flops'] / v['ms'] / 1e9:8.2f} TFLOP/s" if v["flops"] and v["ms"] else "")
+                + (f"  {v['flops'] / v['ms'] / 1e9:8.2f} mod-p TFLOP/s" if v["flops"] and v["ms"] else "")
+                + (f"  {v['ops8'] / v['ms'] / 1e9:8.2f} INT8 TOP/s" if v["ops8"] and v["ms"] else "")
                 + (f"  {v['bytes'] / v['ms'] / 1e6:8.1f} GB/s" if v["bytes"] and v["ms"] else ""))
         log(f"    sum of kernel time {tot_ms:.3f} ms; timed steps {ms:.3f} ms/step")
     cpu = None
@@ -176,9 +198,10 @@ def main():
         "metric": METRIC,
         "value": round(value, 2), "unit": "GOPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": "f64" if args.path == "f64" else "i8", "data": "synthetic",
         "config": {"workload": cfg["name"], "n": n, "p": p, "rank": r, "threshold": args.threshold or 128,
-                   "path": "fp64-mfma", "input": "uint32 residues in HBM"},
+                   "path": "fp64-mfma" if args.path == "f64" else "int8-split-mfma",
+                   "input": "uint32 residues in HBM"},
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

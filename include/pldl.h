@@ -92,6 +92,38 @@ int pldl_factor(pldl_ctx *ctx, uint32_t p, int64_t n, void *A, int64_t lda, int3
                 void *e, int32_t *perm, int32_t *rpm, int64_t *rank, const pldl_opts *opts,
                 void *stream);
 
+/*
+ * pldl_factor_batched -- `batch` independent factorizations (each as
+ * pldl_factor, order n_b <= 512) in one persistent launch: workgroups take
+ * matrices from a device counter, so uneven orders and ranks balance by
+ * themselves.  Each matrix is factored by the base-case elimination of
+ * Section 5 (rows in increasing order, lexicographically first nonzero of the
+ * Schur-complement row as pivot, 1x1 / 2x2 blocks, relaxed 2x2 blocks in
+ * characteristic 2, zero rows set aside): perm is that elimination's
+ * canonical order, and rpm is the rank profile matrix (Theorem 1).
+ *
+ *  n, lda, rank   device int64[batch]: order, leading dimension, rank out.
+ *  A, e           device arrays of batch device pointers (dtype `dtype`): the
+ *                 matrices (lower triangle in, L / diag(D) out, as pldl_factor)
+ *                 and their e vectors (n_b entries each).
+ *  perm, rpm      device arrays of batch device pointers to int32[n_b].
+ *  status         device int32[batch]: 0, PLDL_ERANGE (an entry >= p, when
+ *                 opts->check_range), or -3 (n_b outside [0, 512], lda_b < n_b
+ *                 or a NULL pointer); outputs of a failed matrix are undefined.
+ *  opts           may be NULL; threshold and path are ignored; standard_form
+ *                 must be 0 (-13).
+ * The call is asynchronous (no host synchronisation: read rank and status
+ * after synchronising `stream`) and launches two kernels, so it can be
+ * captured in a HIP graph.  The first call on a context allocates its
+ * workspace (two workgroup slots per compute unit, 2 MiB each) and the inverse
+ * table of p: make that first call outside a capture.  Per-matrix pointers are
+ * trusted (the host cannot check device arrays without synchronising).
+ */
+int pldl_factor_batched(pldl_ctx *ctx, uint32_t p, int64_t batch, const int64_t *n, void *const *A,
+                        const int64_t *lda, int32_t dtype, void *const *e, int32_t *const *perm,
+                        int32_t *const *rpm, int64_t *rank, int32_t *status, const pldl_opts *opts,
+                        void *stream);
+
 /* ---------------- building blocks (Section 3), FP64 residues ---------------- */
 
 /*
@@ -165,8 +197,8 @@ int pldl_set_path(pldl_ctx *ctx, int32_t path);
 
 /* Per-kernel-class totals collected with HIP events recorded around every
  * launch the library makes on the caller's stream while profiling is on. */
-#define PLDL_NCLASS 8
-#define PLDL_CLASS_GEMM 0        /* mod-p MFMA products (GEMM/TRMM/SYRDK/SYRD2K)   */
+#define PLDL_NCLASS 9
+#define PLDL_CLASS_GEMM 0        /* mod-p FP64 MFMA products (GEMM/TRMM/SYRDK/SYRD2K) */
 #define PLDL_CLASS_TRSM_LEAF 1   /* triangular-solve leaves                         */
 #define PLDL_CLASS_BASE_CASE 2   /* base case of Section 5                          */
 #define PLDL_CLASS_PLDUQ_LEAF 3  /* PLDUQ tile leaves                               */
@@ -174,10 +206,13 @@ int pldl_set_path(pldl_ctx *ctx, int32_t path);
 #define PLDL_CLASS_PERM 5        /* symmetric permutations / assembly moves          */
 #define PLDL_CLASS_OTHER 6       /* scaling, bookkeeping, input/output kernels      */
 #define PLDL_CLASS_HOST_SYNC 7   /* host waits for a rank (launches = count, ms = wall) */
+#define PLDL_CLASS_GEMM_I8 8     /* mod-p INT8-split MFMA products (limb split: OTHER) */
 typedef struct {
     int64_t launches;  /* number of launches (or synchronisations)               */
-    double flops;      /* algorithmic FP64 flops (2 per multiply-add), class 0     */
+    double flops;      /* algorithmic mod-p flops (2 per multiply-add), classes 0, 8 */
     double bytes;      /* algorithmic HBM bytes (read + write), class 5            */
+    double ops8;       /* class 8: INT8 MFMA operations (L^2 byte products per
+                          mod-p product, 2 per multiply-add)                        */
     double ms;         /* summed GPU duration of the launches (event-timed)        */
 } pldl_kstat;
 typedef struct {
@@ -186,8 +221,8 @@ typedef struct {
 
 /*
  * Profiling control.  mode 1: reset the totals and start recording every
- * class; mode 3: reset and record the GEMM class only (two events per GEMM
- * launch, the other launches untouched: the light mode a timed run uses);
+ * class; mode 3: reset and record the two product classes only (two events per
+ * product launch, the other launches untouched: the light mode a timed run uses);
  * mode 0: stop recording; mode 2: leave the state unchanged.  In every mode
  * `out` (host, may be NULL) receives the totals gathered so far.  Recording
  * adds two events per recorded launch (a few microseconds of queue time each);

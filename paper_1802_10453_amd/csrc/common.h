@@ -85,13 +85,32 @@ void launch_gemm(hipStream_t s, const Field& F, int64_t m, int64_t n, double* C,
                  int32_t nzoff = 0);
 
 // The same product on the INT8 matrix cores with residues split into signed
-// bytes (gemm_i8.hip).  ws (ws_bytes) receives the limb planes; returns false,
-// having queued nothing, when the workspace is too small or a K exceeds the
-// INT32 accumulation bound (the caller then uses launch_gemm).
+// bytes (gemm_i8.hip), in two launches: i8_prepare writes the operands' limb
+// planes into ws (ws_bytes) and fills `out`; it returns false, having queued
+// nothing, when the workspace is too small or a K exceeds the INT32
+// accumulation bound (the caller then uses launch_gemm).  i8_run is the product.
+struct I8Product {
+    int64_t m = 0, n = 0;
+    int L = 0;
+    const int8_t* A[2] = {nullptr, nullptr};
+    const int8_t* B[2] = {nullptr, nullptr};
+    int64_t Kp[2] = {0, 0};
+};
 int i8_limbs(uint32_t p);
 size_t i8_workspace_bytes(uint32_t p, int64_t m, int64_t n, const GemmSeg* segs, int nseg);
-bool launch_gemm_i8(hipStream_t s, const Field& F, int64_t m, int64_t n, double* C, int64_t ldc, const GemmSeg* segs,
-                    int nseg, bool lower_c, bool b_upper, int8_t* ws, size_t ws_bytes);
+bool i8_prepare(hipStream_t s, const Field& F, int64_t m, int64_t n, const GemmSeg* segs, int nseg, bool b_upper,
+                int8_t* ws, size_t ws_bytes, I8Product* out);
+void i8_run(hipStream_t s, const Field& F, const I8Product& pr, double* C, int64_t ldc, bool lower_c);
+// Batched factorizations (batched.hip): one persistent launch, one workgroup
+// per matrix at a time (slots workgroups, each with a private slot of
+// batched_slot_bytes() in ws); queue is a device counter the launch resets.
+int batched_nb_max();
+size_t batched_slot_bytes();
+void launch_factor_batched(hipStream_t s, const Field& F, const uint32_t* itab, int64_t batch, const int64_t* n,
+                           void* const* A, const int64_t* lda, int32_t dtype, void* const* e, int32_t* const* perm,
+                           int32_t* const* rpm, int64_t* rank, int32_t* status, int check_range, double* ws,
+                           int slots, int32_t* queue);
+
 // Products below this many flops stay on FP64 inside a factorization.
 constexpr double I8_MIN_FLOPS = 67108864.0;
 

@@ -63,14 +63,14 @@ static inline unsigned nblk(int64_t x, int b = 256) { return (unsigned)((x + b -
 // Profiling: HIP events around each launch, harvested at host synchronisations.
 struct Prof {
     bool on = false;
-    uint32_t mask = 0xFFu;   // classes recorded while on
+    uint32_t mask = 0x1FFu;  // classes recorded while on
     pldl_stats tot{};
-    struct Rec { hipEvent_t a, b; int cls; double flops, bytes; };
+    struct Rec { hipEvent_t a, b; int cls; double flops, bytes, ops8; };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
     hipEvent_t open_a = nullptr;
     int open_cls = -1;
-    double open_f = 0.0, open_b = 0.0;
+    double open_f = 0.0, open_b = 0.0, open_o = 0.0;
     hipEvent_t ev() {
         if (pool.empty()) {
             hipEvent_t e;
@@ -81,17 +81,17 @@ struct Prof {
         pool.pop_back();
         return e;
     }
-    void begin(hipStream_t st, int c, double flops = 0.0, double bytes = 0.0) {
+    void begin(hipStream_t st, int c, double flops = 0.0, double bytes = 0.0, double ops8 = 0.0) {
         if (!on || !((mask >> c) & 1u)) return;
         open_a = ev();
         HIPCHK(hipEventRecord(open_a, st));
-        open_cls = c; open_f = flops; open_b = bytes;
+        open_cls = c; open_f = flops; open_b = bytes; open_o = ops8;
     }
     void end(hipStream_t st) {
         if (!on || open_cls < 0) return;
         hipEvent_t b = ev();
         HIPCHK(hipEventRecord(b, st));
-        recs.push_back(Rec{open_a, b, open_cls, open_f, open_b});
+        recs.push_back(Rec{open_a, b, open_cls, open_f, open_b, open_o});
         open_cls = -1;
     }
     void harvest() {
@@ -100,7 +100,7 @@ struct Prof {
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
             pldl_kstat& k = tot.cls[r.cls];
-            k.launches += 1; k.flops += r.flops; k.bytes += r.bytes; k.ms += ms;
+            k.launches += 1; k.flops += r.flops; k.bytes += r.bytes; k.ops8 += r.ops8; k.ms += ms;
             pool.push_back(r.a); pool.push_back(r.b);
         }
         recs.clear();
@@ -244,15 +244,25 @@ struct Engine {
         mm(C, ld, m, nn, segs, 2, lower, b_upper, nullptr, 0, 2.0 * outs * kk);
     }
     // one product on the selected matrix cores (INT8 split needs no first-nonzero detection)
+    // (the limb split is timed as class OTHER, the INT8 product as class GEMM)
     void mm(double* C, int64_t ldc, int64_t m, int64_t nn, const GemmSeg* segs, int nseg, bool lower, bool b_upper,
             int32_t* nzrow, int32_t nzoff, double flops) {
-        prof->begin(st, PLDL_CLASS_GEMM, flops);
-        bool done = false;
         if (path == PLDL_PATH_I8 && !nzrow && flops >= i8_min_flops) {
             i8->ensure(i8_workspace_bytes((uint32_t)F.ip, m, nn, segs, nseg), st);
-            done = launch_gemm_i8(st, F, m, nn, C, ldc, segs, nseg, lower, b_upper, i8->p, i8->cap);
+            I8Product pr;
+            prof->begin(st, PLDL_CLASS_OTHER);
+            const bool ok = i8_prepare(st, F, m, nn, segs, nseg, b_upper, i8->p, i8->cap, &pr);
+            prof->end(st);
+            if (ok) {
+                const int L = pr.L;
+                prof->begin(st, PLDL_CLASS_GEMM_I8, flops, 0.0, flops * (double)(L * L));
+                i8_run(st, F, pr, C, ldc, lower);
+                prof->end(st);
+                return;
+            }
         }
-        if (!done) launch_gemm(st, F, m, nn, C, ldc, segs, nseg, lower, b_upper, nzrow, nzoff);
+        prof->begin(st, PLDL_CLASS_GEMM, flops);
+        launch_gemm(st, F, m, nn, C, ldc, segs, nseg, lower, b_upper, nzrow, nzoff);
         prof->end(st);
     }
 
@@ -567,6 +577,9 @@ struct pldl_ctx {
     uint32_t itab_p = 0;
     int path = PLDL_PATH_F64;  // matrix cores of the products (pldl_set_path)
     I8Space i8;
+    double* bws = nullptr;     // batched factorizations: one slot per persistent workgroup
+    int bslots = 0;
+    int32_t* bqueue = nullptr;
     // an Engine on this context's workspace, products on `path`
     void setup(Engine& E, int pth, double i8_min) {
         E.path = pth;
@@ -635,6 +648,8 @@ int pldl_destroy(pldl_ctx* ctx) {
     (void)hipDeviceSynchronize();
     ctx->ws.release();
     ctx->i8.release();
+    if (ctx->bws) (void)hipFree(ctx->bws);
+    if (ctx->bqueue) (void)hipFree(ctx->bqueue);
     if (ctx->itab) (void)hipFree(ctx->itab);
     delete ctx;
     return PLDL_OK;
@@ -863,6 +878,50 @@ int pldl_plduq(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, double* Y, int64
     });
 }
 
+int pldl_factor_batched(pldl_ctx* ctx, uint32_t p, int64_t batch, const int64_t* n, void* const* A, const int64_t* lda,
+                        int32_t dtype, void* const* e, int32_t* const* perm, int32_t* const* rpm, int64_t* rank,
+                        int32_t* status, const pldl_opts* opts, void* stream) {
+    if (!ctx) return -1;
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (batch < 0 || batch > ((int64_t)1 << 30)) return fail(ctx, -3, "batch out of range");
+    if (batch > 0 && !n) return fail(ctx, -4, "n is NULL");
+    if (batch > 0 && !A) return fail(ctx, -5, "A is NULL");
+    if (batch > 0 && !lda) return fail(ctx, -6, "lda is NULL");
+    if (dtype != PLDL_U32 && dtype != PLDL_F64) return fail(ctx, -7, "unknown dtype");
+    if (batch > 0 && !e) return fail(ctx, -8, "e is NULL");
+    if (batch > 0 && !perm) return fail(ctx, -9, "perm is NULL");
+    if (batch > 0 && !rpm) return fail(ctx, -10, "rpm is NULL");
+    if (batch > 0 && !rank) return fail(ctx, -11, "rank is NULL");
+    if (batch > 0 && !status) return fail(ctx, -12, "status is NULL");
+    pldl_opts o{PLDL_PATH_AUTO, 0, 0, 1};
+    if (opts) o = *opts;
+    if (o.standard_form) return fail(ctx, -13, "standard_form is not available in batched mode");
+    if (batch == 0) return PLDL_OK;
+    hipStream_t st = as_stream(stream);
+    return guarded(ctx, [&]() {
+        if (!ctx->bws) {
+            hipDeviceProp_t prop;
+            HIPCHK(hipGetDeviceProperties(&prop, ctx->device));
+            const int slots = std::max(1, 2 * prop.multiProcessorCount);
+            if (hipMalloc((void**)&ctx->bws, (size_t)slots * batched_slot_bytes()) != hipSuccess ||
+                hipMalloc((void**)&ctx->bqueue, 256) != hipSuccess) {
+                (void)hipGetLastError();
+                if (ctx->bws) (void)hipFree(ctx->bws);
+                ctx->bws = nullptr;
+                throw Err(PLDL_ENOMEM, "batched workspace allocation failed");
+            }
+            ctx->bslots = slots;
+        }
+        const uint32_t* itab = ctx->inv_table(p, st);
+        Field F = make_field(p);
+        ctx->prof.begin(st, PLDL_CLASS_BASE_CASE);
+        launch_factor_batched(st, F, itab, batch, n, A, lda, dtype, e, perm, rpm, rank, status, o.check_range,
+                              ctx->bws, ctx->bslots, ctx->bqueue);
+        ctx->prof.end(st);
+        HIPCHK(hipGetLastError());
+    });
+}
+
 int pldl_set_path(pldl_ctx* ctx, int32_t path) {
     if (!ctx) return -1;
     if (path != PLDL_PATH_F64 && path != PLDL_PATH_I8) return fail(ctx, -2, "path must be PLDL_PATH_F64 or PLDL_PATH_I8");
@@ -878,7 +937,7 @@ int pldl_profile(pldl_ctx* ctx, int32_t mode, pldl_stats* out) {
         if (mode == 1 || mode == 3) {
             ctx->prof.tot = pldl_stats{};
             ctx->prof.on = true;
-            ctx->prof.mask = (mode == 1) ? 0xFFu : (1u << PLDL_CLASS_GEMM);
+            ctx->prof.mask = (mode == 1) ? 0x1FFu : ((1u << PLDL_CLASS_GEMM) | (1u << PLDL_CLASS_GEMM_I8));
         }
         if (mode == 0) ctx->prof.on = false;
         if (out) *out = ctx->prof.tot;

@@ -230,24 +230,19 @@ size_t i8_workspace_bytes(uint32_t p, int64_t m, int64_t n, const GemmSeg* segs,
     return b;
 }
 
-bool launch_gemm_i8(hipStream_t s, const Field& F, int64_t m, int64_t n, double* C, int64_t ldc, const GemmSeg* segs,
-                    int nseg, bool lower_c, bool b_upper, int8_t* ws, size_t ws_bytes) {
-    if (m <= 0 || n <= 0) return true;
+bool i8_prepare(hipStream_t s, const Field& F, int64_t m, int64_t n, const GemmSeg* segs, int nseg, bool b_upper,
+                int8_t* ws, size_t ws_bytes, I8Product* out) {
     const uint32_t p = (uint32_t)F.ip;
     const int L = i8_limbs(p);
     if (i8_workspace_bytes(p, m, n, segs, nseg) > ws_bytes) return false;
-    I8Args g{};
-    g.m = m; g.n = n; g.C = C; g.ldc = ldc; g.F = F;
-    g.tiles_n = (int)((n + 63) / 64);
-    double w = 1.0;
-    for (int sidx = 0; sidx < 5; ++sidx) { g.w[sidx] = w; w = std::fmod(w * 256.0, (double)p); }
+    for (int i = 0; i < nseg && i < 2; ++i)
+        if (segs[i].k > 32768) return false;   // INT32 accumulation bound
+    *out = I8Product{};
+    out->m = m; out->n = n; out->L = L;
     int8_t* cur = ws;
-    bool any = false;
     for (int i = 0; i < 2; ++i) {
-        g.A[i] = nullptr; g.B[i] = nullptr; g.Kp[i] = 0;
         if (i >= nseg || segs[i].k <= 0) continue;
         const int64_t K = segs[i].k, Kp = (K + 63) / 64 * 64;
-        if (K > 32768) return false;   // INT32 accumulation bound
         int8_t* ap = cur;
         int8_t* bp = ap + (size_t)L * m * Kp;
         cur = bp + (size_t)L * n * Kp;
@@ -258,14 +253,23 @@ bool launch_gemm_i8(hipStream_t s, const Field& F, int64_t m, int64_t n, double*
         if (L == 1) { split_launch<1>(s, F, segs[i].A, m, K, Kp, false, ap); split_launch<1>(s, F, bt, n, K, Kp, mask, bp); }
         if (L == 2) { split_launch<2>(s, F, segs[i].A, m, K, Kp, false, ap); split_launch<2>(s, F, bt, n, K, Kp, mask, bp); }
         if (L == 3) { split_launch<3>(s, F, segs[i].A, m, K, Kp, false, ap); split_launch<3>(s, F, bt, n, K, Kp, mask, bp); }
-        g.A[i] = ap; g.B[i] = bp; g.Kp[i] = Kp;
-        any = true;
+        out->A[i] = ap; out->B[i] = bp; out->Kp[i] = Kp;
     }
-    if (!any) return true;
-    if (L == 1) gemm_launch<1>(s, g, lower_c);
-    if (L == 2) gemm_launch<2>(s, g, lower_c);
-    if (L == 3) gemm_launch<3>(s, g, lower_c);
     return true;
+}
+
+void i8_run(hipStream_t s, const Field& F, const I8Product& pr, double* C, int64_t ldc, bool lower_c) {
+    if (pr.m <= 0 || pr.n <= 0 || (pr.Kp[0] <= 0 && pr.Kp[1] <= 0)) return;
+    const uint32_t p = (uint32_t)F.ip;
+    I8Args g{};
+    g.m = pr.m; g.n = pr.n; g.C = C; g.ldc = ldc; g.F = F;
+    g.tiles_n = (int)((pr.n + 63) / 64);
+    double w = 1.0;
+    for (int sidx = 0; sidx < 5; ++sidx) { g.w[sidx] = w; w = std::fmod(w * 256.0, (double)p); }
+    for (int i = 0; i < 2; ++i) { g.A[i] = pr.A[i]; g.B[i] = pr.B[i]; g.Kp[i] = pr.Kp[i]; }
+    if (pr.L == 1) gemm_launch<1>(s, g, lower_c);
+    if (pr.L == 2) gemm_launch<2>(s, g, lower_c);
+    if (pr.L == 3) gemm_launch<3>(s, g, lower_c);
 }
 
 }  // namespace pldl

@@ -27,16 +27,16 @@ PLDL_PATH_AUTO, PLDL_PATH_F64, PLDL_PATH_I8 = 0, 1, 2
 ERRORS = {1: "PLDL_ERANGE", 2: "PLDL_EUNSUPPORTED_P", 3: "PLDL_EHIP", 4: "PLDL_ENOMEM", 5: "PLDL_EINTERNAL"}
 
 
-CLASS_NAMES = ("gemm", "trsm_leaf", "base_case", "plduq_leaf", "trss_leaf", "perm", "other", "host_sync")
+CLASS_NAMES = ("gemm", "trsm_leaf", "base_case", "plduq_leaf", "trss_leaf", "perm", "other", "host_sync", "gemm_i8")
 
 
 class pldl_kstat(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
-                ("ms", ctypes.c_double)]
+                ("ops8", ctypes.c_double), ("ms", ctypes.c_double)]
 
 
 class pldl_stats(ctypes.Structure):
-    _fields_ = [("cls", pldl_kstat * 8)]
+    _fields_ = [("cls", pldl_kstat * len(CLASS_NAMES))]
 
 
 class pldl_opts(ctypes.Structure):
@@ -56,12 +56,14 @@ _lib.pldl_trss.argtypes = [_vp, _u32, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp
 _lib.pldl_plduq.argtypes = [_vp, _u32, _i64, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(_i64), _vp]
 _lib.pldl_profile.argtypes = [_vp, _i32, ctypes.POINTER(pldl_stats)]
 _lib.pldl_set_path.argtypes = [_vp, _i32]
+_lib.pldl_factor_batched.argtypes = [_vp, _u32, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
+                                     ctypes.POINTER(pldl_opts), _vp]
 for _f in ("pldl_create", "pldl_destroy", "pldl_factor", "pldl_gemm", "pldl_trsm", "pldl_syrdk", "pldl_trss",
-           "pldl_plduq", "pldl_profile", "pldl_set_path"):
+           "pldl_plduq", "pldl_profile", "pldl_set_path", "pldl_factor_batched"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("pldl_create", "pldl_destroy", "pldl_last_error", "pldl_factor", "pldl_gemm", "pldl_trsm",
-            "pldl_syrdk", "pldl_trss", "pldl_plduq", "pldl_profile", "pldl_set_path")
+            "pldl_syrdk", "pldl_trss", "pldl_plduq", "pldl_profile", "pldl_set_path", "pldl_factor_batched")
 
 
 class PldlError(RuntimeError):
@@ -139,6 +141,35 @@ class Context:
         self._check(rc)
         return dict(perm=perm[:n], rpm=rpm[:n], e=e[:n], rank=int(rank.value))
 
+    def batched_args(self, mats):
+        """Device argument arrays of pldl_factor_batched for a list of square tensors (int32
+        holding uint32 residues, or float64), all of one dtype.  Returns a dict that keeps
+        every array alive; pass it to factor_batched (also inside a graph capture)."""
+        dev = mats[0].device
+        dt = mats[0].dtype
+        assert all(m.dtype == dt and m.device == dev and m.dim() == 2 and m.shape[0] == m.shape[1] for m in mats)
+        ns = [m.shape[0] for m in mats]
+        e = [torch.zeros(max(k, 1), dtype=dt, device=dev) for k in ns]
+        perm = [torch.zeros(max(k, 1), dtype=torch.int32, device=dev) for k in ns]
+        rpm = [torch.zeros(max(k, 1), dtype=torch.int32, device=dev) for k in ns]
+        ptrs = lambda ts: torch.tensor([t.data_ptr() for t in ts], dtype=torch.int64, device=dev)
+        return dict(mats=mats, dtype=PLDL_U32 if dt == torch.int32 else PLDL_F64,
+                    n=torch.tensor(ns, dtype=torch.int64, device=dev),
+                    lda=torch.tensor([max(_ld(m), 1) for m in mats], dtype=torch.int64, device=dev),
+                    A=ptrs(mats), e=e, e_p=ptrs(e), perm=perm, perm_p=ptrs(perm), rpm=rpm, rpm_p=ptrs(rpm),
+                    rank=torch.zeros(len(mats), dtype=torch.int64, device=dev),
+                    status=torch.zeros(len(mats), dtype=torch.int32, device=dev))
+
+    def factor_batched(self, p: int, args: dict, check_range: bool = True):
+        """pldl_factor_batched on the arrays of batched_args (asynchronous)."""
+        o = pldl_opts(PLDL_PATH_AUTO, 0, 0, int(bool(check_range)))
+        rc = _lib.pldl_factor_batched(self._h, int(p), len(args["mats"]), _ptr(args["n"]), _ptr(args["A"]),
+                                      _ptr(args["lda"]), args["dtype"], _ptr(args["e_p"]), _ptr(args["perm_p"]),
+                                      _ptr(args["rpm_p"]), _ptr(args["rank"]), _ptr(args["status"]),
+                                      ctypes.byref(o), _stream())
+        self._check(rc)
+        return args
+
     def factor_raw(self, p, n, A_ptr, lda, dtype, e_ptr, perm_ptr, rpm_ptr, opts=None):
         """Direct call with raw device pointers (used by the boundary tests)."""
         rank = _i64(0)
@@ -152,7 +183,7 @@ class Context:
         st = pldl_stats()
         self._check(_lib.pldl_profile(self._h, int(mode), ctypes.byref(st)))
         return {name: dict(launches=st.cls[i].launches, flops=st.cls[i].flops, bytes=st.cls[i].bytes,
-                           ms=st.cls[i].ms) for i, name in enumerate(CLASS_NAMES)}
+                           ops8=st.cls[i].ops8, ms=st.cls[i].ms) for i, name in enumerate(CLASS_NAMES)}
 
     # ------------------------------------------------------------------ building blocks
     def gemm(self, p, C, A, B, transA=False, transB=False, lower_only=False):
