@@ -221,12 +221,13 @@ typedef struct {
 
 /*
  * Profiling control.  mode 1: reset the totals and start recording every
- * class; mode 3: reset and record the two product classes only (two events per
- * product launch, the other launches untouched: the light mode a timed run uses);
- * mode 0: stop recording; mode 2: leave the state unchanged.  In every mode
- * `out` (host, may be NULL) receives the totals gathered so far.  Recording
- * adds two events per recorded launch (a few microseconds of queue time each);
- * it never changes results.
+ * class with two HIP events around each launch (a few microseconds of queue
+ * time each); mode 3: reset and record the two product classes only, timed
+ * inside the kernels (first workgroup start to last workgroup end on the
+ * device wall clock; no events, no extra launches: the light mode a timed run
+ * uses); mode 0: stop recording; mode 2: leave the state unchanged.  In every
+ * mode `out` (host, may be NULL) receives the totals gathered so far.
+ * Recording never changes results.
  */
 int pldl_profile(pldl_ctx *ctx, int32_t mode, pldl_stats *out);
 

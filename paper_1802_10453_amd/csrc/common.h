@@ -72,6 +72,26 @@ struct MatV {
 };
 
 // ---------------------------------------------------------------------------
+// In-kernel launch timing: the earliest workgroup start and the latest
+// workgroup end of one launch on the device's constant-rate wall clock, folded
+// into a slot with atomicMin / atomicMax (null pointers: off).  It adds no
+// launch and no queue marker, so a timed run is not perturbed by it.
+struct Stamp {
+    unsigned long long* t0 = nullptr;
+    unsigned long long* t1 = nullptr;
+};
+__device__ __forceinline__ void stamp_begin(const Stamp& s) {
+    if (s.t0 && threadIdx.x == 0) atomicMin(s.t0, (unsigned long long)wall_clock64());
+}
+// every thread of the workgroup calls it (one barrier when timing is on)
+__device__ __forceinline__ void stamp_end(const Stamp& s) {
+    if (s.t1) {
+        __syncthreads();
+        if (threadIdx.x == 0) atomicMax(s.t1, (unsigned long long)wall_clock64());
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers (host functions; each validates nothing -- callers check bounds).
 struct GemmSeg {
     MatV A, B;     // A: m x k, B: k x n
@@ -82,7 +102,7 @@ struct GemmSeg {
 //   nzrow (optional): atomicMin(nzrow, nzoff + index of the first row of C holding a nonzero result)
 void launch_gemm(hipStream_t s, const Field& F, int64_t m, int64_t n, double* C, int64_t ldc,
                  const GemmSeg* segs, int nseg, bool lower_c, bool b_upper, int32_t* nzrow = nullptr,
-                 int32_t nzoff = 0);
+                 int32_t nzoff = 0, Stamp stamp = Stamp{});
 
 // The same product on the INT8 matrix cores with residues split into signed
 // bytes (gemm_i8.hip), in two launches: i8_prepare writes the operands' limb
@@ -100,7 +120,8 @@ int i8_limbs(uint32_t p);
 size_t i8_workspace_bytes(uint32_t p, int64_t m, int64_t n, const GemmSeg* segs, int nseg);
 bool i8_prepare(hipStream_t s, const Field& F, int64_t m, int64_t n, const GemmSeg* segs, int nseg, bool b_upper,
                 int8_t* ws, size_t ws_bytes, I8Product* out);
-void i8_run(hipStream_t s, const Field& F, const I8Product& pr, double* C, int64_t ldc, bool lower_c);
+void i8_run(hipStream_t s, const Field& F, const I8Product& pr, double* C, int64_t ldc, bool lower_c,
+            Stamp stamp = Stamp{});
 // Batched factorizations (batched.hip): one persistent launch, one workgroup
 // per matrix at a time (slots workgroups, each with a private slot of
 // batched_slot_bytes() in ws); queue is a device counter the launch resets.

@@ -63,6 +63,7 @@ static inline unsigned nblk(int64_t x, int b = 256) { return (unsigned)((x + b -
 // Profiling: HIP events around each launch, harvested at host synchronisations.
 struct Prof {
     bool on = false;
+    bool light = false;      // product launches timed in-kernel, nothing else recorded
     uint32_t mask = 0x1FFu;  // classes recorded while on
     pldl_stats tot{};
     struct Rec { hipEvent_t a, b; int cls; double flops, bytes, ops8; };
@@ -71,6 +72,15 @@ struct Prof {
     hipEvent_t open_a = nullptr;
     int open_cls = -1;
     double open_f = 0.0, open_b = 0.0, open_o = 0.0;
+    // in-kernel stamps: NTS slots of (start, end) wall-clock ticks
+    static constexpr int NTS = 16384;
+    unsigned long long *ts0 = nullptr, *ts1 = nullptr;
+    int nts = 0;
+    double wall_khz = 0.0;
+    hipStream_t ts_stream = nullptr;
+    struct TRec { int cls; double flops, ops8; };
+    std::vector<TRec> trecs;
+
     hipEvent_t ev() {
         if (pool.empty()) {
             hipEvent_t e;
@@ -81,11 +91,15 @@ struct Prof {
         pool.pop_back();
         return e;
     }
-    void begin(hipStream_t st, int c, double flops = 0.0, double bytes = 0.0, double ops8 = 0.0) {
-        if (!on || !((mask >> c) & 1u)) return;
+    // Starts recording one launch of class c; in light mode returns the stamp slot
+    // the launch must fill (product classes only) instead of recording events.
+    Stamp begin(hipStream_t st, int c, double flops = 0.0, double bytes = 0.0, double ops8 = 0.0) {
+        if (!on || !((mask >> c) & 1u)) return Stamp{};
+        if (light) return stamp(st, c, flops, ops8);
         open_a = ev();
         HIPCHK(hipEventRecord(open_a, st));
         open_cls = c; open_f = flops; open_b = bytes; open_o = ops8;
+        return Stamp{};
     }
     void end(hipStream_t st) {
         if (!on || open_cls < 0) return;
@@ -93,6 +107,43 @@ struct Prof {
         HIPCHK(hipEventRecord(b, st));
         recs.push_back(Rec{open_a, b, open_cls, open_f, open_b, open_o});
         open_cls = -1;
+    }
+    Stamp stamp(hipStream_t st, int c, double flops, double ops8) {
+        if (!ts0) {
+            int dev = 0, khz = 0;
+            HIPCHK(hipGetDevice(&dev));
+            HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+            wall_khz = (double)khz;
+            HIPCHK(hipMalloc((void**)&ts0, NTS * sizeof(unsigned long long)));
+            HIPCHK(hipMalloc((void**)&ts1, NTS * sizeof(unsigned long long)));
+            reset_stamps(st);
+        }
+        if (nts == NTS || (ts_stream && ts_stream != st)) harvest_stamps();
+        ts_stream = st;
+        trecs.push_back(TRec{c, flops, ops8});
+        const int k = nts++;
+        return Stamp{ts0 + k, ts1 + k};
+    }
+    void reset_stamps(hipStream_t st) {
+        HIPCHK(hipMemsetAsync(ts0, 0xFF, NTS * sizeof(unsigned long long), st));
+        HIPCHK(hipMemsetAsync(ts1, 0x00, NTS * sizeof(unsigned long long), st));
+    }
+    // waits for the stamped launches, folds them into the totals, re-arms the slots
+    void harvest_stamps() {
+        if (nts == 0) return;
+        HIPCHK(hipStreamSynchronize(ts_stream));
+        std::vector<unsigned long long> a(nts), b(nts);
+        HIPCHK(hipMemcpy(a.data(), ts0, nts * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(b.data(), ts1, nts * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+        for (int k = 0; k < nts; ++k) {
+            pldl_kstat& s = tot.cls[trecs[k].cls];
+            s.launches += 1; s.flops += trecs[k].flops; s.ops8 += trecs[k].ops8;
+            if (b[k] > a[k]) s.ms += (double)(b[k] - a[k]) / wall_khz;
+        }
+        nts = 0;
+        trecs.clear();
+        reset_stamps(ts_stream);
+        HIPCHK(hipStreamSynchronize(ts_stream));
     }
     void harvest() {
         for (Rec& r : recs) {
@@ -104,15 +155,18 @@ struct Prof {
             pool.push_back(r.a); pool.push_back(r.b);
         }
         recs.clear();
+        harvest_stamps();
     }
     void host_wait(double ms) {
-        if (!on || !((mask >> PLDL_CLASS_HOST_SYNC) & 1u)) return;
+        if (!on || light || !((mask >> PLDL_CLASS_HOST_SYNC) & 1u)) return;
         tot.cls[PLDL_CLASS_HOST_SYNC].launches += 1;
         tot.cls[PLDL_CLASS_HOST_SYNC].ms += ms;
     }
     ~Prof() {
         for (Rec& r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        if (ts0) (void)hipFree(ts0);
+        if (ts1) (void)hipFree(ts1);
     }
 };
 
@@ -129,11 +183,13 @@ struct Workspace {
     int64_t cap = -1;
     double *W = nullptr, *tmp1 = nullptr, *tmp2 = nullptr, *dd = nullptr, *de = nullptr;
     double *xinv = nullptr, *yy = nullptr, *dvec = nullptr;
+    double* tinv = nullptr;   // N_k = I - T_kk^{-1} of the diagonal blocks of a TRSM (64 x 64 each)
+    int64_t tinv_rows = 0;    // tinv holds tinv_rows / 64 blocks
     int8_t* kind = nullptr;
     int32_t *orig = nullptr, *sig = nullptr, *tmpo = nullptr, *info = nullptr, *pidx = nullptr;
     int32_t* hinfo = nullptr;  // pinned host mirror of info (rank, error flag, sigma)
     void release() {
-        double* ds[] = {W, tmp1, tmp2, dd, de, xinv, yy, dvec};
+        double* ds[] = {W, tmp1, tmp2, dd, de, xinv, yy, dvec, tinv};
         for (double* p : ds) if (p) (void)hipFree(p);
         if (kind) (void)hipFree(kind);
         int32_t* is[] = {orig, sig, tmpo, info, pidx};
@@ -161,6 +217,8 @@ struct Workspace {
         dalloc(&xinv, m + 1);
         dalloc(&yy, m + 1);
         dalloc(&dvec, 2 * m + 2);
+        dalloc(&tinv, 64 * (size_t)(m + 64));
+        tinv_rows = m + 64;
         if (hipMalloc((void**)&kind, m + 1) != hipSuccess) { release(); throw Err(PLDL_ENOMEM, "alloc"); }
         int32_t** ips[] = {&orig, &sig, &tmpo, &pidx};
         for (int32_t** p : ips)
@@ -227,7 +285,7 @@ struct Engine {
         auto t0 = std::chrono::steady_clock::now();
         HIPCHK(hipMemcpyAsync(ws.hinfo, ws.info, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        if (prof->on) {
+        if (prof->on && !prof->light) {   // (stamps are collected when their slots run out, or at pldl_profile)
             prof->host_wait(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
             prof->harvest();
         }
@@ -255,14 +313,14 @@ struct Engine {
             prof->end(st);
             if (ok) {
                 const int L = pr.L;
-                prof->begin(st, PLDL_CLASS_GEMM_I8, flops, 0.0, flops * (double)(L * L));
-                i8_run(st, F, pr, C, ldc, lower);
+                const Stamp sp = prof->begin(st, PLDL_CLASS_GEMM_I8, flops, 0.0, flops * (double)(L * L));
+                i8_run(st, F, pr, C, ldc, lower, sp);
                 prof->end(st);
                 return;
             }
         }
-        prof->begin(st, PLDL_CLASS_GEMM, flops);
-        launch_gemm(st, F, m, nn, C, ldc, segs, nseg, lower, b_upper, nzrow, nzoff);
+        const Stamp sp = prof->begin(st, PLDL_CLASS_GEMM, flops);
+        launch_gemm(st, F, m, nn, C, ldc, segs, nseg, lower, b_upper, nzrow, nzoff, sp);
         prof->end(st);
     }
 
@@ -296,29 +354,62 @@ struct Engine {
     }
 
     // ---- TRSM (Section 3) ---------------------------------------------------
+    // Recursive halving (on multiples of 64) down to 64-blocks; the blocks'
+    // inverses come from one launch, and each leaf is one product applied in
+    // place: the output has a single column tile (right solve, r <= 64) or a
+    // single row tile (left solve), so every workgroup of k_gemm reads all of
+    // its operand rows (columns) before it writes them, and the INT8 path reads
+    // the limb planes it made beforehand.
     // B (m x r, row-major) <- B T^{-1}, T unit upper (view)
     void trsm_ru(MatV B, int64_t m, int64_t r, MatV T) {
         if (m <= 0 || r <= 0) return;
-        if (r <= 64) {
-            LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trsm_ru_leaf, dim3(nblk(m, 64)), dim3(64), 0, st, B.p, B.rs, m, (int)r, T, F);
+        const int64_t nb = (r + 63) / 64;
+        ensure_tinv(nb * 64);
+        LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trinv_blocks, dim3((unsigned)nb), dim3(64), 0, st, T, r, 0, ws.tinv, F);
+        trsm_ru_rec(B, m, r, T, ws.tinv);
+    }
+    void trsm_ru_rec(MatV B, int64_t m, int64_t r, MatV T, double* Nb) {
+        if (r <= 64) {   // B <- B - B N
+            gemm_ld(B.p, B.rs, m, r, GemmSeg{MatV{B.p, B.rs, 1}, MatV{Nb, 64, 1}, r});
             return;
         }
         int64_t r1 = std::max<int64_t>(64, (r / 2) / 64 * 64);
-        trsm_ru(B, m, r1, T);
+        trsm_ru_rec(B, m, r1, T, Nb);
         gemm_ld(B.p + r1, B.rs, m, r - r1, GemmSeg{MatV{B.p, B.rs, 1}, MatV{T.p + r1 * T.cs, T.rs, T.cs}, r1});
-        trsm_ru(MatV{B.p + r1, B.rs, 1}, m, r - r1, MatV{T.p + r1 * (T.rs + T.cs), T.rs, T.cs});
+        trsm_ru_rec(MatV{B.p + r1, B.rs, 1}, m, r - r1, MatV{T.p + r1 * (T.rs + T.cs), T.rs, T.cs}, Nb + (r1 / 64) * 4096);
     }
     // B (r x ncols, row-major) <- T^{-1} B, T unit lower (view)
     void trsm_ll(MatV B, int64_t r, int64_t ncols, MatV T) {
         if (r <= 0 || ncols <= 0) return;
-        if (r <= 64) {
-            LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trsm_ll_leaf, dim3(nblk(ncols, 64)), dim3(64), 0, st, B.p, B.rs, ncols, (int)r, T, F);
+        const int64_t nb = (r + 63) / 64;
+        ensure_tinv(nb * 64);
+        LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trinv_blocks, dim3((unsigned)nb), dim3(64), 0, st, T, r, 1, ws.tinv, F);
+        trsm_ll_rec(B, r, ncols, T, ws.tinv);
+    }
+    void trsm_ll_rec(MatV B, int64_t r, int64_t ncols, MatV T, double* Nb) {
+        if (r <= 64) {   // B <- B - N B
+            gemm_ld(B.p, B.rs, r, ncols, GemmSeg{MatV{Nb, 64, 1}, MatV{B.p, B.rs, 1}, r});
             return;
         }
         int64_t r1 = std::max<int64_t>(64, (r / 2) / 64 * 64);
-        trsm_ll(B, r1, ncols, T);
+        trsm_ll_rec(B, r1, ncols, T, Nb);
         gemm_ld(B.p + r1 * B.rs, B.rs, r - r1, ncols, GemmSeg{MatV{T.p + r1 * T.rs, T.rs, T.cs}, MatV{B.p, B.rs, 1}, r1});
-        trsm_ll(MatV{B.p + r1 * B.rs, B.rs, 1}, r - r1, ncols, MatV{T.p + r1 * (T.rs + T.cs), T.rs, T.cs});
+        trsm_ll_rec(MatV{B.p + r1 * B.rs, B.rs, 1}, r - r1, ncols, MatV{T.p + r1 * (T.rs + T.cs), T.rs, T.cs},
+                    Nb + (r1 / 64) * 4096);
+    }
+    // the block inverses of a triangle of order `rows` (grown after the queued work is done)
+    void ensure_tinv(int64_t rows) {
+        if (rows <= ws.tinv_rows) return;
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipFree(ws.tinv));
+        ws.tinv = nullptr;
+        ws.tinv_rows = 0;
+        if (hipMalloc((void**)&ws.tinv, 64 * (size_t)rows * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            ws.tinv = nullptr;
+            throw Err(PLDL_ENOMEM, "device allocation of the triangle inverses failed");
+        }
+        ws.tinv_rows = rows;
     }
     void gemm_ld(double* C, int64_t ldc, int64_t m, int64_t nn, GemmSeg s0, int32_t* nzrow = nullptr, int32_t nzoff = 0) {
         if (m <= 0 || nn <= 0 || s0.k <= 0) return;
@@ -616,7 +707,7 @@ int guarded(pldl_ctx* ctx, Fn&& fn) {
     try {
         HIPCHK(hipSetDevice(ctx->device));
         fn();
-        if (ctx->prof.on || !ctx->prof.recs.empty()) ctx->prof.harvest();
+        if ((ctx->prof.on && !ctx->prof.light) || !ctx->prof.recs.empty()) ctx->prof.harvest();
         ctx->err.clear();
         return PLDL_OK;
     } catch (const Err& e) {
@@ -937,6 +1028,7 @@ int pldl_profile(pldl_ctx* ctx, int32_t mode, pldl_stats* out) {
         if (mode == 1 || mode == 3) {
             ctx->prof.tot = pldl_stats{};
             ctx->prof.on = true;
+            ctx->prof.light = (mode == 3);
             ctx->prof.mask = (mode == 1) ? 0x1FFu : ((1u << PLDL_CLASS_GEMM) | (1u << PLDL_CLASS_GEMM_I8));
         }
         if (mode == 0) ctx->prof.on = false;

@@ -32,6 +32,7 @@ struct GemmKArgs {
     int tiles_n;
     int32_t* nzrow;   // optional: atomicMin(nzrow, nzoff + first row of C with a nonzero result)
     int32_t nzoff;
+    Stamp stamp;
 };
 
 template <int BM, int BN, bool A_ROW, bool B_ROW, bool LOWER_C, bool B_UPPER>
@@ -42,6 +43,7 @@ __global__ __launch_bounds__(NT) void k_gemm(GemmKArgs g) {
     __shared__ double As[2][BK][BM + PAD];
     __shared__ double Bs[2][BK][BN + PAD];
     const Field F = g.F;
+    stamp_begin(g.stamp);
     const int bid = blockIdx.x;
     int ti, tj;
     if (LOWER_C) {
@@ -176,6 +178,7 @@ __global__ __launch_bounds__(NT) void k_gemm(GemmKArgs g) {
             if (v < (1 << 30)) atomicMin(g.nzrow, g.nzoff + v);
         }
     }
+    stamp_end(g.stamp);
 }
 
 template <int BM, int BN, bool AR, bool BR>
@@ -202,11 +205,13 @@ void dispatch_layout(hipStream_t s, GemmKArgs& g, bool ar, bool br, bool lower_c
 }  // namespace
 
 void launch_gemm(hipStream_t s, const Field& F, int64_t m, int64_t n, double* C, int64_t ldc,
-                 const GemmSeg* segs, int nseg, bool lower_c, bool b_upper, int32_t* nzrow, int32_t nzoff) {
+                 const GemmSeg* segs, int nseg, bool lower_c, bool b_upper, int32_t* nzrow, int32_t nzoff,
+                 Stamp stamp) {
     if (m <= 0 || n <= 0) return;
     GemmKArgs g{};
     g.m = m; g.n = n; g.C = C; g.ldc = ldc; g.F = F;
     g.nzrow = nzrow; g.nzoff = nzoff;
+    g.stamp = stamp;
     bool any = false;
     for (int i = 0; i < 2; ++i) {
         if (i < nseg && segs[i].k > 0) {

@@ -94,6 +94,7 @@ struct I8Args {
     Field F;
     double w[5];          // 256^s mod p
     int tiles_n;
+    Stamp stamp;
 };
 
 // Workgroup tile 64 x 64, four waves in a 2 x 2 grid, wave tile 32 x 32 (2 x 2
@@ -103,6 +104,7 @@ struct I8Args {
 template <int L, bool LOWER_C>
 __global__ __launch_bounds__(256) void k_gemm_i8(I8Args g) {
     constexpr int NS = 2 * L - 1;
+    stamp_begin(g.stamp);
     const int bid = blockIdx.x;
     int ti, tj;
     if (LOWER_C) {
@@ -199,6 +201,7 @@ __global__ __launch_bounds__(256) void k_gemm_i8(I8Args g) {
                     *c = fred(*c - fred(v, F), F);
                 }
             }
+    stamp_end(g.stamp);
 }
 
 template <int L>
@@ -258,12 +261,13 @@ bool i8_prepare(hipStream_t s, const Field& F, int64_t m, int64_t n, const GemmS
     return true;
 }
 
-void i8_run(hipStream_t s, const Field& F, const I8Product& pr, double* C, int64_t ldc, bool lower_c) {
+void i8_run(hipStream_t s, const Field& F, const I8Product& pr, double* C, int64_t ldc, bool lower_c, Stamp stamp) {
     if (pr.m <= 0 || pr.n <= 0 || (pr.Kp[0] <= 0 && pr.Kp[1] <= 0)) return;
     const uint32_t p = (uint32_t)F.ip;
     I8Args g{};
     g.m = pr.m; g.n = pr.n; g.C = C; g.ldc = ldc; g.F = F;
     g.tiles_n = (int)((pr.n + 63) / 64);
+    g.stamp = stamp;
     double w = 1.0;
     for (int sidx = 0; sidx < 5; ++sidx) { g.w[sidx] = w; w = std::fmod(w * 256.0, (double)p); }
     for (int i = 0; i < 2; ++i) { g.A[i] = pr.A[i]; g.B[i] = pr.B[i]; g.Kp[i] = pr.Kp[i]; }

@@ -19,9 +19,8 @@ __global__ void k_idx_gather(const int32_t* idx, int64_t a, int64_t len, const i
 __global__ void k_idx_copy(int32_t* idx, int64_t a, int64_t len, const int32_t* tmp);
 __global__ void k_zlp_sigma_total(int32_t* sig, int64_t mz, int64_t nc, int64_t rY, const int32_t* pR,
                                   const int32_t* pC);
+__global__ void k_trinv_blocks(MatV T, int64_t r, int lower, double* N, Field F);
 __global__ void k_trss_leaf(double* W, int64_t ld, int64_t s0, int64_t u0, int r, Field F);
-__global__ void k_trsm_ru_leaf(double* B, int64_t ld, int64_t m, int r, MatV T, Field F);
-__global__ void k_trsm_ll_leaf(double* B, int64_t ld, int64_t ncols, int r, MatV T, Field F);
 struct PermGeom { int64_t n, lo, hi, s, nb0, nb1, B0, B1, B2, B3; int parts; };
 __global__ void k_perm_sym(double* W, int64_t ld, PermGeom g, const int32_t* sig, int64_t rot1, double* tmp,
                            int32_t* orig, int32_t* tmpo, int dir);

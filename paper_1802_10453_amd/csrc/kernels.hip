@@ -558,81 +558,54 @@ __global__ __launch_bounds__(64) void k_trss_leaf(double* W, int64_t ld, int64_t
 }
 
 // ===========================================================================
-// Triangular solve leaves (Section 3, TRSM) with unit triangular T of order
-// r <= 64: one thread per right-hand side, its 64 unknowns in registers (fully
-// unrolled substitution, T broadcast from LDS), delayed reduction over at most
-// 63 products.
+// Triangular solves (Section 3, TRSM) through the inverses of the 64 x 64
+// diagonal blocks: over F_p an explicit inverse is exact, so every leaf of the
+// recursive TRSM becomes one matrix-core product.  Block k of the unit
+// triangular T (order r) gets N_k = I - T_kk^{-1}, row-major 64 x 64 (strict
+// lower part for a lower T, strict upper part for an upper T), so that
+// T_kk^{-1} X = X - N_k X and X T_kk^{-1} = X - X N_k.  One workgroup per
+// block; thread c solves for column c of the inverse of the lower-triangular
+// form L_k (T_kk itself, or T_kk^T for an upper T: (T^T)^{-1} = (T^{-1})^T) by
+// forward substitution in registers, with at most 63 products accumulated
+// before each entry is reduced.
 // ===========================================================================
-// B (m x r, row-major) <- B T^{-1}, T unit upper; 64 rows per workgroup of 64 threads.
-__global__ __launch_bounds__(64) void k_trsm_ru_leaf(double* B, int64_t ld, int64_t m, int r, MatV T, Field F) {
-    __shared__ double Ts[64][64];
-    __shared__ double Bs[64][65];
+__global__ __launch_bounds__(64) void k_trinv_blocks(MatV T, int64_t r, int lower, double* N, Field F) {
+    __shared__ double Ls[64][65];
     const int tid = threadIdx.x;
-    const int64_t i0 = (int64_t)blockIdx.x * 64;
-    const int rows = (int)min((int64_t)64, m - i0);
-    // T: thread tid loads column tid of T (64 independent loads in flight)
+    const int64_t o = (int64_t)blockIdx.x * 64;
+    const int rb = (int)min((int64_t)64, r - o);
     {
+        // unconditional loads (coordinates clamped into the block) so that all are in flight together
+        const int64_t c = o + min(tid, rb - 1);
         double tv[64];
 #pragma unroll
-        for (int a = 0; a < 64; ++a) tv[a] = (a < tid && tid < r) ? T.p[a * T.rs + tid * T.cs] : 0.0;
-#pragma unroll
-        for (int a = 0; a < 64; ++a) Ts[a][tid] = fcen(tv[a], F);
-    }
-    // B tile: 64 rows, each row read by consecutive threads
-#pragma unroll 4
-    for (int i = 0; i < rows; ++i) Bs[i][tid] = (tid < r) ? B[(i0 + i) * ld + tid] : 0.0;
-    __syncthreads();
-    double z[64];
-#pragma unroll
-    for (int j = 0; j < 64; ++j) z[j] = (j < r && tid < rows) ? Bs[tid][j] : 0.0;
-#pragma unroll
-    for (int j = 0; j < 64; ++j) {
-        if (j < r) {
-            const double zj = fredc(z[j], F);
-            z[j] = zj;
-#pragma unroll
-            for (int jj = j + 1; jj < 64; ++jj) z[jj] = fma(-zj, Ts[j][jj], z[jj]);
+        for (int a = 0; a < 64; ++a) {
+            const int64_t ra = o + min(a, rb - 1);
+            tv[a] = lower ? T.p[ra * T.rs + c * T.cs] : T.p[c * T.rs + ra * T.cs];
         }
-    }
 #pragma unroll
-    for (int j = 0; j < 64; ++j)
-        if (tid < rows && j < r) Bs[tid][j] = fcan(z[j], F);
-    __syncthreads();
-#pragma unroll 4
-    for (int i = 0; i < rows; ++i)
-        if (tid < r) B[(i0 + i) * ld + tid] = Bs[i][tid];
-}
-
-// B (r x ncols, row-major) <- T^{-1} B, T unit lower; one thread per column, 64 columns per workgroup.
-__global__ __launch_bounds__(64) void k_trsm_ll_leaf(double* B, int64_t ld, int64_t ncols, int r, MatV T, Field F) {
-    __shared__ double Ts[64][64];
-    const int tid = threadIdx.x;
-    const int64_t col = (int64_t)blockIdx.x * 64 + tid;
-    // T: thread tid loads column tid of T (64 independent loads in flight)
-    {
-        double tv[64];
-#pragma unroll
-        for (int a = 0; a < 64; ++a) tv[a] = (a > tid && a < r) ? T.p[a * T.rs + tid * T.cs] : 0.0;
-#pragma unroll
-        for (int a = 0; a < 64; ++a) Ts[a][tid] = fcen(tv[a], F);
+        for (int a = 0; a < 64; ++a) Ls[a][tid] = (a > tid && a < rb) ? fcen(tv[a], F) : 0.0;
     }
     __syncthreads();
-    const bool ok = col < ncols;
     double z[64];
 #pragma unroll
-    for (int i = 0; i < 64; ++i) z[i] = (i < r && ok) ? B[i * ld + col] : 0.0;
+    for (int i = 0; i < 64; ++i) z[i] = (i == tid) ? 1.0 : 0.0;
 #pragma unroll
     for (int i = 0; i < 64; ++i) {
-        if (i < r) {
+        if (i < rb) {
             const double zi = fredc(z[i], F);
             z[i] = zi;
 #pragma unroll
-            for (int ii = i + 1; ii < 64; ++ii) z[ii] = fma(-Ts[ii][i], zi, z[ii]);
+            for (int ii = i + 1; ii < 64; ++ii) z[ii] = fma(-Ls[ii][i], zi, z[ii]);
         }
     }
+    double* Nk = N + (int64_t)blockIdx.x * 4096;
 #pragma unroll
-    for (int i = 0; i < 64; ++i)
-        if (i < r && ok) B[i * ld + col] = fcan(z[i], F);
+    for (int a = 0; a < 64; ++a) {
+        const double v = (a > tid && a < rb) ? fcan(fredc(-z[a], F), F) : 0.0;
+        if (lower) Nk[a * 64 + tid] = v;
+        else Nk[tid * 64 + a] = v;
+    }
 }
 
 // ===========================================================================
