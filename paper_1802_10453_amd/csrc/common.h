@@ -63,6 +63,12 @@ constexpr int32_t NZ_NONE = 0x7F7F7F7F;
 // Most workgroups of a PLDUQ right-part update (one first-nonzero candidate each).
 constexpr int NZB_MAX = 2048;
 
+// Pivot columns of a PLDUQ slab (T row indices); a slab has at most 64 pivots.
+struct PivList {
+    int32_t col[64];
+    int32_t n;
+};
+
 // ---------------------------------------------------------------------------
 // Strided matrix view: element (i, j) at p[i*rs + j*cs].  One of the strides
 // is 1 for every view the library forms (row-major: cs = 1; column-major: rs = 1).

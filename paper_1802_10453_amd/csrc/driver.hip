@@ -187,12 +187,16 @@ struct Workspace {
     int64_t tinv_rows = 0;    // tinv holds tinv_rows / 64 blocks
     int8_t* kind = nullptr;
     int32_t *orig = nullptr, *sig = nullptr, *tmpo = nullptr, *info = nullptr, *pidx = nullptr;
+    int32_t* ipool = nullptr;          // PLDUQ: stack of index snapshots, then scratch
+    int64_t ipool_len = 0;             // ints of the stack part
+    int32_t* ipool_scratch = nullptr;  // two halves: inverse map, reorder source
+    int64_t ipool_scratch_len = 0;
     int32_t* hinfo = nullptr;  // pinned host mirror of info (rank, error flag, sigma)
     void release() {
         double* ds[] = {W, tmp1, tmp2, dd, de, xinv, yy, dvec, tinv};
         for (double* p : ds) if (p) (void)hipFree(p);
         if (kind) (void)hipFree(kind);
-        int32_t* is[] = {orig, sig, tmpo, info, pidx};
+        int32_t* is[] = {orig, sig, tmpo, info, pidx, ipool};
         for (int32_t* p : is) if (p) (void)hipFree(p);
         if (hinfo) (void)hipHostFree(hinfo);
         *this = Workspace();
@@ -227,6 +231,15 @@ struct Workspace {
                 throw Err(PLDL_ENOMEM, "alloc");
             }
         if (hipMalloc((void**)&info, (1024 + NZB_MAX) * sizeof(int32_t)) != hipSuccess) { release(); throw Err(PLDL_ENOMEM, "alloc"); }
+        // snapshot stack: 3 segments of at most m entries per row-split level (<= 11 levels
+        // for m <= 65535), then the scratch (inverse map and source, m + 64 each)
+        ipool_len = 40 * (m + 64);
+        ipool_scratch_len = 2 * (m + 64);
+        if (hipMalloc((void**)&ipool, (ipool_len + ipool_scratch_len) * sizeof(int32_t)) != hipSuccess) {
+            release();
+            throw Err(PLDL_ENOMEM, "alloc");
+        }
+        ipool_scratch = ipool + ipool_len;
         if (hipHostMalloc((void**)&hinfo, 1024 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
             release();
             throw Err(PLDL_ENOMEM, "pinned alloc");
@@ -541,94 +554,171 @@ struct Engine {
     }
 
     // ---- PLDUQ revealing the rank profile, on a compact transposed copy -------
-    // T (TR x TC, leading dimension ldT) holds Y^T: Y[i][j] = T[j][i].  Row and
-    // column permutations of Y move only T and are recorded in pR / pC (the
-    // caller applies their composition to W once).
+    // T (TR x TC, leading dimension ldT) holds Y^T: Y[i][j] = T[j][i].  pR / pC
+    // give the original row / column index at each position of Y.  A call on rows
+    // [a0, a1) and columns [c0, c1) reorders rows and columns of that submatrix
+    // only, and keeps pR[a0 .. a1) and pC[c0 .. c1) up to date; its caller
+    // carries the new orders to the other parts of the matrix that hold data
+    // (from snapshots of pR / pC taken before the call), so no step moves the
+    // whole width of Y.  The caller of the whole PLDUQ applies pC to W once.
     double* T = nullptr;
     int64_t ldT = 0, TR = 0, TC = 0;
     int32_t *pR = nullptr, *pC = nullptr;
+    int64_t ip_top = 0;   // stack pointer in ws.ipool (snapshots of pR / pC segments)
 
-    // Y columns [a, b) = rows of T;  Y rows [a, b) = columns of T
-    void t_perm(bool ycols, int64_t a, int64_t b, const int32_t* sg, int64_t rot1 = -1) {
-        const int64_t sz = b - a;
-        if (sz <= 1) return;
-        const int64_t rows = ycols ? sz : TR, cols = ycols ? TC : sz;
-        if (rows <= 0 || cols <= 0) return;
-        REQUIRE(rows + 1 <= 65535);
-        int32_t* idx = ycols ? pC : pR;
-        dim3 g(nblk(std::max(cols, sz)), (unsigned)(rows + 1));
-        prof->begin(st, PLDL_CLASS_PERM, 0.0, 16.0 * (double)rows * (double)cols);
-        hipLaunchKernelGGL(k_tperm, g, dim3(256), 0, st, T, ldT, TR, TC, ycols ? 1 : 0, a, sz, sg, rot1, ws.tmp1, idx, ws.tmpo, 0);
-        hipLaunchKernelGGL(k_tperm, g, dim3(256), 0, st, T, ldT, TR, TC, ycols ? 1 : 0, a, sz, sg, rot1, ws.tmp1, idx, ws.tmpo, 1);
+    int32_t* ipush(int64_t cnt) {
+        REQUIRE(ip_top + cnt + 64 <= ws.ipool_len);
+        int32_t* p = ws.ipool + ip_top;
+        ip_top += (cnt + 63) / 64 * 64;
+        return p;
+    }
+    int32_t* snapshot(const int32_t* src, int64_t len) {
+        int32_t* p = ipush(std::max<int64_t>(len, 1));
+        if (len > 0) HIPCHK(hipMemcpyAsync(p, src, len * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+        return p;
+    }
+    // src[q] = old position of the entry now at q, from a snapshot of an index segment
+    int32_t* reorder_src(const int32_t* snap, const int32_t* cur, int64_t len) {
+        int32_t* inv = ws.ipool_scratch;   // indexed by original index (< max(TR, TC))
+        int32_t* src = ws.ipool_scratch + ws.ipool_scratch_len / 2;
+        LAUNCH(PLDL_CLASS_OTHER, k_inv_scatter, dim3(nblk(len)), dim3(256), 0, st, snap, len, inv);
+        LAUNCH(PLDL_CLASS_OTHER, k_src_gather, dim3(nblk(len)), dim3(256), 0, st, cur, len, inv, src);
+        return src;
+    }
+    // reorder T rows [j0, j0+len) (Y columns) by src, in T columns [i0, i0+ni) (Y rows)
+    void tcolperm(int64_t j0, int64_t len, const int32_t* src, int64_t i0, int64_t ni) {
+        if (len <= 1 || ni <= 0) return;
+        REQUIRE(len <= 65535 && len * ni <= ws.cap * ws.cap);
+        dim3 g(nblk(ni), (unsigned)len);
+        prof->begin(st, PLDL_CLASS_PERM, 0.0, 16.0 * (double)len * (double)ni);
+        hipLaunchKernelGGL(k_tcolperm, g, dim3(256), 0, st, T, ldT, j0, len, src, i0, ni, ws.tmp1, 0);
+        hipLaunchKernelGGL(k_tcolperm, g, dim3(256), 0, st, T, ldT, j0, len, src, i0, ni, ws.tmp1, 1);
         prof->end(st);
     }
-    void t_perm_ycols(int64_t a, int64_t b, const int32_t* sg) { t_perm(true, a, b, sg); }
-    void t_perm_yrows(int64_t a, int64_t b, const int32_t* sg) { t_perm(false, a, b, sg); }
-    void t_rot_ycols(int64_t a, int64_t b, int64_t c) {
-        if (a == b || b == c) return;
-        t_perm(true, a, c, nullptr, b - a);
+    // reorder T columns [i0, i0+len) (Y rows) by src, within T rows [j0, j0+nj)
+    void trowperm(int64_t j0, int64_t nj, int64_t i0, int64_t len, const int32_t* src) {
+        if (len <= 1 || nj <= 0) return;
+        REQUIRE(nj <= 65535 && len * nj <= ws.cap * ws.cap);
+        dim3 g(nblk(len), (unsigned)nj);
+        prof->begin(st, PLDL_CLASS_PERM, 0.0, 16.0 * (double)len * (double)nj);
+        hipLaunchKernelGGL(k_trowperm, g, dim3(256), 0, st, T, ldT, j0, nj, i0, len, src, ws.tmp1, 0);
+        hipLaunchKernelGGL(k_trowperm, g, dim3(256), 0, st, T, ldT, j0, nj, i0, len, src, ws.tmp1, 1);
+        prof->end(st);
     }
-    void t_rot_yrows(int64_t a, int64_t b, int64_t c) {
-        if (a == b || b == c) return;
-        t_perm(false, a, c, nullptr, b - a);
+    // idx[a + q] <- idx[a + src[q]]
+    void idx_reorder(int32_t* idx, int64_t a, int64_t len, const int32_t* src) {
+        if (len <= 1) return;
+        LAUNCH(PLDL_CLASS_OTHER, k_idx_gather, dim3(nblk(len)), dim3(256), 0, st, idx, a, len, src, ws.tmpo);
+        LAUNCH(PLDL_CLASS_OTHER, k_idx_copy, dim3(nblk(len)), dim3(256), 0, st, idx, a, len, ws.tmpo);
     }
 
-    // rows [a0, a1) and columns [c0, c1) of Y.  Row slabs of <= 64 rows; within a
-    // slab the leaf finds the pivots of the first column chunk that is not zero on
-    // the slab, the rest of the columns are updated (TRSM, GEMM) and searched again.
-    // hint (device ints, may be NULL; the minimum of nhint entries): a lower bound on the first column of the
-    // slab's rows holding a nonzero, left by the update that preceded the call.
+    // rows [a0, a1) and columns [c0, c1) of Y.  Row slabs of <= 64 rows; the
+    // bottom half of a row split is updated with the top half's pivots (TRSM,
+    // GEMM) and continues on the columns the top half left.  hint (device
+    // ints, may be NULL; the minimum of nhint entries): a lower bound on the
+    // first column of these rows holding a nonzero, left by the preceding update.
     int64_t plduq_t(int64_t a0, int64_t a1, int64_t c0, int64_t c1, const int32_t* hint = nullptr, int nhint = 0) {
         const int64_t m = a1 - a0;
         if (m <= 0 || c1 <= c0) return 0;
         REQUIRE(a1 <= TC && c1 <= TR);
+        if (m <= 64) return plduq_slab(a0, a1, c0, c1, hint, nhint);
         int32_t* nzh = ws.info + 8;
-        if (m > 64) {
-            const int64_t am = a0 + std::max<int64_t>(64, (m / 2) / 64 * 64);
-            const int64_t r1 = plduq_t(a0, am, c0, c1, hint, nhint);
-            const int32_t* bhint = nullptr;
-            if (r1 > 0) {
-                const int64_t mb = a1 - am, ncr = c1 - c0 - r1;
-                // Wb^T = U_t^{-T} Y_b1^T  (U_t^T unit lower at T[c0.., a0..])
-                trsm_ll(MatV{T + c0 * ldT + am, ldT, 1}, r1, mb, MatV{T + c0 * ldT + a0, ldT, 1});
-                // Y_b2^T -= V_t^T Wb^T, recording the first column left nonzero on the bottom rows
-                if (ncr > 0) {
-                    HIPCHK(hipMemsetAsync(nzh, 0x7F, sizeof(int32_t), st));
-                    gemm_ld(T + (c0 + r1) * ldT + am, ldT, ncr, mb,
-                            GemmSeg{MatV{T + (c0 + r1) * ldT + a0, ldT, 1}, MatV{T + c0 * ldT + am, ldT, 1}, r1}, nzh,
-                            (int32_t)(c0 + r1));
-                    bhint = nzh;
-                }
-                // L_b^T = D_t^{-1} Wb^T
-                LAUNCH(PLDL_CLASS_OTHER, k_scale_pack, dim3(nblk(mb), (unsigned)r1), dim3(256), 0, st, T + c0 * ldT + am, ldT, r1, mb,
-                       T + c0 * ldT + a0, ldT, 1, itab, F);
+        const int64_t ip_save = ip_top;
+        const int64_t am = a0 + std::max<int64_t>(64, (m / 2) / 64 * 64);
+        int32_t* snapC = snapshot(pC + c0, c1 - c0);
+        const int64_t r1 = plduq_t(a0, am, c0, c1, hint, nhint);
+        const int32_t* bhint = nullptr;
+        if (r1 > 0) {
+            const int64_t mb = a1 - am, ncr = c1 - c0 - r1;
+            // the bottom rows take the top half's column order
+            tcolperm(c0, c1 - c0, reorder_src(snapC, pC + c0, c1 - c0), am, mb);
+            // Wb^T = U_t^{-T} Y_b1^T  (U_t^T unit lower at T[c0.., a0..])
+            trsm_ll(MatV{T + c0 * ldT + am, ldT, 1}, r1, mb, MatV{T + c0 * ldT + a0, ldT, 1});
+            // Y_b2^T -= V_t^T Wb^T, recording the first column left nonzero on the bottom rows
+            if (ncr > 0) {
+                HIPCHK(hipMemsetAsync(nzh, 0x7F, sizeof(int32_t), st));
+                gemm_ld(T + (c0 + r1) * ldT + am, ldT, ncr, mb,
+                        GemmSeg{MatV{T + (c0 + r1) * ldT + a0, ldT, 1}, MatV{T + c0 * ldT + am, ldT, 1}, r1}, nzh,
+                        (int32_t)(c0 + r1));
+                bhint = nzh;
             }
-            const int64_t r2 = plduq_t(am, a1, c0 + r1, c1, bhint, 1);
-            t_rot_yrows(a0 + r1, am, am + r2);
-            return r1 + r2;
+            // L_b^T = D_t^{-1} Wb^T
+            LAUNCH(PLDL_CLASS_OTHER, k_scale_pack, dim3(nblk(mb), (unsigned)r1), dim3(256), 0, st, T + c0 * ldT + am, ldT, r1, mb,
+                   T + c0 * ldT + a0, ldT, 1, itab, F);
         }
-        LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_leaf, dim3(1), dim3(1024), 0, st, T, ldT, a0, (int)m, c0, c1, F, itab, hint,
-               nhint, ws.sig, ws.sig + 64, ws.info);
-        const int32_t* h = read_info(3);
-        const int64_t r = h[0], cs = h[1], w = h[2];
-        if (r == 0) return 0;  // the slab is zero on [c0, c1)
-        t_perm_yrows(a0, a1, ws.sig);
-        t_perm_ycols(cs, cs + w, ws.sig + 64);
-        if (cs > c0) t_rot_ycols(c0, cs, cs + r);
-        const int64_t ce = cs + w;
-        int64_t r2 = 0;
-        if (ce < c1) {
-            const int64_t nr = c1 - ce;
-            // (D U_R)^T = Y_R[piv]^T L_t^{-T}, Y_R[np]^T -= (D U_R)^T M_t^T, U_R = D^{-1} (D U_R), in one
-            // pass; each workgroup leaves the first column it found nonzero on the rows below in nzb
-            int32_t* nzb = ws.info + 1024;
-            const int64_t nb = std::min<int64_t>((nr + 3) / 4, NZB_MAX);
-            LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_rupdate, dim3((unsigned)nb), dim3(256), 0, st, T, ldT, a0, (int)m, (int)r,
-                   c0, ce, nr, F, itab, (m > r) ? nzb : nullptr);
-            r2 = plduq_t(a0 + r, a1, ce, c1, (m > r) ? nzb : nullptr, (int)nb);
-            t_rot_ycols(c0 + r, ce, ce + r2);
+        int32_t* snapC2 = snapshot(pC + c0 + r1, c1 - c0 - r1);
+        int32_t* snapR2 = snapshot(pR + am, a1 - am);
+        const int64_t r2 = plduq_t(am, a1, c0 + r1, c1, bhint, 1);
+        if (r2 > 0) {
+            // the top rows take the bottom half's column order, the bottom rows' multipliers its row order
+            tcolperm(c0 + r1, c1 - c0 - r1, reorder_src(snapC2, pC + c0 + r1, c1 - c0 - r1), a0, am - a0);
+            if (r1 > 0) trowperm(c0, r1, am, a1 - am, reorder_src(snapR2, pR + am, a1 - am));
+            // pivot rows of both halves first: rotate the top non-pivots behind the bottom pivots
+            if (am - a0 > r1) {
+                const int64_t len = am + r2 - (a0 + r1);
+                int32_t* src = ws.ipool_scratch + ws.ipool_scratch_len / 2;
+                LAUNCH(PLDL_CLASS_OTHER, k_rot_src, dim3(nblk(len)), dim3(256), 0, st, len, am - a0 - r1, src);
+                trowperm(c0, c1 - c0, a0 + r1, len, src);
+                idx_reorder(pR, a0 + r1, len, src);
+            }
         }
-        return r + r2;
+        ip_top = ip_save;
+        return r1 + r2;
+    }
+
+    // A slab (<= 64 rows): leaves over 256-column chunks from left to right.  Each
+    // leaf eliminates the first chunk that is not zero on the slab's active rows
+    // (those without a pivot yet), moves its pivot rows to the front of them and
+    // writes its chunk in the new order; the update that follows carries that row
+    // order to the rest of the slab (the columns on the right, and the earlier
+    // pivot columns that hold multipliers) and eliminates the new pivots from the
+    // right part.  At the end the slab's pivot columns are moved to the front of
+    // [c0, c1), for the slab's rows.
+    int64_t plduq_slab(int64_t a0, int64_t a1, int64_t c0, int64_t c1, const int32_t* hint, int nhint) {
+        const int64_t m = a1 - a0;
+        PivList piv{};   // the slab's pivot columns, in pivot order
+        int64_t R = 0, cur = c0;
+        const int32_t* h = hint;
+        int nh = nhint;
+        int32_t* nzb = ws.info + 1024;
+        while (R < m && cur < c1) {
+            LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_leaf, dim3(1), dim3(1024), 0, st, T, ldT, a0 + R, (int)(m - R), cur, c1, F,
+                   itab, h, nh, ws.sig, ws.info, pR);
+            const int32_t* hi = read_info(16 + 64);
+            const int64_t r = hi[0], cs = hi[1], w = hi[2];
+            if (r == 0) break;   // the active rows are zero on [cur, c1)
+            REQUIRE(R + r <= 64);
+            PivList cp{};
+            for (int64_t s = 0; s < r; ++s) cp.col[s] = hi[16 + s];
+            cp.n = (int32_t)r;
+            const int64_t ce = cs + w, nr = c1 - ce, ma = m - R;
+            const int64_t items = nr + piv.n;
+            if (items > 0) {
+                const bool more = ma > r && nr > 0;
+                const int64_t nb = std::min<int64_t>((items + 3) / 4, NZB_MAX);
+                LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_rupdate, dim3((unsigned)nb), dim3(256), 0, st, T, ldT, a0 + R, (int)ma, (int)r,
+                       cp, ce, nr, F, itab, more ? nzb : nullptr, ws.sig, piv);
+                h = more ? nzb : nullptr;
+                nh = (int)nb;
+            } else {
+                h = nullptr;
+                nh = 0;
+            }
+            for (int64_t s = 0; s < r; ++s) piv.col[piv.n + s] = cp.col[s];
+            piv.n += (int32_t)r;
+            R += r;
+            cur = ce;
+        }
+        if (R > 0) {
+            PivList srt = piv;
+            std::sort(srt.col, srt.col + srt.n);
+            const int64_t len = c1 - c0;
+            int32_t* src = ws.ipool_scratch + ws.ipool_scratch_len / 2;
+            LAUNCH(PLDL_CLASS_OTHER, k_slab_colsrc, dim3(nblk(len)), dim3(256), 0, st, piv, srt, c0, len, src);
+            tcolperm(c0, len, src, a0, m);
+            idx_reorder(pC, c0, len, src);
+        }
+        return R;
     }
 
     // ---- Algorithm 1 (TRSS): C at W[s0..s0+r)^2, U[a][b] = W[s0+b][u0+a] -----

@@ -7,10 +7,18 @@ namespace pldl {
 __global__ void k_bc_leaf(double* W, int64_t ld, int64_t lo, int s, Field F, const uint32_t* itab, double* dd,
                           double* de, int32_t* sig_out, int32_t* rank_out);
 __global__ void k_plduq_leaf(double* T, int64_t ld, int64_t a0, int m, int64_t c0, int64_t c1, Field F,
-                             const uint32_t* itab, const int32_t* hint, int nhint, int32_t* rsig, int32_t* csig,
-                             int32_t* info);
-__global__ void k_plduq_rupdate(double* T, int64_t ld, int64_t a0, int m, int r, int64_t cp, int64_t ce, int64_t nr,
-                                Field F, const uint32_t* itab, int32_t* nzblk);
+                             const uint32_t* itab, const int32_t* hint, int nhint, int32_t* rsig, int32_t* info,
+                             int32_t* pR);
+__global__ void k_plduq_rupdate(double* T, int64_t ld, int64_t a0, int m, int r, PivList piv, int64_t ce, int64_t nr,
+                                Field F, const uint32_t* itab, int32_t* nzblk, const int32_t* rsig, PivList prev);
+__global__ void k_slab_colsrc(PivList ord, PivList srt, int64_t c0, int64_t len, int32_t* src);
+__global__ void k_inv_scatter(const int32_t* snap, int64_t len, int32_t* inv);
+__global__ void k_src_gather(const int32_t* cur, int64_t len, const int32_t* inv, int32_t* src);
+__global__ void k_rot_src(int64_t len, int64_t rot1, int32_t* src);
+__global__ void k_tcolperm(double* T, int64_t ld, int64_t j0, int64_t len, const int32_t* src, int64_t i0,
+                           int64_t ni, double* tmp, int phase);
+__global__ void k_trowperm(double* T, int64_t ld, int64_t j0, int64_t nj, int64_t i0, int64_t len,
+                           const int32_t* src, double* tmp, int phase);
 __global__ void k_inv_table(uint32_t* tab, Field F);
 __global__ void k_mat_gather(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t rows, int64_t cols,
                              const int32_t* rsig, int64_t roff, const int32_t* csig, int64_t coff);
@@ -24,8 +32,6 @@ __global__ void k_trss_leaf(double* W, int64_t ld, int64_t s0, int64_t u0, int r
 struct PermGeom { int64_t n, lo, hi, s, nb0, nb1, B0, B1, B2, B3; int parts; };
 __global__ void k_perm_sym(double* W, int64_t ld, PermGeom g, const int32_t* sig, int64_t rot1, double* tmp,
                            int32_t* orig, int32_t* tmpo, int dir);
-__global__ void k_tperm(double* T, int64_t ldT, int64_t R, int64_t C, int by_rows, int64_t a, int64_t sz,
-                        const int32_t* sig, int64_t rot1, double* tmp, int32_t* idx, int32_t* tmpi, int dir);
 __global__ void k_scale_pack(double* X, int64_t ld, int64_t rows, int64_t cols, const double* P, int64_t ldp,
                              int by_row, const uint32_t* itab, Field F);
 __global__ void k_sigma_rotate(int32_t* sig, int64_t len1, int64_t len2);

@@ -249,13 +249,17 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
 // thread t owns row t%64 and columns t/64 + 16k (k < 16).  Every wave runs the
 // pivot search itself (no serial thread); row, multiplier and mask vectors
 // are double buffered: three barriers per pivot.
-// Output: the LU pack of the chunk in the ORIGINAL (unpermuted) coordinates,
-// rsig (m) / csig (chunk width) and info = {rank, chunk start, chunk width}.
+// Output, in place: the LU pack of the chunk with its rows in the new order
+// (pivot rows first, in pivot order, then the others in their previous order;
+// the same reordering applied to pR[a0 .. a0+m)) and its columns in place,
+// rsig (new row -> old row, for the rest of these rows) and
+// info = {rank, chunk start, chunk width} and info[16 ..] = T rows of the r
+// pivot columns.
 // ===========================================================================
 __global__ __launch_bounds__(1024) void k_plduq_leaf(double* T, int64_t ld, int64_t a0, int m, int64_t c0,
                                                      int64_t c1, Field F, const uint32_t* itab,
                                                      const int32_t* hint, int nhint, int32_t* rsig,
-                                                     int32_t* csig, int32_t* info) {
+                                                     int32_t* info, int32_t* pR) {
     __shared__ double rowI[2][256];   // centered reduced row (0 on pivot columns)
     __shared__ double fvec[2][64];    // centered multipliers of the rows below
     __shared__ int ispc[256], cpiv[256];
@@ -395,8 +399,12 @@ __global__ __launch_bounds__(1024) void k_plduq_leaf(double* T, int64_t ld, int6
     }
     __syncthreads();
     if (tid == 0) { info[0] = r; info[1] = (int32_t)cs; info[2] = w; }
+    if (tid < r) info[16 + tid] = (int32_t)(cs + cord[tid]);   // T row of pivot tid's column
     if (tid < m) rsig[tid] = rord[tid];
-    if (tid < w) csig[tid] = cord[tid];
+    // pR follows the new row order (all old entries read before any write)
+    const int pr_old = (tid < m) ? pR[a0 + rord[tid]] : 0;
+    // the tile, already in registers, is written with its rows in the new order
+    // (columns stay in place: the slab moves its pivot columns once, at its end)
     if (row < m) {
         const int a = rposs[row];
 #pragma unroll
@@ -410,9 +418,11 @@ __global__ __launch_bounds__(1024) void k_plduq_leaf(double* T, int64_t ld, int6
             else if (bpos < a && bpos < r) out = v;                    // L / M (stored multipliers)
             else if (a < bpos && a < r) out = fmulm(v, pinvx[a], F);   // U / V
             else out = 0.0;
-            T[(cs + col) * ld + a0 + row] = out;
+            T[(cs + col) * ld + a0 + a] = out;
         }
     }
+    __syncthreads();
+    if (tid < m) pR[a0 + tid] = pr_old;
 }
 
 // ===========================================================================
@@ -421,37 +431,47 @@ __global__ __launch_bounds__(1024) void k_plduq_leaf(double* T, int64_t ld, int6
 // D^{-1}), fused into one pass over the columns to the right of the tile.  In
 // the compact transposed copy T, Y column j is T row j and the slab's rows
 // a0 .. a0+m-1 are m contiguous entries of it, so one wave takes one column
-// with lane t on slab row t.  The tile's pivot columns sit at T rows
-// cp .. cp+r-1 (pivot rows first in the slab): entry (s, t > s) of those rows
-// is the multiplier of slab row t for pivot s, entry (s, s) is D_s.  For each
-// column: u_s = y_s - sum_{s' < s} L[s][s'] u_s' (column elimination, one wave
-// shuffle per pivot), the other rows y_t -= M[t][s] u_s, then u_s <- u_s / D_s.
-// At most 64 products accumulate before the final reduction (below 2^53 for
-// p < 2^23).  With nzblk, workgroup b writes to nzblk[b] the first of its
-// columns left nonzero on rows r .. m-1 (NZ_NONE if none): the next leaf's scan
-// starts at the minimum (no atomics on one address from thousands of waves).
+// with lane t on slab row t.  The leaf reordered the rows of its tile (rsig:
+// new row -> old row); each column is gathered through rsig on load, so the
+// reordering and the update share one pass.  The tile's pivot columns sit at T
+// rows piv.col[0 .. r) (pivot rows first): entry (s, t > s) is the multiplier of
+// row t for pivot s, entry (s, s) is D_s.  For each column: u_s = y_s -
+// sum_{s' < s} L[s][s'] u_s' (column elimination, one wave shuffle per pivot),
+// the other rows y_t -= M[t][s] u_s, then u_s <- u_s / D_s.  At most 64
+// products accumulate before the final reduction (below 2^53 for p < 2^23).
+// The pivot columns of the slab's earlier tiles (prev.col) hold these rows'
+// multipliers: they are only reordered.  With nzblk, workgroup b writes to
+// nzblk[b] the first of its columns left nonzero on rows r .. m-1 (NZ_NONE if
+// none): the next leaf's scan starts at the minimum.
 // ===========================================================================
-__global__ __launch_bounds__(256) void k_plduq_rupdate(double* T, int64_t ld, int64_t a0, int m, int r, int64_t cp,
+__global__ __launch_bounds__(256) void k_plduq_rupdate(double* T, int64_t ld, int64_t a0, int m, int r, PivList piv,
                                                        int64_t ce, int64_t nr, Field F, const uint32_t* itab,
-                                                       int32_t* nzblk) {
+                                                       int32_t* nzblk, const int32_t* rsig, PivList prev) {
     __shared__ double Lc[64][64];   // Lc[s][t]: multiplier of row t > s for pivot s, 0 for t <= s
     __shared__ double dinv[64];
     __shared__ int wfirst[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int e = tid; e < r * 64; e += 256) {
         const int sp = e >> 6, t = e & 63;
-        Lc[sp][t] = (t > sp && t < m) ? fcen(T[(cp + sp) * ld + a0 + t], F) : 0.0;
+        Lc[sp][t] = (t > sp && t < m) ? fcen(T[(int64_t)piv.col[sp] * ld + a0 + t], F) : 0.0;
     }
     if (tid < r) {
-        const double d = T[(cp + tid) * ld + a0 + tid];
+        const double d = T[(int64_t)piv.col[tid] * ld + a0 + tid];
         dinv[tid] = itab ? (double)itab[(int)d] : finv(d, F);
     }
     __syncthreads();
+    const int src = (lane < m) ? rsig[lane] : 0;
     int first = NZ_NONE;
-    const int64_t stride = (int64_t)gridDim.x * 4;
-    for (int64_t jj = (int64_t)blockIdx.x * 4 + wave; jj < nr; jj += stride) {
+    const int64_t stride = (int64_t)gridDim.x * 4, items = nr + prev.n;
+    for (int64_t jj = (int64_t)blockIdx.x * 4 + wave; jj < items; jj += stride) {
+        if (jj >= nr) {   // an earlier pivot column: reorder only
+            double* col = T + (int64_t)prev.col[jj - nr] * ld + a0;
+            const double v = (lane < m) ? col[src] : 0.0;
+            if (lane < m) col[lane] = v;
+            continue;
+        }
         double* col = T + (ce + jj) * ld + a0;
-        double y = (lane < m) ? fcen(col[lane], F) : 0.0;
+        double y = (lane < m) ? fcen(col[src], F) : 0.0;
         for (int sp = 0; sp < r; ++sp) {
             const double us = fredc(__shfl(y, sp), F);
             y = (lane == sp) ? us : fma(-Lc[sp][lane], us, y);
@@ -467,6 +487,62 @@ __global__ __launch_bounds__(256) void k_plduq_rupdate(double* T, int64_t ld, in
         __syncthreads();
         if (tid == 0) nzblk[blockIdx.x] = min(min(wfirst[0], wfirst[1]), min(wfirst[2], wfirst[3]));
     }
+}
+
+// The column order of a finished PLDUQ slab on [c0, c0+len): its pivot columns
+// (T rows ord.col[], in pivot order) first, then the other positions in
+// increasing order (srt: the same columns sorted).  src[q] = old position
+// relative to c0.
+__global__ void k_slab_colsrc(PivList ord, PivList srt, int64_t c0, int64_t len, int32_t* src) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= len) return;
+    int64_t pos;
+    if (q < ord.n) {
+        pos = ord.col[q] - c0;
+    } else {
+        pos = q - ord.n;   // the pos-th position that is not a pivot column
+        for (int s = 0; s < srt.n; ++s) {
+            if (srt.col[s] - c0 <= pos) ++pos;
+            else break;
+        }
+    }
+    src[q] = (int32_t)pos;
+}
+
+// inv[snap[q]] = q (snap: a segment of an index array before a reordering)
+__global__ void k_inv_scatter(const int32_t* snap, int64_t len, int32_t* inv) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q < len) inv[snap[q]] = (int32_t)q;
+}
+// src[q] = inv[cur[q]]: the old position of the entry now at q
+__global__ void k_src_gather(const int32_t* cur, int64_t len, const int32_t* inv, int32_t* src) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q < len) src[q] = inv[cur[q]];
+}
+// src[q] of the rotation that moves the first rot1 of len positions after the others
+__global__ void k_rot_src(int64_t len, int64_t rot1, int32_t* src) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= len) return;
+    const int64_t len2 = len - rot1;
+    src[q] = (int32_t)(q < len2 ? rot1 + q : q - len2);
+}
+
+// Reorder T rows j0 .. j0+len (Y columns) by src, restricted to T columns
+// [i0, i0+ni) (Y rows): phase 0 gathers into tmp, phase 1 copies back.
+__global__ void k_tcolperm(double* T, int64_t ld, int64_t j0, int64_t len, const int32_t* src, int64_t i0,
+                           int64_t ni, double* tmp, int phase) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x, q = blockIdx.y;
+    if (i >= ni || q >= len) return;
+    if (phase == 0) tmp[q * ni + i] = T[(j0 + src[q]) * ld + i0 + i];
+    else T[(j0 + q) * ld + i0 + i] = tmp[q * ni + i];
+}
+// Reorder T columns i0 .. i0+len (Y rows) by src, within T rows [j0, j0+nj).
+__global__ void k_trowperm(double* T, int64_t ld, int64_t j0, int64_t nj, int64_t i0, int64_t len,
+                           const int32_t* src, double* tmp, int phase) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+    if (q >= len || j >= nj) return;
+    if (phase == 0) tmp[j * len + q] = T[(j0 + j) * ld + i0 + src[q]];
+    else T[(j0 + j) * ld + i0 + q] = tmp[j * len + q];
 }
 
 // inverse table: tab[x] = x^{-1} mod p (tab[0] = 0), built once per modulus
@@ -658,32 +734,6 @@ __global__ __launch_bounds__(256) void k_perm_sym(double* W, int64_t ld, PermGeo
         if (c >= s) return;
         if (dir == 0) tmpo[c] = orig[lo + sigma_at(sig, c, s, rot1)];
         else orig[lo + c] = tmpo[c];
-    }
-}
-
-// Row (by_rows = 1) or column permutation of the window [a, a+sz) of the
-// compact matrix T (R x C, leading dimension ldT), with the index map idx
-// composed alongside (idx[a+q] <- idx[a+sig[q]]).  Grid y = rows of the
-// gathered block + 1 (the extra row handles idx); dir 0 gathers, 1 scatters.
-__global__ __launch_bounds__(256) void k_tperm(double* T, int64_t ldT, int64_t R, int64_t C, int by_rows, int64_t a,
-                                              int64_t sz, const int32_t* sig, int64_t rot1, double* tmp, int32_t* idx,
-                                              int32_t* tmpi, int dir) {
-    const int64_t rows = by_rows ? sz : R, cols = by_rows ? C : sz;
-    const int64_t i = blockIdx.y, j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i == rows) {
-        if (j >= sz) return;
-        if (dir == 0) tmpi[j] = idx[a + sigma_at(sig, j, sz, rot1)];
-        else idx[a + j] = tmpi[j];
-        return;
-    }
-    if (j >= cols) return;
-    if (dir == 0) {
-        int64_t si = by_rows ? a + sigma_at(sig, i, sz, rot1) : i;
-        int64_t sj = by_rows ? j : a + sigma_at(sig, j, sz, rot1);
-        tmp[i * cols + j] = T[si * ldT + sj];
-    } else {
-        int64_t di = by_rows ? a + i : i, dj = by_rows ? j : a + j;
-        T[di * ldT + dj] = tmp[i * cols + j];
     }
 }
 
