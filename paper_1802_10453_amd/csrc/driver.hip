@@ -378,7 +378,7 @@ struct Engine {
         if (m <= 0 || r <= 0) return;
         const int64_t nb = (r + 63) / 64;
         ensure_tinv(nb * 64);
-        LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trinv_blocks, dim3((unsigned)nb), dim3(64), 0, st, T, r, 0, ws.tinv, F);
+        LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trinv_blocks, dim3((unsigned)nb), dim3(256), 0, st, T, r, 0, ws.tinv, F);
         trsm_ru_rec(B, m, r, T, ws.tinv);
     }
     void trsm_ru_rec(MatV B, int64_t m, int64_t r, MatV T, double* Nb) {
@@ -396,7 +396,7 @@ struct Engine {
         if (r <= 0 || ncols <= 0) return;
         const int64_t nb = (r + 63) / 64;
         ensure_tinv(nb * 64);
-        LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trinv_blocks, dim3((unsigned)nb), dim3(64), 0, st, T, r, 1, ws.tinv, F);
+        LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trinv_blocks, dim3((unsigned)nb), dim3(256), 0, st, T, r, 1, ws.tinv, F);
         trsm_ll_rec(B, r, ncols, T, ws.tinv);
     }
     void trsm_ll_rec(MatV B, int64_t r, int64_t ncols, MatV T, double* Nb) {
@@ -725,7 +725,7 @@ struct Engine {
     void trss(int64_t s0, int64_t r, int64_t u0) {
         if (r <= 0) return;
         if (r <= 64) {
-            LAUNCH(PLDL_CLASS_TRSS_LEAF, k_trss_leaf, dim3(1), dim3(64), 0, st, W, ld, s0, u0, (int)r, F);
+            LAUNCH(PLDL_CLASS_TRSS_LEAF, k_trss_leaf, dim3(1), dim3(256), 0, st, W, ld, s0, u0, (int)r, F);
             return;
         }
         int64_t h = std::max<int64_t>(64, (r / 2) / 64 * 64);

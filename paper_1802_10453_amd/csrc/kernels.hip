@@ -582,54 +582,139 @@ __global__ void k_idx_copy(int32_t* idx, int64_t a, int64_t len, const int32_t* 
 }
 
 // ===========================================================================
-// TRSS leaf (Problem 1) of order r <= 64, one wave: X upper with
-// X^T U + U^T X = C, solved column by column from the defining equations
-// (entry (i, j), i < j, determines X[i][j] through U[i][i] = 1; the diagonal
-// entry gives 2 X[j][j]; in characteristic 2 X[j][j] = 0).
+// 64 x 64 blocks held in LDS by one 256-thread workgroup (padding column 65).
+// ===========================================================================
+typedef double Blk[64][65];
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// V = T^{-1} for a unit upper triangular T of order 64 (Ts: strict upper part,
+// centered; the diagonal and the lower part are not read).  Blocked: the four
+// 16 x 16 diagonal blocks are inverted by substitution (one thread per column),
+// then the block super-diagonals d = 1, 2, 3 from T V = I:
+//   V_ij = -V_ii sum_{l = i+1 .. j} T_il V_lj.
+// Every entry is a sum of at most 48 products before its reduction.  V is
+// written centered, zero below the diagonal; S is scratch.  Ends with a barrier.
+__device__ void tri_inv64(const Blk& Ts, Blk& Vs, Blk& S, const Field& F) {
+    const int tid = threadIdx.x;
+    for (int e = tid; e < 64 * 64; e += 256) Vs[e >> 6][e & 63] = 0.0;
+    __syncthreads();
+    if (tid < 64) {
+        const int o = 16 * (tid >> 4), c = tid & 15;
+        double v[16];
+#pragma unroll
+        for (int a = 0; a < 16; ++a) v[a] = (a == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int a = 15; a >= 0; --a) {
+            if (a < c) {
+                double t = 0.0;
+#pragma unroll
+                for (int l = a + 1; l < 16; ++l)
+                    if (l <= c) t = fma(Ts[o + a][o + l], v[l], t);
+                v[a] = fredc(-t, F);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 16; ++a) Vs[o + a][o + c] = v[a];
+    }
+    __syncthreads();
+    for (int d = 1; d < 4; ++d) {
+        const int nb = (4 - d) * 256;
+        for (int e = tid; e < nb; e += 256) {
+            const int i = e >> 8, a = (e >> 4) & 15, bcol = e & 15, j = i + d;
+            double t = 0.0;
+            for (int g = 16 * (i + 1); g < 16 * (j + 1); ++g) t = fma(Ts[16 * i + a][g], Vs[g][16 * j + bcol], t);
+            S[16 * i + a][16 * j + bcol] = fredc(t, F);
+        }
+        __syncthreads();
+        for (int e = tid; e < nb; e += 256) {
+            const int i = e >> 8, a = (e >> 4) & 15, bcol = e & 15, j = i + d;
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) t = fma(Vs[16 * i + a][16 * i + q], S[16 * i + q][16 * j + bcol], t);
+            Vs[16 * i + a][16 * j + bcol] = fredc(-t, F);
+        }
+        __syncthreads();
+    }
+}
+
+// D = op(A) B (op(A) = A or A^T) of 64 x 64 blocks on the FP64 matrix cores:
+// wave w takes the 32 x 32 quadrant (w/2, w%2) as 2 x 2 v_mfma_f64_16x16x4f64
+// blocks.  Inputs centered: the 64 products of an entry sum exactly (< 2^53);
+// D is written reduced (centered) and must not alias A or B.  The caller
+// synchronises before (inputs written) and after (D read).
+__device__ void mm64(const Blk& A, bool transA, const Blk& B, Blk& D, const Field& F) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave >> 1, wn = wave & 1, lr = lane & 15, lk = lane >> 4;
+    d4 acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k = 0; k < 64; k += 4) {
+        double av[2], bv[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            const int row = 32 * wm + 16 * x + lr;
+            av[x] = transA ? A[k + lk][row] : A[row][k + lk];
+        }
+#pragma unroll
+        for (int y = 0; y < 2; ++y) bv[y] = B[k + lk][32 * wn + 16 * y + lr];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
+    }
+    // lane l, register r of a block holds D[l/16 + 4r][l%16]
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                D[32 * wm + 16 * x + lk + 4 * r][32 * wn + 16 * y + lr] = fredc(acc[x][y][r], F);
+}
+
+// ===========================================================================
+// TRSS leaf (Problem 1) of order r <= 64: the upper triangular X with
+// X^T U + U^T X = C (U unit upper, C symmetric).  With V = U^{-1} and Z = X V
+// (upper triangular) the equation reads Z + Z^T = V^T C V =: M, so Z is the
+// upper part of M with its diagonal halved (and 0 in characteristic 2, where
+// M's diagonal vanishes and X's diagonal is free: the leaf convention), and
+// X = Z U.  One inverse and three products of 64 x 64 blocks (zero padding
+// beyond r: the padded part of V is the identity, of X zero).
 // C (lower) at W[s0..s0+r)^2, U[a][b] = W[s0+b][u0+a] (a < b).  X^T is
 // written over C's lower triangle.
 // ===========================================================================
-__global__ __launch_bounds__(64) void k_trss_leaf(double* W, int64_t ld, int64_t s0, int64_t u0, int r, Field F) {
-    __shared__ double X[64][65];  // X[t][j]
-    __shared__ double U[64][65];  // U[t][j], unit upper
-    __shared__ double C[64][65];  // symmetric C
-    const int lane = threadIdx.x;
-    for (int e = lane; e < r * r; e += 64) {
-        int a = e / r, b = e % r;
-        U[a][b] = (a == b) ? 1.0 : (a < b ? fcen(W[(s0 + b) * ld + u0 + a], F) : 0.0);
-        C[a][b] = (a >= b) ? W[(s0 + a) * ld + s0 + b] : W[(s0 + b) * ld + s0 + a];
-        X[a][b] = 0.0;
+__global__ __launch_bounds__(256) void k_trss_leaf(double* W, int64_t ld, int64_t s0, int64_t u0, int r, Field F) {
+    __shared__ Blk Us, Vs, Cs, Ps;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < 64 * 64; e += 256) {
+        const int a = e >> 6, b = e & 63;
+        Us[a][b] = (a < b && b < r) ? fcen(W[(s0 + b) * ld + u0 + a], F) : 0.0;
+        double c = 0.0;
+        if (a < r && b < r) c = (a >= b) ? W[(s0 + a) * ld + s0 + b] : W[(s0 + b) * ld + s0 + a];
+        Cs[a][b] = fcen(c, F);
     }
     __syncthreads();
-    for (int j = 0; j < r; ++j) {
-        // b_i = C_ij - sum_{t<=i} X[t][i] U[t][j]   (i < j; lane i)
-        double bi = 0.0;
-        if (lane < j) {
-            double s = C[lane][j];
-            for (int t = 0; t <= lane; ++t) s = fma(-X[t][lane], U[t][j], s);
-            bi = fred(s, F);
-        }
-        // solve sum_{t<=i} U[t][i] X[t][j] = b_i, U unit: forward substitution
-        for (int i = 0; i < j; ++i) {
-            double xi = __shfl(bi, i);
-            xi = fcen(fred(xi, F), F);
-            if (lane == i) X[i][j] = fcan(xi, F);
-            if (lane > i && lane < j) bi = fma(-U[i][lane], xi, bi);
-        }
-        __syncthreads();
-        if (lane == 0) {
-            if (F.ip == 2) X[j][j] = 0.0;
-            else {
-                double s = 0.0;
-                for (int t = 0; t < j; ++t) s = fma(fcen(X[t][j], F), U[t][j], s);
-                X[j][j] = fcan(fred(fmulm(C[j][j], F.inv2, F) - fred(s, F), F), F);
-            }
-        }
-        __syncthreads();
+    tri_inv64(Us, Vs, Ps, F);
+    mm64(Cs, false, Vs, Ps, F);   // P = C V
+    __syncthreads();
+    mm64(Vs, true, Ps, Cs, F);    // M = V^T P
+    __syncthreads();
+    for (int e = tid; e < 64 * 64; e += 256) {   // Z = upper part of M, halved diagonal
+        const int a = e >> 6, b = e & 63;
+        double z = Cs[a][b];
+        if (a > b) z = 0.0;
+        else if (a == b) z = (F.ip == 2) ? 0.0 : fredc(z * F.inv2, F);
+        Cs[a][b] = z;
     }
-    for (int e = lane; e < r * r; e += 64) {
-        int a = e / r, b = e % r;
-        if (b <= a) W[(s0 + a) * ld + s0 + b] = X[b][a];
+    __syncthreads();
+    mm64(Cs, false, Us, Ps, F);   // Z (U - I)
+    __syncthreads();
+    for (int e = tid; e < 64 * 64; e += 256) {   // X = Z (U - I) + Z, written transposed
+        const int a = e >> 6, b = e & 63;
+        if (a < r && b <= a) W[(s0 + a) * ld + s0 + b] = fred(Ps[b][a] + Cs[b][a], F);
     }
 }
 
@@ -640,47 +725,29 @@ __global__ __launch_bounds__(64) void k_trss_leaf(double* W, int64_t ld, int64_t
 // triangular T (order r) gets N_k = I - T_kk^{-1}, row-major 64 x 64 (strict
 // lower part for a lower T, strict upper part for an upper T), so that
 // T_kk^{-1} X = X - N_k X and X T_kk^{-1} = X - X N_k.  One workgroup per
-// block; thread c solves for column c of the inverse of the lower-triangular
-// form L_k (T_kk itself, or T_kk^T for an upper T: (T^T)^{-1} = (T^{-1})^T) by
-// forward substitution in registers, with at most 63 products accumulated
-// before each entry is reduced.
+// block; a lower block is inverted through its transpose ((T^T)^{-1} =
+// (T^{-1})^T).
 // ===========================================================================
-__global__ __launch_bounds__(64) void k_trinv_blocks(MatV T, int64_t r, int lower, double* N, Field F) {
-    __shared__ double Ls[64][65];
+__global__ __launch_bounds__(256) void k_trinv_blocks(MatV T, int64_t r, int lower, double* N, Field F) {
+    __shared__ Blk Us, Vs, Ss;
     const int tid = threadIdx.x;
     const int64_t o = (int64_t)blockIdx.x * 64;
     const int rb = (int)min((int64_t)64, r - o);
-    {
-        // unconditional loads (coordinates clamped into the block) so that all are in flight together
-        const int64_t c = o + min(tid, rb - 1);
-        double tv[64];
-#pragma unroll
-        for (int a = 0; a < 64; ++a) {
-            const int64_t ra = o + min(a, rb - 1);
-            tv[a] = lower ? T.p[ra * T.rs + c * T.cs] : T.p[c * T.rs + ra * T.cs];
-        }
-#pragma unroll
-        for (int a = 0; a < 64; ++a) Ls[a][tid] = (a > tid && a < rb) ? fcen(tv[a], F) : 0.0;
+    for (int e = tid; e < 64 * 64; e += 256) {
+        const int a = e >> 6, b = e & 63;   // Us[a][b], a < b: T[a][b] (upper) or T[b][a] (lower)
+        double v = 0.0;
+        if (a < b && b < rb) v = lower ? T.p[(o + b) * T.rs + (o + a) * T.cs] : T.p[(o + a) * T.rs + (o + b) * T.cs];
+        Us[a][b] = fcen(v, F);
     }
     __syncthreads();
-    double z[64];
-#pragma unroll
-    for (int i = 0; i < 64; ++i) z[i] = (i == tid) ? 1.0 : 0.0;
-#pragma unroll
-    for (int i = 0; i < 64; ++i) {
-        if (i < rb) {
-            const double zi = fredc(z[i], F);
-            z[i] = zi;
-#pragma unroll
-            for (int ii = i + 1; ii < 64; ++ii) z[ii] = fma(-Ls[ii][i], zi, z[ii]);
-        }
-    }
+    tri_inv64(Us, Vs, Ss, F);
     double* Nk = N + (int64_t)blockIdx.x * 4096;
-#pragma unroll
-    for (int a = 0; a < 64; ++a) {
-        const double v = (a > tid && a < rb) ? fcan(fredc(-z[a], F), F) : 0.0;
-        if (lower) Nk[a * 64 + tid] = v;
-        else Nk[tid * 64 + a] = v;
+    for (int e = tid; e < 64 * 64; e += 256) {
+        const int a = e >> 6, b = e & 63;
+        double v = 0.0;
+        if (lower) { if (a > b) v = fcan(fredc(-Vs[b][a], F), F); }
+        else if (a < b) v = fcan(fredc(-Vs[a][b], F), F);
+        Nk[a * 64 + b] = v;
     }
 }
 
