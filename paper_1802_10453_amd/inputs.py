@@ -188,21 +188,24 @@ def batch_params(count: int, nmin: int, nmax: int, seed: int):
 
 def _batch_one(args):
     n, r, f, c, s, p = args
-    A, _ = rank_profile_matrix_input(n, p, f, c, s, check=0)
-    return A
+    return rank_profile_matrix_input(n, p, f, c, s, check=0)
 
 
-def batch_input(cfg: dict, index_seed: int = 0, workers: int = 0):
+def batch_input(cfg: dict, index_seed: int = 0, workers: int = 0, with_rpm: bool = False):
     """The matrices of a batched workload (list of uint32 arrays) and their per-matrix
-    (n, r, f, c, seed); ``workers`` processes build them (0: serial)."""
+    (n, r, f, c, seed) (and, with_rpm, their rank profile matrices); ``workers``
+    processes build them (0: serial)."""
     params = batch_params(cfg["count"], cfg["nmin"], cfg["nmax"], SEED_BASE + index_seed)
     jobs = [(n, r, f, c, s, cfg["p"]) for (n, r, f, c, s) in params]
     if workers and workers > 1:
         import multiprocessing as mp
         with mp.get_context("spawn").Pool(workers) as pool:
-            mats = pool.map(_batch_one, jobs, chunksize=16)
+            out = pool.map(_batch_one, jobs, chunksize=16)
     else:
-        mats = [_batch_one(j) for j in jobs]
+        out = [_batch_one(j) for j in jobs]
+    mats = [A for A, _ in out]
+    if with_rpm:
+        return mats, params, [rpm for _, rpm in out]
     return mats, params
 
 
