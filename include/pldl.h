@@ -47,7 +47,8 @@ typedef struct pldl_ctx pldl_ctx;
 
 typedef struct {
     int32_t path;          /* PLDL_PATH_*                                              */
-    int32_t threshold;     /* base-case order t of the cascade (Section 5); 0 = default */
+    int32_t threshold;     /* base-case order t of the cascade (Section 5), 1..128;
+                              0 = the context's autotuned value (pldl_autotune), else 128 */
     int32_t standard_form; /* p == 2 only: turn relaxed 2x2 blocks into the standard
                               form of Section 2.3 (after the rank profile is taken)     */
     int32_t check_range;   /* nonzero: reject inputs with an entry >= p (PLDL_ERANGE)   */
@@ -123,6 +124,35 @@ int pldl_factor_batched(pldl_ctx *ctx, uint32_t p, int64_t batch, const int64_t 
                         const int64_t *lda, int32_t dtype, void *const *e, int32_t *const *perm,
                         int32_t *const *rpm, int64_t *rank, int32_t *status, const pldl_opts *opts,
                         void *stream);
+
+/*
+ * pldl_char2_to_standard -- the transform of Section 2.3 applied to a
+ * characteristic-2 factorization returned by pldl_factor (p = 2, standard_form
+ * 0): every relaxed 2x2 block [[0,c],[c,d]] with d != 0 is turned into the
+ * 1x1 blocks (d) and (c^2/d) by P~ = P P_J, L~ = (P_J^T L P_J) L_J.
+ * A (lda), e, perm: pldl_factor's outputs, updated in place (same layout);
+ * rpm is not changed by the transform (take it from pldl_factor).  Entries
+ * outside {0, 1} give PLDL_ERANGE.  Synchronises `stream`.
+ */
+int pldl_char2_to_standard(pldl_ctx *ctx, int64_t n, void *A, int64_t lda, int32_t dtype, void *e,
+                           int32_t *perm, void *stream);
+
+/*
+ * pldl_autotune -- picks the base-case threshold of the cascade (Section 5)
+ * for each order in n_list[0 .. count) (host array, 1 <= n <= 16384) over F_p:
+ * builds two synthetic matrices of that order on the device (uniform
+ * symmetric, i.e. a generic rank profile; and L R L^T with a random rank
+ * profile of rank about n/2), times pldl_factor at thresholds 32, 48, 64, 96
+ * and 128 (best of two runs each) and keeps the threshold with the smallest
+ * total.  Later pldl_factor calls on this context with opts->threshold = 0
+ * use the entry of the same p (else of any p) nearest to their n on a log
+ * scale.  table_path (may be NULL): the table is written there as text lines
+ * "p n threshold ms_uniform ms_rank_profile".  With count = 0, the table at
+ * table_path is read instead.  Allocates five n x n FP64 buffers per order
+ * while it runs; synchronises `stream`.
+ */
+int pldl_autotune(pldl_ctx *ctx, uint32_t p, const int64_t *n_list, int64_t count, const char *table_path,
+                  void *stream);
 
 /* ---------------- building blocks (Section 3), FP64 residues ---------------- */
 

@@ -16,6 +16,9 @@
 #include <cstring>
 #include <stdexcept>
 #include <chrono>
+#include <fstream>
+#include <random>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -758,6 +761,21 @@ struct pldl_ctx {
     uint32_t itab_p = 0;
     int path = PLDL_PATH_F64;  // matrix cores of the products (pldl_set_path)
     I8Space i8;
+    // autotuned base-case thresholds: (p, n, threshold); pldl_factor takes the entry of
+    // the same p (else any p) nearest to its n on a log scale, else 128
+    struct Tune { uint32_t p; int64_t n; int t; };
+    std::vector<Tune> tune;
+    int tuned_threshold(uint32_t p, int64_t n) const {
+        int best = 128;
+        double bd = 1e300;
+        for (int pass = 0; pass < 2 && bd == 1e300; ++pass)
+            for (const Tune& e : tune) {
+                if (pass == 0 && e.p != p) continue;
+                const double dist = std::fabs(std::log((double)std::max<int64_t>(n, 1) / (double)e.n));
+                if (dist < bd) { bd = dist; best = e.t; }
+            }
+        return best;
+    }
     double* bws = nullptr;     // batched factorizations: one slot per persistent workgroup
     int bslots = 0;
     int32_t* bqueue = nullptr;
@@ -855,7 +873,7 @@ int pldl_factor(pldl_ctx* ctx, uint32_t p, int64_t n, void* A, int64_t lda, int3
     if (o.path != PLDL_PATH_AUTO && o.path != PLDL_PATH_F64 && o.path != PLDL_PATH_I8)
         return fail(ctx, -11, "unknown path");
     if (o.threshold < 0 || o.threshold > 128) return fail(ctx, -11, "threshold must be in [0, 128]");
-    int t = o.threshold ? o.threshold : 128;
+    int t = o.threshold ? o.threshold : ctx->tuned_threshold(p, n);
     if (n == 0) { *rank = 0; return PLDL_OK; }
     hipStream_t st = as_stream(stream);
     return guarded(ctx, [&]() {
@@ -1101,6 +1119,168 @@ int pldl_factor_batched(pldl_ctx* ctx, uint32_t p, int64_t batch, const int64_t*
         ctx->prof.end(st);
         HIPCHK(hipGetLastError());
     });
+}
+
+int pldl_char2_to_standard(pldl_ctx* ctx, int64_t n, void* A, int64_t lda, int32_t dtype, void* e, int32_t* perm,
+                           void* stream) {
+    if (!ctx) return -1;
+    if (n < 0 || n > 65535) return fail(ctx, -2, "n out of range [0, 65535]");
+    if (n > 0 && !A) return fail(ctx, -3, "A is NULL");
+    if (lda < std::max<int64_t>(1, n)) return fail(ctx, -4, "lda < max(1, n)");
+    if (dtype != PLDL_U32 && dtype != PLDL_F64) return fail(ctx, -5, "unknown dtype");
+    if (n > 0 && !e) return fail(ctx, -6, "e is NULL");
+    if (n > 0 && !perm) return fail(ctx, -7, "perm is NULL");
+    if (n == 0) return PLDL_OK;
+    hipStream_t st = as_stream(stream);
+    return guarded(ctx, [&]() {
+        ctx->ws.ensure(n);
+        Workspace& ws = ctx->ws;
+        Prof* prof = &ctx->prof;
+        Field F = make_field(2);
+        const int64_t ld = n;
+        HIPCHK(hipMemsetAsync(ws.info, 0, sizeof(int32_t) * 4, st));
+        dim3 g(nblk(n), (unsigned)n);
+        if (dtype == PLDL_U32) {
+            LAUNCH(PLDL_CLASS_OTHER, k_load_input<uint32_t>, g, dim3(256), 0, st, (const uint32_t*)A, lda, ws.W, ld, n, F, ws.info + 2);
+            LAUNCH(PLDL_CLASS_OTHER, k_load_factors<uint32_t>, dim3(nblk(n)), dim3(256), 0, st, ws.W, ld, n, (const uint32_t*)e, perm, ws.dd, ws.de, ws.orig);
+        } else {
+            LAUNCH(PLDL_CLASS_OTHER, k_load_input<double>, g, dim3(256), 0, st, (const double*)A, lda, ws.W, ld, n, F, ws.info + 2);
+            LAUNCH(PLDL_CLASS_OTHER, k_load_factors<double>, dim3(nblk(n)), dim3(256), 0, st, ws.W, ld, n, (const double*)e, perm, ws.dd, ws.de, ws.orig);
+        }
+        LAUNCH(PLDL_CLASS_OTHER, k_char2_std, g, dim3(256), 0, st, ws.W, ld, n, ws.dd, ws.de, ws.orig, ws.tmp1, 0);
+        LAUNCH(PLDL_CLASS_OTHER, k_char2_std, g, dim3(256), 0, st, ws.W, ld, n, ws.dd, ws.de, ws.orig, ws.tmp1, 1);
+        LAUNCH(PLDL_CLASS_OTHER, k_char2_std, dim3(nblk(n)), dim3(256), 0, st, ws.W, ld, n, ws.dd, ws.de, ws.orig, ws.tmp1, 2);
+        if (dtype == PLDL_U32)
+            LAUNCH(PLDL_CLASS_OTHER, k_store_output<uint32_t>, g, dim3(256), 0, st, (uint32_t*)A, lda, ws.W, ld, n, ws.dd, ws.de, (uint32_t*)e, ws.orig, perm);
+        else
+            LAUNCH(PLDL_CLASS_OTHER, k_store_output<double>, g, dim3(256), 0, st, (double*)A, lda, ws.W, ld, n, ws.dd, ws.de, (double*)e, ws.orig, perm);
+        HIPCHK(hipGetLastError());
+        int32_t bad = 0;
+        HIPCHK(hipMemcpyAsync(&bad, ws.info + 2, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (bad) throw Err(PLDL_ERANGE, "an entry of the factorization is not in [0, 2)");
+    });
+}
+
+int pldl_autotune(pldl_ctx* ctx, uint32_t p, const int64_t* n_list, int64_t count, const char* table_path,
+                  void* stream) {
+    if (!ctx) return -1;
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (count < 0) return fail(ctx, -4, "count < 0");
+    if (count > 0 && !n_list) return fail(ctx, -3, "n_list is NULL");
+    for (int64_t k = 0; k < count; ++k)
+        if (n_list[k] < 1 || n_list[k] > 16384) return fail(ctx, -3, "every n must lie in [1, 16384]");
+    if (count == 0) {   // load a table written by an earlier call
+        if (!table_path) return fail(ctx, -5, "nothing to tune and no table to read");
+        std::ifstream in(table_path);
+        if (!in) return fail(ctx, -5, std::string("cannot read ") + table_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            if (line.empty() || line[0] == '#') continue;
+            std::istringstream ls(line);
+            uint32_t tp; int64_t tn; int tt;
+            if (ls >> tp >> tn >> tt && tt >= 1 && tt <= 128 && tn >= 1) ctx->tune.push_back({tp, tn, tt});
+        }
+        return PLDL_OK;
+    }
+    hipStream_t st = as_stream(stream);
+    static const int cand[] = {32, 48, 64, 96, 128};
+    std::vector<std::string> rows;
+    int rc = guarded(ctx, [&]() {
+        for (int64_t k = 0; k < count; ++k) {
+            const int64_t n = n_list[k];
+            const size_t nn = (size_t)n * (size_t)n;
+            double *A0 = nullptr, *A1 = nullptr, *Aw = nullptr, *Lb = nullptr, *Bb = nullptr, *ev = nullptr, *sc = nullptr;
+            int32_t *perm = nullptr, *rpm = nullptr, *rr = nullptr;
+            auto cleanup = [&]() {
+                double* ds[] = {A0, A1, Aw, Lb, Bb, ev, sc};
+                for (double* q : ds) if (q) (void)hipFree(q);
+                int32_t* is[] = {perm, rpm, rr};
+                for (int32_t* q : is) if (q) (void)hipFree(q);
+            };
+            try {
+                HIPCHK(hipMalloc((void**)&A0, nn * 8));
+                HIPCHK(hipMalloc((void**)&A1, nn * 8));
+                HIPCHK(hipMalloc((void**)&Aw, nn * 8));
+                HIPCHK(hipMalloc((void**)&Lb, nn * 8));
+                HIPCHK(hipMalloc((void**)&Bb, nn * 8));
+                HIPCHK(hipMalloc((void**)&ev, n * 8));
+                HIPCHK(hipMalloc((void**)&sc, n * 8));
+                HIPCHK(hipMalloc((void**)&perm, n * 4));
+                HIPCHK(hipMalloc((void**)&rpm, n * 4));
+                HIPCHK(hipMalloc((void**)&rr, n * 4));
+                Field F = make_field(p);
+                dim3 g2(nblk(n), (unsigned)n);
+                const uint64_t seed = 0x243F6A8885A308D3ull ^ (uint64_t)n;
+                // class 1: uniform symmetric (generic rank profile)
+                hipLaunchKernelGGL(k_fill_uniform_sym, g2, dim3(256), 0, st, A0, n, p, seed);
+                // class 2: A = L R L^T, R a random symmetric rook placement of rank about n/2
+                std::mt19937_64 rng(seed);
+                std::vector<int32_t> hr(n, -1);
+                std::vector<double> hs(n, 0.0);
+                std::vector<int64_t> idx(n);
+                for (int64_t i = 0; i < n; ++i) idx[i] = i;
+                std::shuffle(idx.begin(), idx.end(), rng);
+                const int64_t f = n / 4, c = n / 8;
+                for (int64_t i = 0; i < f; ++i) { hr[idx[i]] = (int32_t)idx[i]; hs[idx[i]] = (double)(1 + rng() % (p - 1)); }
+                for (int64_t i = 0; i < c; ++i) {
+                    const int64_t a = idx[f + 2 * i], b = idx[f + 2 * i + 1];
+                    const double s = (double)(1 + rng() % (p - 1));
+                    hr[a] = (int32_t)b; hr[b] = (int32_t)a; hs[a] = s; hs[b] = s;
+                }
+                HIPCHK(hipMemcpyAsync(rr, hr.data(), n * 4, hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpyAsync(sc, hs.data(), n * 8, hipMemcpyHostToDevice, st));
+                hipLaunchKernelGGL(k_fill_unit_lower, g2, dim3(256), 0, st, Lb, n, p, seed + 1);
+                hipLaunchKernelGGL(k_fill_neg_rlt, g2, dim3(256), 0, st, Bb, Lb, n, rr, sc, F);
+                HIPCHK(hipMemsetAsync(A1, 0, nn * 8, st));
+                GemmSeg sg{MatV{Lb, n, 1}, MatV{Bb, n, 1}, n};
+                launch_gemm(st, F, n, n, A1, n, &sg, 1, true, false);
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipStreamSynchronize(st));
+                double best = 1e300, bu = 0.0, br = 0.0;
+                int bt = 128;
+                for (int t : cand) {
+                    if (t > n && t != cand[0]) continue;
+                    double ms[2];
+                    for (int cls = 0; cls < 2; ++cls) {
+                        ms[cls] = 1e300;
+                        for (int rep = 0; rep < 2; ++rep) {
+                            HIPCHK(hipMemcpyAsync(Aw, cls ? A1 : A0, nn * 8, hipMemcpyDeviceToDevice, st));
+                            HIPCHK(hipStreamSynchronize(st));
+                            pldl_opts o{PLDL_PATH_AUTO, t, 0, 0};
+                            int64_t rk = 0;
+                            const auto t0 = std::chrono::steady_clock::now();
+                            const int frc = pldl_factor(ctx, p, n, Aw, n, PLDL_F64, ev, perm, rpm, &rk, &o, stream);
+                            const double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                            if (frc != PLDL_OK) throw Err(frc, "factorization during tuning failed: " + ctx->err);
+                            ms[cls] = std::min(ms[cls], el);
+                        }
+                    }
+                    if (ms[0] + ms[1] < best) { best = ms[0] + ms[1]; bt = t; bu = ms[0]; br = ms[1]; }
+                }
+                ctx->tune.erase(std::remove_if(ctx->tune.begin(), ctx->tune.end(),
+                                               [&](const pldl_ctx::Tune& e) { return e.p == p && e.n == n; }),
+                                ctx->tune.end());
+                ctx->tune.push_back({p, n, bt});
+                char buf[160];
+                std::snprintf(buf, sizeof buf, "%u %lld %d %.3f %.3f", p, (long long)n, bt, bu, br);
+                rows.push_back(buf);
+            } catch (...) {
+                (void)hipStreamSynchronize(st);
+                cleanup();
+                throw;
+            }
+            HIPCHK(hipStreamSynchronize(st));
+            cleanup();
+        }
+    });
+    if (rc == PLDL_OK && table_path) {
+        std::ofstream out(table_path);
+        if (!out) return fail(ctx, -5, std::string("cannot write ") + table_path);
+        out << "# pldl_autotune: p n threshold ms_uniform ms_rank_profile\n";
+        for (const std::string& r : rows) out << r << "\n";
+    }
+    return rc;
 }
 
 int pldl_set_path(pldl_ctx* ctx, int32_t path) {

@@ -74,4 +74,11 @@ __global__ void k_trss_pack(const double* U, int64_t ldu, const double* C, int64
 __global__ void k_trss_unpack(const double* W, int64_t ldw, int64_t n, double* X, int64_t ldx);
 
 
+template <typename T>
+__global__ void k_load_factors(const double* W, int64_t ld, int64_t n, const T* e, const int32_t* perm, double* dd,
+                               double* de, int32_t* orig);
+__global__ void k_fill_uniform_sym(double* A, int64_t n, uint32_t p, uint64_t seed);
+__global__ void k_fill_unit_lower(double* L, int64_t n, uint32_t p, uint64_t seed);
+__global__ void k_fill_neg_rlt(double* B, const double* L, int64_t n, const int32_t* rpm, const double* scale, Field F);
+
 }  // namespace pldl

@@ -1081,6 +1081,52 @@ __global__ void k_store_output(T* A, int64_t lda, const double* W, int64_t ld, i
     if (j == 0) { e[i] = (T)de[i]; perm[i] = orig[i]; }
 }
 
+// A factorization handed back in (lower triangle: L and diag(D), e, perm):
+// the working form of the Section 2.3 transform (W and diag(D) already loaded).
+template <typename T>
+__global__ void k_load_factors(const double* W, int64_t ld, int64_t n, const T* e, const int32_t* perm, double* dd,
+                               double* de, int32_t* orig) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    dd[i] = W[i * ld + i];
+    de[i] = (double)e[i];
+    orig[i] = perm[i];
+}
+
+// Synthetic inputs of the autotuner (counter-based: splitmix64 of (seed, i, j)).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+// A (n x n, FP64): uniform symmetric residues (lower triangle and diagonal drawn)
+__global__ void k_fill_uniform_sym(double* A, int64_t n, uint32_t p, uint64_t seed) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
+    if (i >= n || j > i) return;
+    const uint64_t h = mix64(seed ^ mix64(((uint64_t)i << 32) | (uint64_t)j));
+    const double v = (double)(h % p);
+    A[i * n + j] = v;
+    A[j * n + i] = v;
+}
+// L (n x n, FP64): unit lower triangular, strictly lower entries uniform
+__global__ void k_fill_unit_lower(double* L, int64_t n, uint32_t p, uint64_t seed) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
+    if (i >= n || j >= n) return;
+    double v = 0.0;
+    if (i == j) v = 1.0;
+    else if (j < i) v = (double)(mix64(seed ^ mix64(((uint64_t)i << 32) | (uint64_t)j)) % p);
+    L[i * n + j] = v;
+}
+// B = -(R L^T) for the symmetric rook placement R (rpm, scale): B[i][j] = -s_i L[j][rpm[i]]
+__global__ void k_fill_neg_rlt(double* B, const double* L, int64_t n, const int32_t* rpm, const double* scale, Field F) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
+    if (i >= n || j >= n) return;
+    double v = 0.0;
+    if (rpm[i] >= 0) v = fcan(-fred(scale[i] * L[j * n + rpm[i]], F), F);
+    B[i * n + j] = v;
+}
+
 // rpm from the block structure: R = P Psi P^T (pivoting matrix, Section 2.1)
 __global__ void k_rpm(const int32_t* orig, const double* de, int64_t n, int64_t r, int32_t* rpm) {
     int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -1193,6 +1239,10 @@ __global__ void k_trss_unpack(const double* W, int64_t ldw, int64_t n, double* X
 // ===========================================================================
 // Explicit instantiations used by the driver.
 // ===========================================================================
+template __global__ void k_load_factors<uint32_t>(const double*, int64_t, int64_t, const uint32_t*, const int32_t*,
+                                                  double*, double*, int32_t*);
+template __global__ void k_load_factors<double>(const double*, int64_t, int64_t, const double*, const int32_t*, double*,
+                                                double*, int32_t*);
 template __global__ void k_load_input<uint32_t>(const uint32_t*, int64_t, double*, int64_t, int64_t, Field, int32_t*);
 template __global__ void k_load_input<double>(const double*, int64_t, double*, int64_t, int64_t, Field, int32_t*);
 template __global__ void k_store_output<uint32_t>(uint32_t*, int64_t, const double*, int64_t, int64_t, const double*,

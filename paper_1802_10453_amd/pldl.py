@@ -56,14 +56,18 @@ _lib.pldl_trss.argtypes = [_vp, _u32, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp
 _lib.pldl_plduq.argtypes = [_vp, _u32, _i64, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(_i64), _vp]
 _lib.pldl_profile.argtypes = [_vp, _i32, ctypes.POINTER(pldl_stats)]
 _lib.pldl_set_path.argtypes = [_vp, _i32]
+_lib.pldl_char2_to_standard.argtypes = [_vp, _i64, _vp, _i64, _i32, _vp, _vp, _vp]
+_lib.pldl_autotune.argtypes = [_vp, _u32, ctypes.POINTER(_i64), _i64, ctypes.c_char_p, _vp]
 _lib.pldl_factor_batched.argtypes = [_vp, _u32, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
                                      ctypes.POINTER(pldl_opts), _vp]
 for _f in ("pldl_create", "pldl_destroy", "pldl_factor", "pldl_gemm", "pldl_trsm", "pldl_syrdk", "pldl_trss",
-           "pldl_plduq", "pldl_profile", "pldl_set_path", "pldl_factor_batched"):
+           "pldl_plduq", "pldl_profile", "pldl_set_path", "pldl_factor_batched", "pldl_char2_to_standard",
+           "pldl_autotune"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("pldl_create", "pldl_destroy", "pldl_last_error", "pldl_factor", "pldl_gemm", "pldl_trsm",
-            "pldl_syrdk", "pldl_trss", "pldl_plduq", "pldl_profile", "pldl_set_path", "pldl_factor_batched")
+            "pldl_syrdk", "pldl_trss", "pldl_plduq", "pldl_profile", "pldl_set_path", "pldl_factor_batched",
+            "pldl_char2_to_standard", "pldl_autotune")
 
 
 class PldlError(RuntimeError):
@@ -140,6 +144,20 @@ class Context:
                               ctypes.byref(rank), ctypes.byref(o), _stream())
         self._check(rc)
         return dict(perm=perm[:n], rpm=rpm[:n], e=e[:n], rank=int(rank.value))
+
+    def char2_to_standard(self, A: torch.Tensor, e: torch.Tensor, perm: torch.Tensor):
+        """pldl_char2_to_standard on pldl_factor's outputs (p = 2), in place."""
+        n = A.shape[0]
+        dt = PLDL_U32 if A.dtype == torch.int32 else PLDL_F64
+        self._check(_lib.pldl_char2_to_standard(self._h, n, _ptr(A), _ld(A) if n else 1, dt, _ptr(e), _ptr(perm),
+                                                _stream()))
+
+    def autotune(self, p: int, n_list, table_path: str = None):
+        """pldl_autotune: base-case thresholds for the orders in n_list (or, with an empty
+        list, read the table at table_path)."""
+        arr = (_i64 * max(len(n_list), 1))(*[int(x) for x in n_list])
+        self._check(_lib.pldl_autotune(self._h, int(p), arr, len(n_list),
+                                       table_path.encode() if table_path else None, _stream()))
 
     def batched_args(self, mats):
         """Device argument arrays of pldl_factor_batched for a list of square tensors (int32
