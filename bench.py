@@ -195,6 +195,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--threshold", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the base-case threshold with pldl_autotune before the warm-up (untimed)")
     ap.add_argument("--path", default="f64", choices=["f64", "i8"],
                     help="matrix cores of the products: FP64 with delayed reduction, or INT8 with residues "
                          "split into signed bytes")
@@ -226,6 +228,17 @@ def main():
     copies = [A0.clone() for _ in range(nrun)]
     ctx = pldl.Context(0)
     ctx.set_path(pldl.PLDL_PATH_I8 if args.path == "i8" else pldl.PLDL_PATH_F64)
+    threshold_used = args.threshold or 128
+    if args.autotune and not args.threshold:
+        import tempfile
+        tpath = os.path.join(tempfile.mkdtemp(), "tune.txt")
+        t0 = time.perf_counter()
+        ctx.autotune(p, [n], table_path=tpath)
+        with open(tpath) as f:
+            row = [l.split() for l in f if not l.startswith("#")][0]
+        threshold_used = int(row[2])
+        log(f"[bench] autotuned threshold {threshold_used} in {time.perf_counter() - t0:.1f} s "
+            f"(uniform {row[3]} ms, rank-profile {row[4]} ms at that threshold)")
     out = None
     for w in range(args.warmup):
         out = ctx.factor(copies[w], p, threshold=args.threshold)
@@ -301,7 +314,7 @@ def main():
         "value": round(value, 2), "unit": "GOPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.path == "f64" else "i8", "data": "synthetic",
-        "config": {"workload": cfg["name"], "n": n, "p": p, "rank": r, "threshold": args.threshold or 128,
+        "config": {"workload": cfg["name"], "n": n, "p": p, "rank": r, "threshold": threshold_used,
                    "path": "fp64-mfma" if args.path == "f64" else "int8-split-mfma",
                    "input": "uint32 residues in HBM"},
         "roofline": roofline, "cpu_baseline": cpu,
