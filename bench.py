@@ -108,10 +108,10 @@ def bench_batched(args, torch, inputs, pldl):
     persistent batched launch, on its own copy of the input batch."""
     cfg = inputs.C3
     p = cfg["p"]
-    workers = min(16, os.cpu_count() or 1)
-    log(f"[bench] generating {cfg['name']} with {workers} processes ...")
+    workers = min(16, os.cpu_count() or 1) if args.gen_workers < 0 else args.gen_workers
+    log(f"[bench] generating {cfg['name']} with {max(workers, 1)} process(es) ...")
     t0 = time.perf_counter()
-    mats, params = inputs.batch_input(cfg, workers=workers)
+    mats, params = inputs.batch_input(cfg, workers=workers, progress=lambda k: log(f"[bench]   {k} matrices"))
     log(f"[bench] input ready in {time.perf_counter() - t0:.1f} s")
     ctx = pldl.Context(0)
     nrun = args.warmup + args.steps
@@ -195,6 +195,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--threshold", type=int, default=0)
+    ap.add_argument("--gen-workers", type=int, default=-1,
+                    help="processes that build the batched input (-1: up to 16, 0: this process)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the base-case threshold with pldl_autotune before the warm-up (untimed)")
     ap.add_argument("--path", default="f64", choices=["f64", "i8"],

@@ -191,10 +191,10 @@ def _batch_one(args):
     return rank_profile_matrix_input(n, p, f, c, s, check=0)
 
 
-def batch_input(cfg: dict, index_seed: int = 0, workers: int = 0, with_rpm: bool = False):
+def batch_input(cfg: dict, index_seed: int = 0, workers: int = 0, with_rpm: bool = False, progress=None):
     """The matrices of a batched workload (list of uint32 arrays) and their per-matrix
     (n, r, f, c, seed) (and, with_rpm, their rank profile matrices); ``workers``
-    processes build them (0: serial)."""
+    processes build them (0: serial, calling progress(done) every 256 matrices)."""
     params = batch_params(cfg["count"], cfg["nmin"], cfg["nmax"], SEED_BASE + index_seed)
     jobs = [(n, r, f, c, s, cfg["p"]) for (n, r, f, c, s) in params]
     if workers and workers > 1:
@@ -202,7 +202,11 @@ def batch_input(cfg: dict, index_seed: int = 0, workers: int = 0, with_rpm: bool
         with mp.get_context("spawn").Pool(workers) as pool:
             out = pool.map(_batch_one, jobs, chunksize=16)
     else:
-        out = [_batch_one(j) for j in jobs]
+        out = []
+        for k, j in enumerate(jobs):
+            out.append(_batch_one(j))
+            if progress and (k + 1) % 256 == 0:
+                progress(k + 1)
     mats = [A for A, _ in out]
     if with_rpm:
         return mats, params, [rpm for _, rpm in out]
