@@ -13,7 +13,8 @@ namespace pldl {
 // ===========================================================================
 // Base case (Section 5, Algorithm 4): rank-profile-revealing elimination of a
 // symmetric block of order s <= 128 held in registers (one workgroup, 1024
-// threads, each owning a 4x4 tile of the full symmetric matrix).
+// threads, each owning a 4x4 tile of the full symmetric matrix; the owners of
+// one column form one wave).
 //
 // Pivot search as in Section 5: the current row i is the first unprocessed
 // one; its pivot is the first nonzero of its Schur-complement row (found with
@@ -34,7 +35,9 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
     __shared__ int bt[128];
     __shared__ uint32_t Mo[128][129];
 
-    const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31, lane = tid & 63;
+    // thread -> 4x4 tile: the owners of a column (one tx) all sit in one wave, so the
+    // per-pivot column work (publish, multipliers written back) runs in one wave only
+    const int tid = threadIdx.x, ty = tid & 31, tx = tid >> 5, lane = tid & 63;
     const int r0 = ty * 4, c0 = tx * 4;
     double m[4][4];
 #pragma unroll
@@ -50,7 +53,20 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
     uint64_t al0 = (s >= 64) ? ~0ull : ((1ull << s) - 1ull);
     uint64_t al1 = (s >= 128) ? ~0ull : (s > 64 ? ((1ull << (s - 64)) - 1ull) : 0ull);
     auto alive = [&](int k) -> bool { return k < 64 ? ((al0 >> k) & 1ull) : ((al1 >> (k - 64)) & 1ull); };
-    auto kill = [&](int k) { if (k < 64) al0 &= ~(1ull << k); else al1 &= ~(1ull << (k - 64)); };
+    // this thread's rows r0 .. r0+3 and columns c0 .. c0+3 that are alive, as 4-bit masks
+    uint32_t rbits = 0, cbits = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (r0 + q < s) rbits |= 1u << q;
+        if (c0 + q < s) cbits |= 1u << q;
+    }
+    auto kill = [&](int k) {
+        if (k < 64) al0 &= ~(1ull << k); else al1 &= ~(1ull << (k - 64));
+        if ((k >> 2) == ty) rbits &= ~(1u << (k & 3));
+        if ((k >> 2) == tx) cbits &= ~(1u << (k & 3));
+    };
+    auto ralive = [&](int q) -> bool { return (rbits >> q) & 1u; };
+    auto calive = [&](int q) -> bool { return (cbits >> q) & 1u; };
 
     int r = 0, nz = 0, step = 0;
     for (int i = 0; i < s; ++i) {
@@ -66,7 +82,7 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
                 double v = 0.0;
 #pragma unroll
                 for (int b = 0; b < 4; ++b) v = (b == (i & 3)) ? m[a][b] : v;
-                v = alive(k) ? fredc(v, F) : 0.0;
+                v = ralive(a) ? fredc(v, F) : 0.0;
                 colv[a] = v;
             }
 #pragma unroll
@@ -98,12 +114,12 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
                 int k = r0 + a;
-                vb[a] = alive(k) ? fredc(colI[bI][k] * xi, F) : 0.0;
+                vb[a] = ralive(a) ? fredc(colI[bI][k] * xi, F) : 0.0;
             }
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 int l = c0 + b;
-                vc[b] = alive(l) ? colI[bI][l] : 0.0;
+                vc[b] = calive(b) ? colI[bI][l] : 0.0;
             }
 #pragma unroll
             for (int a = 0; a < 4; ++a)
@@ -125,7 +141,7 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
                     double v = 0.0;
 #pragma unroll
                     for (int b = 0; b < 4; ++b) v = (b == (j & 3)) ? m[a][b] : v;
-                    colJ[bI][k] = alive(k) ? fredc(v, F) : 0.0;
+                    colJ[bI][k] = ralive(a) ? fredc(v, F) : 0.0;
                 }
             }
             __syncthreads();
@@ -142,7 +158,7 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
                 int k = r0 + a;
-                bool al = alive(k);
+                bool al = ralive(a);
                 double ci = al ? colI[bI][k] : 0.0, cj = al ? colJ[bI][k] : 0.0;
                 double bk = fredc(ci * xi, F);
                 double ek = fredc(cj - fredc(w * bk, F), F);
@@ -156,7 +172,7 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 int l = c0 + b;
-                bool al = alive(l);
+                bool al = calive(b);
                 double ci = al ? colI[bI][l] : 0.0, cj = al ? colJ[bI][l] : 0.0;
                 double bl = fredc(ci * xi, F);
                 double el = fredc(cj - fredc(w * bl, F), F);
