@@ -194,7 +194,8 @@ struct Workspace {
     int64_t ipool_len = 0;             // ints of the stack part
     int32_t* ipool_scratch = nullptr;  // two halves: inverse map, reorder source
     int64_t ipool_scratch_len = 0;
-    int32_t* hinfo = nullptr;  // pinned host mirror of info (rank, error flag, sigma)
+    int32_t* hinfo = nullptr;      // pinned host words (rank, error flag, sigma, pivot columns)
+    int32_t* hinfo_dev = nullptr;  // the same words as seen from the device: leaves write them directly
     void release() {
         double* ds[] = {W, tmp1, tmp2, dd, de, xinv, yy, dvec, tinv};
         for (double* p : ds) if (p) (void)hipFree(p);
@@ -243,7 +244,9 @@ struct Workspace {
             throw Err(PLDL_ENOMEM, "alloc");
         }
         ipool_scratch = ipool + ipool_len;
-        if (hipHostMalloc((void**)&hinfo, 1024 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        if (hipHostMalloc((void**)&hinfo, 1024 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+            hipHostGetDevicePointer((void**)&hinfo_dev, hinfo, 0) != hipSuccess) {
+            (void)hipGetLastError();
             release();
             throw Err(PLDL_ENOMEM, "pinned alloc");
         }
@@ -297,9 +300,14 @@ struct Engine {
     MatV vrow(int64_t r0, int64_t c0) { return MatV{W + r0 * ld + c0, ld, 1}; }  // W[r0+i][c0+j]
     MatV vcol(int64_t r0, int64_t c0) { return MatV{W + r0 * ld + c0, 1, ld}; }  // W[r0+j][c0+i]
 
+    // words the device wrote into `info` (device memory): copied back after the queued work
     int32_t* read_info(int cnt) {
-        auto t0 = std::chrono::steady_clock::now();
         HIPCHK(hipMemcpyAsync(ws.hinfo, ws.info, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        return read_host();
+    }
+    // words the device wrote straight into the pinned host words: only a wait
+    int32_t* read_host() {
+        auto t0 = std::chrono::steady_clock::now();
         HIPCHK(hipStreamSynchronize(st));
         if (prof->on && !prof->light) {   // (stamps are collected when their slots run out, or at pldl_profile)
             prof->host_wait(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
@@ -436,15 +444,13 @@ struct Engine {
     int64_t bc(int64_t lo, int64_t hi) {
         int s = (int)(hi - lo);
         REQUIRE(s >= 1 && s <= 128);
-        LAUNCH(PLDL_CLASS_BASE_CASE, k_bc_leaf, dim3(1), dim3(1024), 0, st, W, ld, lo, s, F, itab, ws.dd, ws.de, ws.info + 1, ws.info);
-        int32_t* h = read_info(1 + s);
+        LAUNCH(PLDL_CLASS_BASE_CASE, k_bc_leaf, dim3(1), dim3(1024), 0, st, W, ld, lo, s, F, itab, ws.dd, ws.de, ws.sig,
+               ws.hinfo_dev, ws.hinfo_dev + 1);
+        int32_t* h = read_host();
         int64_t r = h[0];
         bool ident = true;
         for (int q = 0; q < s; ++q) ident &= (h[1 + q] == q);
-        if (!ident) {
-            HIPCHK(hipMemcpyAsync(ws.sig, ws.info + 1, s * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
-            perm_sym(lo, hi, ws.sig, 1 | 4 | 8);
-        }
+        if (!ident) perm_sym(lo, hi, ws.sig, 1 | 4 | 8);
         return r;
     }
 
@@ -584,8 +590,12 @@ struct Engine {
     int32_t* reorder_src(const int32_t* snap, const int32_t* cur, int64_t len) {
         int32_t* inv = ws.ipool_scratch;   // indexed by original index (< max(TR, TC))
         int32_t* src = ws.ipool_scratch + ws.ipool_scratch_len / 2;
-        LAUNCH(PLDL_CLASS_OTHER, k_inv_scatter, dim3(nblk(len)), dim3(256), 0, st, snap, len, inv);
-        LAUNCH(PLDL_CLASS_OTHER, k_src_gather, dim3(nblk(len)), dim3(256), 0, st, cur, len, inv, src);
+        if (len <= 16384) {
+            LAUNCH(PLDL_CLASS_OTHER, k_reorder_src_1wg, dim3(1), dim3(1024), 0, st, snap, cur, len, inv, src);
+        } else {
+            LAUNCH(PLDL_CLASS_OTHER, k_inv_scatter, dim3(nblk(len)), dim3(256), 0, st, snap, len, inv);
+            LAUNCH(PLDL_CLASS_OTHER, k_src_gather, dim3(nblk(len)), dim3(256), 0, st, cur, len, inv, src);
+        }
         return src;
     }
     // reorder T rows [j0, j0+len) (Y columns) by src, in T columns [i0, i0+ni) (Y rows)
@@ -611,6 +621,10 @@ struct Engine {
     // idx[a + q] <- idx[a + src[q]]
     void idx_reorder(int32_t* idx, int64_t a, int64_t len, const int32_t* src) {
         if (len <= 1) return;
+        if (len <= 16384) {
+            LAUNCH(PLDL_CLASS_OTHER, k_idx_reorder_1wg, dim3(1), dim3(1024), 0, st, idx, a, len, src);
+            return;
+        }
         LAUNCH(PLDL_CLASS_OTHER, k_idx_gather, dim3(nblk(len)), dim3(256), 0, st, idx, a, len, src, ws.tmpo);
         LAUNCH(PLDL_CLASS_OTHER, k_idx_copy, dim3(nblk(len)), dim3(256), 0, st, idx, a, len, ws.tmpo);
     }
@@ -686,8 +700,8 @@ struct Engine {
         int32_t* nzb = ws.info + 1024;
         while (R < m && cur < c1) {
             LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_leaf, dim3(1), dim3(1024), 0, st, T, ldT, a0 + R, (int)(m - R), cur, c1, F,
-                   itab, h, nh, ws.sig, ws.info, pR);
-            const int32_t* hi = read_info(16 + 64);
+                   itab, h, nh, ws.sig, ws.hinfo_dev, pR);
+            const int32_t* hi = read_host();
             const int64_t r = hi[0], cs = hi[1], w = hi[2];
             if (r == 0) break;   // the active rows are zero on [cur, c1)
             REQUIRE(R + r <= 64);

@@ -5,7 +5,7 @@
 namespace pldl {
 
 __global__ void k_bc_leaf(double* W, int64_t ld, int64_t lo, int s, Field F, const uint32_t* itab, double* dd,
-                          double* de, int32_t* sig_out, int32_t* rank_out);
+                          double* de, int32_t* sig_out, int32_t* rank_out, int32_t* hsig);
 __global__ void k_plduq_leaf(double* T, int64_t ld, int64_t a0, int m, int64_t c0, int64_t c1, Field F,
                              const uint32_t* itab, const int32_t* hint, int nhint, int32_t* rsig, int32_t* info,
                              int32_t* pR);
@@ -15,6 +15,8 @@ __global__ void k_slab_colsrc(PivList ord, PivList srt, int64_t c0, int64_t len,
 __global__ void k_inv_scatter(const int32_t* snap, int64_t len, int32_t* inv);
 __global__ void k_src_gather(const int32_t* cur, int64_t len, const int32_t* inv, int32_t* src);
 __global__ void k_rot_src(int64_t len, int64_t rot1, int32_t* src);
+__global__ void k_reorder_src_1wg(const int32_t* snap, const int32_t* cur, int64_t len, int32_t* inv, int32_t* src);
+__global__ void k_idx_reorder_1wg(int32_t* idx, int64_t a, int64_t len, const int32_t* src);
 __global__ void k_tcolperm(double* T, int64_t ld, int64_t j0, int64_t len, const int32_t* src, int64_t i0,
                            int64_t ni, double* tmp, int phase);
 __global__ void k_trowperm(double* T, int64_t ld, int64_t j0, int64_t nj, int64_t i0, int64_t len,

@@ -28,7 +28,7 @@ namespace pldl {
 // ===========================================================================
 __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t lo, int s, Field F,
                                                   const uint32_t* itab, double* dd, double* de,
-                                                  int32_t* sig_out, int32_t* rank_out) {
+                                                  int32_t* sig_out, int32_t* rank_out, int32_t* hsig) {
     __shared__ double colI[2][128], colJ[2][128];  // centered reduced columns, 0 on eliminated rows
     __shared__ int order[128], zeros[128], sig[128];
     __shared__ double bx[128], by[128];
@@ -246,6 +246,7 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
     if (tid < s) {
         W[(lo + tid) * ld + lo + tid] = dd[lo + tid];
         sig_out[tid] = sig[tid];
+        hsig[tid] = sig[tid];
     }
 }
 
@@ -535,6 +536,22 @@ __global__ void k_src_gather(const int32_t* cur, int64_t len, const int32_t* inv
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (q < len) src[q] = inv[cur[q]];
 }
+// Both steps above in one workgroup (len <= 16384): inv is written, then read
+// back by the same workgroup after a barrier.
+__global__ __launch_bounds__(1024) void k_reorder_src_1wg(const int32_t* snap, const int32_t* cur, int64_t len,
+                                                          int32_t* inv, int32_t* src) {
+    for (int64_t q = threadIdx.x; q < len; q += 1024) inv[snap[q]] = (int32_t)q;
+    __syncthreads();
+    for (int64_t q = threadIdx.x; q < len; q += 1024) src[q] = inv[cur[q]];
+}
+// idx[a + q] <- idx[a + src[q]] in one workgroup through LDS (len <= 16384)
+__global__ __launch_bounds__(1024) void k_idx_reorder_1wg(int32_t* idx, int64_t a, int64_t len, const int32_t* src) {
+    __shared__ int32_t buf[16384];
+    for (int64_t q = threadIdx.x; q < len; q += 1024) buf[q] = idx[a + src[q]];
+    __syncthreads();
+    for (int64_t q = threadIdx.x; q < len; q += 1024) idx[a + q] = buf[q];
+}
+
 // src[q] of the rotation that moves the first rot1 of len positions after the others
 __global__ void k_rot_src(int64_t len, int64_t rot1, int32_t* src) {
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
