@@ -60,6 +60,10 @@ __device__ __forceinline__ double finv(double a, const Field& F) {
 // ---------------------------------------------------------------------------
 // "No nonzero seen" value of the first-nonzero slots (a column index above any n).
 constexpr int32_t NZ_NONE = 0x7F7F7F7F;
+// Column chunk a PLDUQ leaf eliminates and the leaf's workgroup size (each
+// thread holds PLDUQ_CHUNK / (PLDUQ_THREADS / 64) entries in registers).
+constexpr int PLDUQ_CHUNK = 256;
+constexpr int PLDUQ_THREADS = 1024;
 // Most workgroups of a PLDUQ right-part update (one first-nonzero candidate each).
 constexpr int NZB_MAX = 2048;
 

@@ -699,7 +699,7 @@ struct Engine {
         int nh = nhint;
         int32_t* nzb = ws.info + 1024;
         while (R < m && cur < c1) {
-            LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_leaf, dim3(1), dim3(1024), 0, st, T, ldT, a0 + R, (int)(m - R), cur, c1, F,
+            LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_leaf, dim3(1), dim3(PLDUQ_THREADS), 0, st, T, ldT, a0 + R, (int)(m - R), cur, c1, F,
                    itab, h, nh, ws.sig, ws.hinfo_dev, pR);
             const int32_t* hi = read_host();
             const int64_t r = hi[0], cs = hi[1], w = hi[2];

@@ -253,8 +253,8 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
 // ===========================================================================
 // Rank-profile-revealing PLDUQ leaf (Sections 4.2 and 5 pivoting) on the
 // compact transposed copy T of Y (Y[i][j] = T[j][i], leading dimension ld):
-// rows [a0, a0+m) of Y (m <= 64), columns [c0, c1).  The kernel scans 256-wide
-// column chunks (from max(c0, *hint) when a hint is given: the first column a
+// rows [a0, a0+m) of Y (m <= 64), columns [c0, c1).  The kernel scans
+// PLDUQ_CHUNK-wide column chunks (from max(c0, *hint) when a hint is given: the first column a
 // preceding update found nonzero on these rows) until one holds a nonzero in
 // one of the rows, then eliminates that chunk in row order: a row's pivot is
 // the first nonzero of its reduced row among the chunk's non-pivot columns.
@@ -263,7 +263,8 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
 // stays zero: the loop visits only the rows of an exact nonzero-row mask,
 // i.e. one iteration per pivot.  Right-looking, the chunk in registers, kept
 // reduced (centered) after every update so that the zero tests are exact:
-// thread t owns row t%64 and columns t/64 + 16k (k < 16).  Every wave runs the
+// thread t owns row t%64 and columns t/64 + g k (g = PLDUQ_THREADS / 64 column
+// groups, k < PLDUQ_CHUNK / g).  Every wave runs the
 // pivot search itself (no serial thread); row, multiplier and mask vectors
 // are double buffered: three barriers per pivot.
 // Output, in place: the LU pack of the chunk with its rows in the new order
@@ -273,64 +274,70 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
 // info = {rank, chunk start, chunk width} and info[16 ..] = T rows of the r
 // pivot columns.
 // ===========================================================================
-__global__ __launch_bounds__(1024) void k_plduq_leaf(double* T, int64_t ld, int64_t a0, int m, int64_t c0,
+__global__ __launch_bounds__(PLDUQ_THREADS) void k_plduq_leaf(double* T, int64_t ld, int64_t a0, int m, int64_t c0,
                                                      int64_t c1, Field F, const uint32_t* itab,
                                                      const int32_t* hint, int nhint, int32_t* rsig,
                                                      int32_t* info, int32_t* pR) {
-    __shared__ double rowI[2][256];   // centered reduced row (0 on pivot columns)
+    constexpr int NT = PLDUQ_THREADS, NG = NT / 64;          // threads, column groups (one per wave)
+    constexpr int CW = PLDUQ_CHUNK, KC = CW / NG;            // chunk width, columns per thread
+    static_assert(KC <= 64 && CW % 64 == 0 && CW <= 1024, "live mask and search sizes");
+    __shared__ double rowI[2][CW];    // centered reduced row (0 on pivot columns)
     __shared__ double fvec[2][64];    // centered multipliers of the rows below
-    __shared__ int ispc[256], cpiv[256];
+    __shared__ int ispc[CW], cpiv[CW];
     __shared__ int rpiv[64];
     __shared__ double pinvx[64];
-    __shared__ int wcnt[4];
-    __shared__ int rord[64], cord[256], rposs[64], cposs[256];
-    __shared__ unsigned long long wmask[2][16];
+    __shared__ int rord[64], cord[64], rposs[64];
+    __shared__ unsigned long long wmask[2][NG];
     const int tid = threadIdx.x, row = tid & 63, cg = tid >> 6, lane = tid & 63;
-    double y[16];
+    double y[KC];
     int64_t cs = c0;
     if (hint) {   // the minimum of the nhint candidates left by the preceding update
-        __shared__ int hred[16];
+        __shared__ int hred[NG];
         int v = NZ_NONE;
-        for (int k = tid; k < nhint; k += 1024) v = min(v, hint[k]);
+        for (int k = tid; k < nhint; k += NT) v = min(v, hint[k]);
         for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
         if (lane == 0) hred[cg] = v;
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 16; ++q) v = min(v, hred[q]);
+        for (int q = 0; q < NG; ++q) v = min(v, hred[q]);
         cs = max(c0, (int64_t)v);
     }
     int w = 0;
     // ---- scan for the first chunk with a nonzero on these rows
     for (;;) {
-        w = (int)min((int64_t)256, c1 - cs);
+        w = (int)min((int64_t)CW, c1 - cs);
         if (w <= 0) break;
         int nzf = 0;
+        // unconditional loads (coordinates clamped into the chunk, masked after) in
+        // groups of 16, so that a group is in flight together
+        const double* in_p = T + (cs + min(cg, w - 1)) * ld + a0 + min(row, m - 1);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            int col = cg + 16 * k;
-            double v = (row < m && col < w) ? T[(cs + col) * ld + a0 + row] : 0.0;
-            y[k] = fcen(v, F);
-            nzf |= (v != 0.0);
+        for (int k = 0; k < KC; ++k) {
+            const int col = cg + NG * k;
+            const double v = (col < w) ? in_p[(int64_t)NG * k * ld] : T[(cs + w - 1) * ld + a0 + min(row, m - 1)];
+            y[k] = (row < m && col < w) ? fcen(v, F) : 0.0;
+            nzf |= (row < m && col < w && v != 0.0);
+            if ((k & 15) == 15) __builtin_amdgcn_sched_barrier(0);
         }
         if (__syncthreads_or(nzf)) break;
-        cs += 256;
+        cs += CW;
     }
     if (w <= 0) {  // all rows are zero on [c0, c1)
         if (tid == 0) { info[0] = 0; info[1] = (int32_t)c1; info[2] = 0; }
         return;
     }
-    if (tid < 256) { ispc[tid] = 0; cpiv[tid] = -1; }
+    for (int e = tid; e < CW; e += NT) { ispc[e] = 0; cpiv[e] = -1; }
     if (tid < 64) rpiv[tid] = -1;
-    // live (not yet pivot) columns among this lane's 16, as a register bit mask
-    uint32_t live = 0;
+    // live (not yet pivot) columns among this lane's KC, as a register bit mask
+    uint64_t live = 0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
-        if (cg + 16 * k < w) live |= 1u << k;
+    for (int k = 0; k < KC; ++k)
+        if (cg + NG * k < w) live |= 1ull << k;
     // rows (bits) holding a nonzero on the live columns: per-wave ballots, OR-ed
     auto row_nz = [&]() {
         bool nz = false;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) nz |= ((live >> k) & 1u) && y[k] != 0.0;
+        for (int k = 0; k < KC; ++k) nz |= ((live >> k) & 1ull) && y[k] != 0.0;
         return nz;
     };
     {
@@ -342,20 +349,20 @@ __global__ __launch_bounds__(1024) void k_plduq_leaf(double* T, int64_t ld, int6
     for (;;) {
         unsigned long long rows_nz = 0;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) rows_nz |= wmask[mb][q];
+        for (int q = 0; q < NG; ++q) rows_nz |= wmask[mb][q];
         rows_nz &= (i >= 63) ? 0ull : (~0ull << (i + 1));
         if (rows_nz == 0) break;
         i = __ffsll((long long)rows_nz) - 1;
         const int b = r & 1;
         if (row == i) {
 #pragma unroll
-            for (int k = 0; k < 16; ++k) rowI[b][cg + 16 * k] = ((live >> k) & 1u) ? y[k] : 0.0;
+            for (int k = 0; k < KC; ++k) rowI[b][cg + NG * k] = ((live >> k) & 1ull) ? y[k] : 0.0;
         }
         __syncthreads();
         // every wave finds the first nonzero of the row (lowest column index); the
         // mask guarantees there is one
         int c = -1;
-        for (int q = 0; q < 4 && c < 0; ++q) {
+        for (int q = 0; q < CW / 64 && c < 0; ++q) {
             unsigned long long bal = __ballot(rowI[b][q * 64 + lane] != 0.0);
             if (bal) c = q * 64 + __ffsll((long long)bal) - 1;
         }
@@ -363,28 +370,31 @@ __global__ __launch_bounds__(1024) void k_plduq_leaf(double* T, int64_t ld, int6
         const double xi = itab ? (double)itab[(int)x] : finv(x, F);
         // this lane's columns: the pivot column leaves the live set
 #pragma unroll
-        for (int k = 0; k < 16; ++k)
-            if (cg + 16 * k == c) live &= ~(1u << k);
+        for (int k = 0; k < KC; ++k)
+            if (cg + NG * k == c) live &= ~(1ull << k);
         if (tid == 0) { rpiv[i] = r; cpiv[c] = r; pinvx[r] = xi; ispc[c] = 1; }
         // multipliers of the rows below: f = Y[i'][c] / x  (owners of column c)
-        if (cg == (c & 15)) {
+        if (cg == (c % NG)) {
             double v = 0.0;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) v = (k == (c >> 4)) ? y[k] : v;
+            for (int k = 0; k < KC; ++k) v = (k == c / NG) ? y[k] : v;
             fvec[b][row] = (row > i && row < m) ? fredc(v * xi, F) : 0.0;
         }
         __syncthreads();
         const double f = fvec[b][row];
-        double rw[16];
+        // in groups of 8 columns (the barrier keeps the compiler from hoisting every
+        // LDS read of the row ahead of the arithmetic: registers stay at y plus a group)
 #pragma unroll
-        for (int k = 0; k < 16; ++k) rw[k] = rowI[b][cg + 16 * k];
+        for (int k0 = 0; k0 < KC; k0 += 8) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) y[k] = fredc(fma(-f, rw[k], y[k]), F);
+            for (int k = k0; k < k0 + 8; ++k) y[k] = fredc(fma(-f, rowI[b][cg + NG * k], y[k]), F);
+            __builtin_amdgcn_sched_barrier(0);
+        }
         // the pivot column now stores the multipliers (L) of the rows below
-        if (cg == (c & 15) && row > i && row < m) {
+        if (cg == (c % NG) && row > i && row < m) {
 #pragma unroll
-            for (int k = 0; k < 16; ++k)
-                if (k == (c >> 4)) y[k] = f;
+            for (int k = 0; k < KC; ++k)
+                if (k == c / NG) y[k] = f;
         }
         ++r;
         mb ^= 1;
@@ -403,17 +413,9 @@ __global__ __launch_bounds__(1024) void k_plduq_leaf(double* T, int64_t ld, int6
             rposs[tid] = pos;
         }
     }
-    const bool npc = (tid < 256) && (tid < w) && cpiv[tid] < 0;
-    const unsigned long long balc = __ballot(npc);
-    if (tid < 256 && lane == 0) wcnt[tid >> 6] = __popcll(balc);
-    __syncthreads();
-    if (tid < w) {
-        int off = 0;
-        for (int q = 0; q < (tid >> 6); ++q) off += wcnt[q];
-        int pos = npc ? r + off + __popcll(balc & ((1ull << lane) - 1ull)) : cpiv[tid];
-        cord[pos] = tid;
-        cposs[tid] = pos;
-    }
+    // the pivot columns in pivot order (the other columns stay where they are)
+    for (int e = tid; e < w; e += NT)
+        if (cpiv[e] >= 0) cord[cpiv[e]] = e;
     __syncthreads();
     if (tid == 0) { info[0] = r; info[1] = (int32_t)cs; info[2] = w; }
     if (tid < r) info[16 + tid] = (int32_t)(cs + cord[tid]);   // T row of pivot tid's column
@@ -424,18 +426,22 @@ __global__ __launch_bounds__(1024) void k_plduq_leaf(double* T, int64_t ld, int6
     // (columns stay in place: the slab moves its pivot columns once, at its end)
     if (row < m) {
         const int a = rposs[row];
+        double* out_p = T + (cs + cg) * ld + a0 + a;   // column cg + NG k is NG k ld further
+        const int64_t step = (int64_t)NG * ld;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            int col = cg + 16 * k;
-            if (col >= w) continue;
-            const int bpos = cposs[col];
-            double v = fred(y[k], F);
-            double out;
-            if (a == bpos && a < r) out = v;                           // D
-            else if (bpos < a && bpos < r) out = v;                    // L / M (stored multipliers)
-            else if (a < bpos && a < r) out = fmulm(v, pinvx[a], F);   // U / V
-            else out = 0.0;
-            T[(cs + col) * ld + a0 + a] = out;
+        for (int k = 0; k < KC; ++k) {
+            const int col = cg + NG * k;
+            if (col < w) {
+                const int bpos = cpiv[col] >= 0 ? cpiv[col] : (1 << 20);   // pivot index of the column
+                const double v = fred(y[k], F);
+                double out;
+                if (a == bpos && a < r) out = v;                           // D
+                else if (bpos < a && bpos < r) out = v;                    // L / M (stored multipliers)
+                else if (a < bpos && a < r) out = fmulm(v, pinvx[a], F);   // U / V
+                else out = 0.0;
+                out_p[k * step] = out;
+            }
+            if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
         }
     }
     __syncthreads();
