@@ -9,12 +9,17 @@
 // its precedence.  The result is the canonical order of that elimination; it
 // reveals the rank profile matrix (Theorem 1) like the recursive cascade.
 //
-// The Schur complement lives in a private FP64 slot (lower triangle, row-major,
-// leading dimension n), updated right-looking with delayed reduction: an
-// update adds at most 3 (p-1)^2/4 to an entry, and the alive part is reduced
-// in place before F.kred such terms can accumulate.  The multiplier of alive
-// row k for pivot column c is stored at the lower-triangle position of (k, c):
-// when c is eliminated, entry (c, k) of a row k < c is no longer needed.
+// The Schur complement lives in a private slot as exact residues in FP32
+// (|value| < p < 2^23), lower triangle stored by columns: entry (k, l), k >= l,
+// at S[l * n + k], so the column a pivot step reads is contiguous.  Updates are
+// lazy: a 1x1 pivot contributes one rank-1 term u v^T, a 2x2 pivot two; up to
+// KMAX terms wait in LDS (u by row, v by column).  A pivot step reads its
+// column from the slot and subtracts the waiting terms for that column only;
+// when the window is full, one pass over the alive triangle applies all of
+// them (FP64 accumulation of at most KMAX products below (p-1)^2/4 each onto a
+// reduced value: far below 2^53) and stores the reduced result.  The
+// multiplier of alive row k for pivot column c goes to the position of (k, c)
+// as soon as c is eliminated; a row set aside leaves zeros in its column.
 // Everything happens on the device (no host synchronisation), so the call can
 // be captured in a graph.
 #include "../../include/pldl.h"
@@ -25,6 +30,9 @@ namespace pldl {
 namespace {
 
 constexpr int NB_MAX = 512;   // largest order of a batched matrix
+constexpr int KMAX = 8;       // rank-1 terms applied per pass over the triangle
+constexpr int NWAVE = 16;     // waves per workgroup (1024 threads)
+constexpr int CG = 4;         // columns whose loads are in flight together in a pass
 
 struct BatchArgs {
     int64_t batch;
@@ -37,7 +45,7 @@ struct BatchArgs {
     int32_t* const* rpm;
     int64_t* rank;
     int32_t* status;
-    double* ws;          // one NB_MAX^2 slot per workgroup
+    float* ws;           // one NB_MAX^2 slot per workgroup
     int32_t* queue;      // next matrix index
     Field F;
     const uint32_t* itab;
@@ -52,22 +60,78 @@ __device__ __forceinline__ void st_out(void* A, int32_t dtype, int64_t off, doub
     else ((double*)A)[off] = v;
 }
 
-__global__ __launch_bounds__(1024) void k_factor_batched(BatchArgs g) {
-    __shared__ double colI[2][NB_MAX], colJ[NB_MAX];
-    __shared__ double va[NB_MAX], vb[NB_MAX], ve[NB_MAX], vf[NB_MAX];
-    __shared__ uint8_t alv[NB_MAX];
-    __shared__ int order[NB_MAX], zeros[NB_MAX], sig[NB_MAX];
-    __shared__ double bx[NB_MAX], by[NB_MAX];
-    __shared__ uint8_t bt[NB_MAX];
-    __shared__ int64_t s_m;
+struct BatchShared {
+    float u[KMAX][NB_MAX];     // row factors of the waiting terms
+    float v[NB_MAX][KMAX];     // column factors of the waiting terms
+    double colI[NB_MAX], colJ[NB_MAX];
+    double bx[NB_MAX], by[NB_MAX];
+    int order[NB_MAX], zeros[NB_MAX], sig[NB_MAX];
+    uint8_t alv[NB_MAX], bt[NB_MAX];
+    int64_t m;
+};
+
+// Applies the npend waiting terms to every alive entry (k, l), k >= l >= i0 (all
+// alive indices are >= i0).  Work items are 64x64 tiles of the lower triangle,
+// dealt round-robin to the waves; a lane owns one row k of its tile and walks
+// the alive columns of the tile CG at a time, all CG loads issued before use.
+__device__ void flush_terms(BatchShared& sh, float* S, int n, int i0, int npend, const Field& F, int wave,
+                            int lane) {
+    const int c0 = i0 >> 6, nch = (n + 63) >> 6;
+    int tile = 0;
+    for (int c = c0; c < nch; ++c)
+        for (int b = c0; b <= c; ++b, ++tile) {
+            if (tile % NWAVE != wave) continue;
+            const int k = 64 * c + lane;
+            const bool kal = k < n && sh.alv[k];
+            float uk[KMAX];
+#pragma unroll
+            for (int t = 0; t < KMAX; ++t) uk[t] = (kal && t < npend) ? sh.u[t][k] : 0.0f;
+            const int lb = 64 * b + lane;
+            uint64_t live = __ballot(lb < n && sh.alv[lb]);
+            while (live) {
+                int ls[CG];
+                float sv[CG];
+#pragma unroll
+                for (int q = 0; q < CG; ++q) {
+                    ls[q] = live ? 64 * b + __ffsll((long long)live) - 1 : -1;
+                    live &= live - 1;
+                }
+#pragma unroll
+                for (int q = 0; q < CG; ++q) {
+                    const int l = ls[q];
+                    sv[q] = (l >= 0 && kal && l <= k) ? S[l * n + k] : 0.0f;
+                }
+#pragma unroll
+                for (int q = 0; q < CG; ++q) {
+                    const int l = ls[q];
+                    if (l >= 0 && kal && l <= k) {
+                        const float* vl = sh.v[l];
+                        double acc = (double)sv[q];
+#pragma unroll
+                        for (int t = 0; t < KMAX; ++t) acc = fma(-(double)uk[t], (double)vl[t], acc);
+                        S[l * n + k] = (float)fredc(acc, F);
+                    }
+                }
+            }
+        }
+}
+
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_factor_batched(BatchArgs g) {
+    __shared__ BatchShared sh;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const Field F = g.F;
-    double* S = g.ws + (int64_t)blockIdx.x * NB_MAX * NB_MAX;
+    float* S = g.ws + (int64_t)blockIdx.x * NB_MAX * NB_MAX;
+    // the term buffers only ever hold finite residues: a zero row factor then
+    // cancels whatever a column factor slot holds
+    for (int q = tid; q < KMAX * NB_MAX; q += 1024) {
+        (&sh.u[0][0])[q] = 0.0f;
+        (&sh.v[0][0])[q] = 0.0f;
+    }
 
     for (;;) {
-        if (tid == 0) s_m = atomicAdd(g.queue, 1);
+        if (tid == 0) sh.m = atomicAdd(g.queue, 1);
         __syncthreads();
-        const int64_t mi = s_m;
+        const int64_t mi = sh.m;
         __syncthreads();
         if (mi >= g.batch) return;
         const int n = (int)g.n[mi];
@@ -82,154 +146,161 @@ __global__ __launch_bounds__(1024) void k_factor_batched(BatchArgs g) {
             if (tid == 0) { g.status[mi] = 0; g.rank[mi] = 0; }
             continue;
         }
-        // ---- load the lower triangle (centered), check the range
+        // ---- load the lower triangle (centered) column by column, check the range
         int bad = 0;
-        for (int k = wave; k < n; k += 16)
-            for (int l = lane; l <= k; l += 64) {
+        for (int l = wave; l < n; l += NWAVE)
+            for (int k = l + lane; k < n; k += 64) {
                 const double v = ld_in(A, g.dtype, (int64_t)k * lda + l);
                 bad |= (v >= F.p || v < 0.0);
-                S[k * n + l] = fcen(v, F);
+                S[l * n + k] = (float)fcen(v, F);
             }
-        for (int k = tid; k < n; k += 1024) alv[k] = 1;
+        for (int k = tid; k < n; k += 1024) sh.alv[k] = 1;
         bad = __syncthreads_or(bad);
         if (bad && g.check_range) {
             if (tid == 0) { g.status[mi] = PLDL_ERANGE; g.rank[mi] = 0; }
             continue;
         }
         // ---- elimination
-        int r = 0, nz = 0, grow = 0, step = 0;
+        int r = 0, nz = 0, np = 0;
         for (int i = 0; i < n; ++i) {
-            if (!alv[i]) continue;
-            const int b = step & 1;
-            ++step;
-            // column i of the Schur complement (= row i), reduced; alive rows only (all >= i)
-            for (int k = tid; k < n; k += 1024) colI[b][k] = alv[k] ? fredc(S[k * n + i], F) : 0.0;
+            if (!sh.alv[i]) continue;
+            if (np + 2 > KMAX) {
+                flush_terms(sh, S, n, i, np, F, wave, lane);
+                np = 0;
+                __syncthreads();
+            }
+            // column i of the Schur complement (alive rows, all >= i), waiting terms applied
+            for (int k = tid; k < n; k += 1024) {
+                double c = 0.0;
+                if (k >= i && sh.alv[k]) {
+                    double a = (double)S[i * n + k];
+                    for (int t = 0; t < np; ++t) a = fma(-(double)sh.u[t][k], (double)sh.v[i][t], a);
+                    c = fredc(a, F);
+                }
+                sh.colI[k] = c;
+            }
             __syncthreads();
             int j = -1;
             for (int q = i >> 6; q * 64 < n && j < 0; ++q) {
                 const int kk = q * 64 + lane;
-                const unsigned long long bal = __ballot(kk < n && colI[b][kk] != 0.0);
+                const unsigned long long bal = __ballot(kk < n && sh.colI[kk] != 0.0);
                 if (bal) j = q * 64 + __ffsll((long long)bal) - 1;
             }
-            if (j < 0) {   // zero row: set aside, precedence kept
-                if (tid == 0) { zeros[nz] = i; alv[i] = 0; }
+            if (j < 0) {   // zero row: set aside, precedence kept, its column left zero
+                for (int k = tid; k < n; k += 1024)
+                    if (k > i && sh.alv[k]) S[i * n + k] = 0.0f;
+                if (tid == 0) { sh.zeros[nz] = i; sh.alv[i] = 0; }
                 ++nz;
                 __syncthreads();
                 continue;
             }
-            if (j == i) {  // 1x1 pivot x: S -= c c^T / x, L(k, i) = c_k / x
-                const double x = fcan(colI[b][i], F);
+            if (j == i) {  // 1x1 pivot x: term b c^T with b = c / x; L(k, i) = b_k
+                const double x = fcan(sh.colI[i], F);
                 const double xi = g.itab ? (double)g.itab[(int)x] : finv(x, F);
-                if (tid == 0) { bx[r] = x; bt[r] = 1; order[r] = i; }
-                for (int k = wave; k < n; k += 16) {
-                    if (k == i || !alv[k]) continue;
-                    const double bk = fredc(colI[b][k] * xi, F);
-                    for (int l = lane; l <= k; l += 64)
-                        if (l != i && alv[l]) S[k * n + l] = fma(-bk, colI[b][l], S[k * n + l]);
-                    if (lane == 0) S[k * n + i] = fcan(bk, F);
+                for (int k = tid; k < n; k += 1024) {
+                    float u = 0.0f, v = 0.0f;
+                    if (k > i && sh.alv[k]) {
+                        const double bk = fredc(sh.colI[k] * xi, F);
+                        S[i * n + k] = (float)fcan(bk, F);
+                        u = (float)bk;
+                        v = (float)sh.colI[k];
+                    }
+                    sh.u[np][k] = u;
+                    sh.v[k][np] = v;
                 }
-                if (tid == 0) alv[i] = 0;
-                grow += 1;
+                if (tid == 0) { sh.bx[r] = x; sh.bt[r] = 1; sh.order[r] = i; sh.alv[i] = 0; }
+                np += 1;
                 r += 1;
             } else {       // 2x2 pivot on (i, j), j > i
                 for (int k = tid; k < n; k += 1024) {
-                    const int hi = k > j ? k : j, lo = k > j ? j : k;
-                    colJ[k] = alv[k] ? fredc(S[hi * n + lo], F) : 0.0;
+                    double c = 0.0;
+                    if (k >= i && sh.alv[k]) {
+                        const int hi = k > j ? k : j, lo = k > j ? j : k;
+                        double a = (double)S[lo * n + hi];
+                        for (int t = 0; t < np; ++t) a = fma(-(double)sh.u[t][hi], (double)sh.v[lo][t], a);
+                        c = fredc(a, F);
+                    }
+                    sh.colJ[k] = c;
                 }
                 __syncthreads();
-                const double x = fcan(colI[b][j], F), y = fcan(colJ[j], F);
+                const double x = fcan(sh.colI[j], F), y = fcan(sh.colJ[j], F);
                 const double xi = g.itab ? (double)g.itab[(int)x] : finv(x, F);
                 double w, d22, lji;
                 if (F.ip == 2) { w = y; d22 = y; lji = 0.0; }
                 else { w = fmulm(y, F.inv2, F); d22 = 0.0; lji = fmulm(w, xi, F); }
-                if (tid == 0) {
-                    bx[r] = x; by[r] = (F.ip == 2) ? y : 0.0; bt[r] = 2; bt[r + 1] = 0;
-                    order[r] = i; order[r + 1] = j;
-                }
-                // per-row coefficients: b_k = c_k / x, e_k = d_k - w b_k, a_k = e_k / x, f_k = d22 b_k
+                // per row: b_k = c_k / x, e_k = d_k - w b_k, a_k = e_k / x, f_k = d22 b_k;
+                // terms (e + f) b^T and c a^T; L(k, i) = a_k, L(k, j) = b_k
                 for (int k = tid; k < n; k += 1024) {
-                    const bool al = alv[k] && k != i && k != j;
-                    const double ci = al ? colI[b][k] : 0.0, cj = al ? colJ[k] : 0.0;
-                    const double bk = fredc(ci * xi, F);
-                    const double ek = fredc(cj - fredc(w * bk, F), F);
-                    vb[k] = bk;
-                    ve[k] = ek;
-                    va[k] = fredc(ek * xi, F);
-                    vf[k] = fredc(d22 * bk, F);
-                }
-                __syncthreads();
-                // S[k][l] -= e_k b_l + c_k a_l + f_k b_l; L(k, i) = a_k, L(k, j) = b_k
-                for (int k = wave; k < n; k += 16) {
-                    if (k == i || k == j || !alv[k]) continue;
-                    const double ek = ve[k], ck = colI[b][k], fk = vf[k];
-                    for (int l = lane; l <= k; l += 64) {
-                        if (l == i || l == j || !alv[l]) continue;
-                        double t = S[k * n + l];
-                        t = fma(-ek, vb[l], t);
-                        t = fma(-ck, va[l], t);
-                        t = fma(-fk, vb[l], t);
-                        S[k * n + l] = t;
+                    float u0 = 0.0f, v0 = 0.0f, u1 = 0.0f, v1 = 0.0f;
+                    if (k > i && k != j && sh.alv[k]) {
+                        const double ck = sh.colI[k], dk = sh.colJ[k];
+                        const double bk = fredc(ck * xi, F);
+                        const double ek = fredc(dk - fredc(w * bk, F), F);
+                        const double ak = fredc(ek * xi, F);
+                        const double fk = fredc(d22 * bk, F);
+                        S[i * n + k] = (float)fcan(ak, F);
+                        if (k > j) S[j * n + k] = (float)fcan(bk, F);
+                        else S[k * n + j] = (float)fcan(bk, F);
+                        u0 = (float)fredc(ek + fk, F);
+                        v0 = (float)bk;
+                        u1 = (float)ck;
+                        v1 = (float)ak;
                     }
-                    if (lane == 0) {
-                        S[k * n + i] = fcan(va[k], F);
-                        if (k > j) S[k * n + j] = fcan(vb[k], F);
-                        else S[j * n + k] = fcan(vb[k], F);
-                    }
+                    sh.u[np][k] = u0;
+                    sh.v[k][np] = v0;
+                    sh.u[np + 1][k] = u1;
+                    sh.v[k][np + 1] = v1;
                 }
-                if (tid == 0) { S[j * n + i] = lji; alv[i] = 0; alv[j] = 0; }
-                grow += 3;
+                if (tid == 0) {
+                    sh.bx[r] = x; sh.by[r] = (F.ip == 2) ? y : 0.0; sh.bt[r] = 2; sh.bt[r + 1] = 0;
+                    sh.order[r] = i; sh.order[r + 1] = j;
+                    S[i * n + j] = (float)lji;
+                    sh.alv[i] = 0; sh.alv[j] = 0;
+                }
+                np += 2;
                 r += 2;
             }
             __syncthreads();
-            if (2 * (grow + 3) > F.kred) {   // reduce the alive part well before the exactness bound
-                for (int k = wave; k < n; k += 16) {
-                    if (!alv[k]) continue;
-                    for (int l = lane; l <= k; l += 64)
-                        if (alv[l]) S[k * n + l] = fredc(S[k * n + l], F);
-                }
-                grow = 0;
-                __syncthreads();
-            }
         }
         // ---- output in place: order = pivots then zero rows
-        for (int q = tid; q < n; q += 1024) sig[q] = q < r ? order[q] : zeros[q - r];
+        for (int q = tid; q < n; q += 1024) sh.sig[q] = q < r ? sh.order[q] : sh.zeros[q - r];
         __syncthreads();
-        for (int q = wave; q < n; q += 16)
+        for (int q = wave; q < n; q += NWAVE)
             for (int c = lane; c < q; c += 64) {
                 double v = 0.0;
                 if (c < r) {
-                    const int a = sig[q], bb = sig[c];
-                    v = fred(a > bb ? S[a * n + bb] : S[bb * n + a], F);
+                    const int a = sh.sig[q], bb = sh.sig[c];
+                    v = fred(a > bb ? (double)S[bb * n + a] : (double)S[a * n + bb], F);
                 }
                 st_out(A, g.dtype, (int64_t)q * lda + c, v);
             }
         if (tid == 0) {
             int q = 0;
             for (int t = 0; t < r;) {
-                if (bt[t] == 1) {
-                    colJ[q] = bx[t]; va[q] = 0.0;
+                if (sh.bt[t] == 1) {
+                    sh.colJ[q] = sh.bx[t]; sh.colI[q] = 0.0;
                     q += 1; t += 1;
                 } else {
-                    colJ[q] = 0.0; va[q] = bx[t];
-                    colJ[q + 1] = by[t]; va[q + 1] = 0.0;
+                    sh.colJ[q] = 0.0; sh.colI[q] = sh.bx[t];
+                    sh.colJ[q + 1] = sh.by[t]; sh.colI[q + 1] = 0.0;
                     q += 2; t += 2;
                 }
             }
-            for (; q < n; ++q) { colJ[q] = 0.0; va[q] = 0.0; }
+            for (; q < n; ++q) { sh.colJ[q] = 0.0; sh.colI[q] = 0.0; }
             g.rank[mi] = r;
             g.status[mi] = 0;
         }
         __syncthreads();
         for (int q = tid; q < n; q += 1024) {
-            st_out(A, g.dtype, (int64_t)q * lda + q, colJ[q]);
-            st_out(g.e[mi], g.dtype, q, va[q]);
-            g.perm[mi][q] = sig[q];
+            st_out(A, g.dtype, (int64_t)q * lda + q, sh.colJ[q]);
+            st_out(g.e[mi], g.dtype, q, sh.colI[q]);
+            g.perm[mi][q] = sh.sig[q];
             g.rpm[mi][q] = -1;
         }
         __syncthreads();
         for (int t = tid; t < r; t += 1024) {
-            if (bt[t] == 1) g.rpm[mi][order[t]] = order[t];
-            else if (bt[t] == 2) { g.rpm[mi][order[t]] = order[t + 1]; g.rpm[mi][order[t + 1]] = order[t]; }
+            if (sh.bt[t] == 1) g.rpm[mi][sh.order[t]] = sh.order[t];
+            else if (sh.bt[t] == 2) { g.rpm[mi][sh.order[t]] = sh.order[t + 1]; g.rpm[mi][sh.order[t + 1]] = sh.order[t]; }
         }
         __syncthreads();
     }
@@ -241,15 +312,15 @@ __global__ void k_zero_counter(int32_t* q) { *q = 0; }
 
 int batched_nb_max() { return NB_MAX; }
 
-size_t batched_slot_bytes() { return (size_t)NB_MAX * NB_MAX * sizeof(double); }
+size_t batched_slot_bytes() { return (size_t)NB_MAX * NB_MAX * sizeof(float); }
 
 void launch_factor_batched(hipStream_t s, const Field& F, const uint32_t* itab, int64_t batch, const int64_t* n,
                            void* const* A, const int64_t* lda, int32_t dtype, void* const* e, int32_t* const* perm,
-                           int32_t* const* rpm, int64_t* rank, int32_t* status, int check_range, double* ws,
+                           int32_t* const* rpm, int64_t* rank, int32_t* status, int check_range, void* ws,
                            int slots, int32_t* queue) {
     BatchArgs g{};
     g.batch = batch; g.n = n; g.A = A; g.lda = lda; g.dtype = dtype; g.e = e; g.perm = perm; g.rpm = rpm;
-    g.rank = rank; g.status = status; g.ws = ws; g.queue = queue; g.F = F; g.itab = itab;
+    g.rank = rank; g.status = status; g.ws = (float*)ws; g.queue = queue; g.F = F; g.itab = itab;
     g.check_range = check_range;
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, queue);
     hipLaunchKernelGGL(k_factor_batched, dim3((unsigned)slots), dim3(1024), 0, s, g);

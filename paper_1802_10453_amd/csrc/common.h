@@ -139,7 +139,7 @@ int batched_nb_max();
 size_t batched_slot_bytes();
 void launch_factor_batched(hipStream_t s, const Field& F, const uint32_t* itab, int64_t batch, const int64_t* n,
                            void* const* A, const int64_t* lda, int32_t dtype, void* const* e, int32_t* const* perm,
-                           int32_t* const* rpm, int64_t* rank, int32_t* status, int check_range, double* ws,
+                           int32_t* const* rpm, int64_t* rank, int32_t* status, int check_range, void* ws,
                            int slots, int32_t* queue);
 
 // Products below this many flops stay on FP64 inside a factorization.

@@ -790,7 +790,7 @@ struct pldl_ctx {
             }
         return best;
     }
-    double* bws = nullptr;     // batched factorizations: one slot per persistent workgroup
+    void* bws = nullptr;       // batched factorizations: one slot per persistent workgroup
     int bslots = 0;
     int32_t* bqueue = nullptr;
     // an Engine on this context's workspace, products on `path`
