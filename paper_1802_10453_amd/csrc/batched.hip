@@ -30,9 +30,10 @@ namespace pldl {
 namespace {
 
 constexpr int NB_MAX = 512;   // largest order of a batched matrix
-constexpr int KMAX = 8;       // rank-1 terms applied per pass over the triangle
+constexpr int KMAX = 12;       // rank-1 terms applied per pass over the triangle
 constexpr int NWAVE = 16;     // waves per workgroup (1024 threads)
-constexpr int CG = 4;         // columns whose loads are in flight together in a pass
+constexpr int CG = 8;         // columns whose loads are in flight together in a pass
+static_assert(NB_MAX <= 1024, "one thread per row of a batched matrix");
 
 struct BatchArgs {
     int64_t batch;
@@ -87,6 +88,7 @@ __device__ void flush_terms(BatchShared& sh, float* S, int n, int i0, int npend,
 #pragma unroll
             for (int t = 0; t < KMAX; ++t) uk[t] = (kal && t < npend) ? sh.u[t][k] : 0.0f;
             const int lb = 64 * b + lane;
+            const int kc = k < n ? k : n - 1;   // in-bounds row for lanes past the end
             uint64_t live = __ballot(lb < n && sh.alv[lb]);
             while (live) {
                 int ls[CG];
@@ -96,11 +98,10 @@ __device__ void flush_terms(BatchShared& sh, float* S, int n, int i0, int npend,
                     ls[q] = live ? 64 * b + __ffsll((long long)live) - 1 : -1;
                     live &= live - 1;
                 }
+                // every load unconditional and in bounds (l, kc < n), so all CG are in flight
+                // together; values of lanes or columns that take no update are not used
 #pragma unroll
-                for (int q = 0; q < CG; ++q) {
-                    const int l = ls[q];
-                    sv[q] = (l >= 0 && kal && l <= k) ? S[l * n + k] : 0.0f;
-                }
+                for (int q = 0; q < CG; ++q) sv[q] = S[(ls[q] >= 0 ? ls[q] : ls[0]) * n + kc];
 #pragma unroll
                 for (int q = 0; q < CG; ++q) {
                     const int l = ls[q];
@@ -160,20 +161,34 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             if (tid == 0) { g.status[mi] = PLDL_ERANGE; g.rank[mi] = 0; }
             continue;
         }
-        // ---- elimination
+        // ---- elimination; thread k owns row k (n <= NB_MAX <= 1024)
         int r = 0, nz = 0, np = 0;
+        const int kc = tid < n ? tid : n - 1;   // in-bounds row for the unconditional column loads
+        float pre = 0.0f;                       // slot column pre_i at row kc, loaded one step ahead
+        int pre_i = -1;
         for (int i = 0; i < n; ++i) {
             if (!sh.alv[i]) continue;
             if (np + 2 > KMAX) {
                 flush_terms(sh, S, n, i, np, F, wave, lane);
                 np = 0;
+                pre_i = -1;
                 __syncthreads();
             }
+            // Column i of the slot changes only in a pass over the triangle (pivot steps
+            // write multipliers to eliminated positions only), so the copy loaded during
+            // the previous step is current unless a pass ran since.  The next column is
+            // loaded now, ahead of its step.
+            const float raw = pre_i == i ? pre : S[i * n + kc];
+            if (i + 1 < n) {
+                pre = S[(i + 1) * n + kc];
+                pre_i = i + 1;
+            }
             // column i of the Schur complement (alive rows, all >= i), waiting terms applied
-            for (int k = tid; k < n; k += 1024) {
+            if (tid < n) {
+                const int k = tid;
                 double c = 0.0;
                 if (k >= i && sh.alv[k]) {
-                    double a = (double)S[i * n + k];
+                    double a = (double)raw;
                     for (int t = 0; t < np; ++t) a = fma(-(double)sh.u[t][k], (double)sh.v[i][t], a);
                     c = fredc(a, F);
                 }
