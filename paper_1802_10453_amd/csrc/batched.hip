@@ -13,15 +13,19 @@
 // (|value| < p < 2^23), lower triangle stored by columns: entry (k, l), k >= l,
 // at S[l * n + k], so the column a pivot step reads is contiguous.  Updates are
 // lazy: a 1x1 pivot contributes one rank-1 term u v^T, a 2x2 pivot two; up to
-// KMAX terms wait in LDS (u by row, v by column).  A pivot step reads its
-// column from the slot and subtracts the waiting terms for that column only;
-// when the window is full, one pass over the alive triangle applies all of
-// them (FP64 accumulation of at most KMAX products below (p-1)^2/4 each onto a
-// reduced value: far below 2^53) and stores the reduced result.  The
-// multiplier of alive row k for pivot column c goes to the position of (k, c)
-// as soon as c is eliminated; a row set aside leaves zeros in its column.
-// Everything happens on the device (no host synchronisation), so the call can
-// be captured in a graph.
+// KMAX terms wait in LDS.  Only the column factor v of a term is stored (by
+// row); its row factor u is recovered mod p from the row's stored factors and
+// two scalars of the pivot step, which halves the LDS a term takes.  A pivot
+// step reads its column from the slot and subtracts the waiting terms for that
+// column only; when the window is full, one pass over the alive triangle
+// applies all of them (FP64 accumulation of at most KMAX products below
+// (p-1)^2/4 each onto a reduced value: far below 2^53) and stores the reduced
+// result.  The multiplier of alive row k for pivot column c goes to the
+// position of (k, c) as soon as c is eliminated; a row set aside leaves zeros
+// in its column.  A step is a chain of short latencies (a column read, two
+// barriers, a ballot), so the design keeps LDS per workgroup small enough for
+// WG_PER_CU matrices in flight on each CU.  Everything happens on the device
+// (no host synchronisation), so the call can be captured in a graph.
 #include "../../include/pldl.h"
 #include "common.h"
 
@@ -29,11 +33,13 @@ namespace pldl {
 
 namespace {
 
-constexpr int NB_MAX = 512;   // largest order of a batched matrix
-constexpr int KMAX = 12;       // rank-1 terms applied per pass over the triangle
-constexpr int NWAVE = 16;     // waves per workgroup (1024 threads)
-constexpr int CG = 8;         // columns whose loads are in flight together in a pass
-static_assert(NB_MAX <= 1024, "one thread per row of a batched matrix");
+constexpr int NB_MAX = 512;       // largest order of a batched matrix
+constexpr int NTH = 512;          // threads per workgroup
+constexpr int NWAVE = NTH / 64;   // waves per workgroup
+constexpr int WG_PER_CU = 4;      // workgroups resident per CU (LDS and register budget)
+constexpr int KMAX = 12;          // rank-1 terms applied per pass over the triangle
+constexpr int CG = 8;             // columns whose loads are in flight together in a pass
+static_assert(NB_MAX <= NTH, "one thread per row of a batched matrix");
 
 struct BatchArgs {
     int64_t batch;
@@ -49,7 +55,6 @@ struct BatchArgs {
     float* ws;           // one NB_MAX^2 slot per workgroup
     int32_t* queue;      // next matrix index
     Field F;
-    const uint32_t* itab;
     int check_range;
 };
 
@@ -61,34 +66,55 @@ __device__ __forceinline__ void st_out(void* A, int32_t dtype, int64_t off, doub
     else ((double*)A)[off] = v;
 }
 
+// Inverse of a pivot: table read through the scalar path (the index is uniform,
+// the table read-only), else the extended Euclidean algorithm.
+__device__ __forceinline__ double inverse(double x, const Field& F, const uint32_t* __restrict__ itab) {
+    if (itab) return (double)itab[__builtin_amdgcn_readfirstlane((int)x)];
+    return finv(x, F);
+}
+
 struct BatchShared {
-    float u[KMAX][NB_MAX];     // row factors of the waiting terms
-    float v[NB_MAX][KMAX];     // column factors of the waiting terms
-    double colI[NB_MAX], colJ[NB_MAX];
-    double bx[NB_MAX], by[NB_MAX];
-    int order[NB_MAX], zeros[NB_MAX], sig[NB_MAX];
+    float v[NB_MAX][KMAX];     // column factor of each waiting term, by row
+    float ta[KMAX], tb[KMAX];  // row factor of term t at row k: ta[t] v[k][t] + tb[t] v[k][tp[t]]
+    int tp[KMAX];
+    float colI[NB_MAX], colJ[NB_MAX];
+    float bx[NB_MAX], by[NB_MAX];
+    int16_t order[NB_MAX], zeros[NB_MAX], sig[NB_MAX];
     uint8_t alv[NB_MAX], bt[NB_MAX];
     int64_t m;
 };
+
+// Row factor of waiting term t at a row whose stored column factors are vk.  A
+// 1x1 pivot x (term b c^T, b = c / x) stores c, so b = x^-1 c.  A 2x2 pair
+// (terms (e + f) b^T and c a^T, with a = e / x, b = c / x, f = d22 b) stores b
+// (term t) and a (term t + 1), so e + f = d22 b + x a and c = x b.  Both forms
+// are ta[t] vk[t] + tb[t] vk[tp[t]], mod p, centered; each product is below
+// p^2 / 2.
+__device__ __forceinline__ double urow(const float* vk, const BatchShared& sh, int t, const Field& F) {
+    return fredc(fma((double)sh.ta[t], (double)vk[t], (double)sh.tb[t] * (double)vk[sh.tp[t]]), F);
+}
 
 // Applies the npend waiting terms to every alive entry (k, l), k >= l >= i0 (all
 // alive indices are >= i0).  Work items are 64x64 tiles of the lower triangle,
 // dealt round-robin to the waves; a lane owns one row k of its tile and walks
 // the alive columns of the tile CG at a time, all CG loads issued before use.
-__device__ void flush_terms(BatchShared& sh, float* S, int n, int i0, int npend, const Field& F, int wave,
+__device__ void flush_terms(const BatchShared& sh, float* S, int n, int i0, int npend, const Field& F, int wave,
                             int lane) {
     const int c0 = i0 >> 6, nch = (n + 63) >> 6;
     int tile = 0;
     for (int c = c0; c < nch; ++c)
         for (int b = c0; b <= c; ++b, ++tile) {
             if (tile % NWAVE != wave) continue;
+            // keeps the per-term scalars from being hoisted out of the tile loop into
+            // registers (they are cheap LDS broadcasts)
+            __asm__ __volatile__("" ::: "memory");
             const int k = 64 * c + lane;
             const bool kal = k < n && sh.alv[k];
+            const int kc = k < n ? k : n - 1;   // in-bounds row for lanes past the end
             float uk[KMAX];
 #pragma unroll
-            for (int t = 0; t < KMAX; ++t) uk[t] = (kal && t < npend) ? sh.u[t][k] : 0.0f;
+            for (int t = 0; t < KMAX; ++t) uk[t] = (kal && t < npend) ? (float)urow(sh.v[kc], sh, t, F) : 0.0f;
             const int lb = 64 * b + lane;
-            const int kc = k < n ? k : n - 1;   // in-bounds row for lanes past the end
             uint64_t live = __ballot(lb < n && sh.alv[lb]);
             while (live) {
                 int ls[CG];
@@ -117,17 +143,15 @@ __device__ void flush_terms(BatchShared& sh, float* S, int n, int i0, int npend,
         }
 }
 
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_factor_batched(BatchArgs g) {
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(8))) void k_factor_batched(
+    BatchArgs g, const uint32_t* __restrict__ itab) {
     __shared__ BatchShared sh;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const Field F = g.F;
     float* S = g.ws + (int64_t)blockIdx.x * NB_MAX * NB_MAX;
-    // the term buffers only ever hold finite residues: a zero row factor then
+    // the term buffer only ever holds finite residues: a zero row factor then
     // cancels whatever a column factor slot holds
-    for (int q = tid; q < KMAX * NB_MAX; q += 1024) {
-        (&sh.u[0][0])[q] = 0.0f;
-        (&sh.v[0][0])[q] = 0.0f;
-    }
+    for (int q = tid; q < KMAX * NB_MAX; q += NTH) (&sh.v[0][0])[q] = 0.0f;
 
     for (;;) {
         if (tid == 0) sh.m = atomicAdd(g.queue, 1);
@@ -155,16 +179,17 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 bad |= (v >= F.p || v < 0.0);
                 S[l * n + k] = (float)fcen(v, F);
             }
-        for (int k = tid; k < n; k += 1024) sh.alv[k] = 1;
+        for (int k = tid; k < n; k += NTH) sh.alv[k] = 1;
         bad = __syncthreads_or(bad);
         if (bad && g.check_range) {
             if (tid == 0) { g.status[mi] = PLDL_ERANGE; g.rank[mi] = 0; }
             continue;
         }
-        // ---- elimination; thread k owns row k (n <= NB_MAX <= 1024)
+        // ---- elimination; thread k owns row k
         int r = 0, nz = 0, np = 0;
-        const int kc = tid < n ? tid : n - 1;   // in-bounds row for the unconditional column loads
-        float pre = 0.0f;                       // slot column pre_i at row kc, loaded one step ahead
+        const int k = tid;
+        const int kc = k < n ? k : n - 1;   // in-bounds row for the unconditional column loads
+        float pre = 0.0f;                   // slot column pre_i at row kc, loaded one step ahead
         int pre_i = -1;
         for (int i = 0; i < n; ++i) {
             if (!sh.alv[i]) continue;
@@ -184,91 +209,87 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 pre_i = i + 1;
             }
             // column i of the Schur complement (alive rows, all >= i), waiting terms applied
-            if (tid < n) {
-                const int k = tid;
+            if (k < n) {
                 double c = 0.0;
                 if (k >= i && sh.alv[k]) {
                     double a = (double)raw;
-                    for (int t = 0; t < np; ++t) a = fma(-(double)sh.u[t][k], (double)sh.v[i][t], a);
+                    for (int t = 0; t < np; ++t) a = fma(-urow(sh.v[k], sh, t, F), (double)sh.v[i][t], a);
                     c = fredc(a, F);
                 }
-                sh.colI[k] = c;
+                sh.colI[k] = (float)c;
             }
             __syncthreads();
             int j = -1;
             for (int q = i >> 6; q * 64 < n && j < 0; ++q) {
                 const int kk = q * 64 + lane;
-                const unsigned long long bal = __ballot(kk < n && sh.colI[kk] != 0.0);
+                const unsigned long long bal = __ballot(kk < n && sh.colI[kk] != 0.0f);
                 if (bal) j = q * 64 + __ffsll((long long)bal) - 1;
             }
             if (j < 0) {   // zero row: set aside, precedence kept, its column left zero
-                for (int k = tid; k < n; k += 1024)
-                    if (k > i && sh.alv[k]) S[i * n + k] = 0.0f;
-                if (tid == 0) { sh.zeros[nz] = i; sh.alv[i] = 0; }
+                if (k < n && k > i && sh.alv[k]) S[i * n + k] = 0.0f;
+                if (tid == 0) { sh.zeros[nz] = (int16_t)i; sh.alv[i] = 0; }
                 ++nz;
                 __syncthreads();
                 continue;
             }
             if (j == i) {  // 1x1 pivot x: term b c^T with b = c / x; L(k, i) = b_k
-                const double x = fcan(sh.colI[i], F);
-                const double xi = g.itab ? (double)g.itab[(int)x] : finv(x, F);
-                for (int k = tid; k < n; k += 1024) {
-                    float u = 0.0f, v = 0.0f;
+                const double x = fcan((double)sh.colI[i], F);
+                const double xi = inverse(x, F, itab);
+                if (k < n) {
+                    float v = 0.0f;
                     if (k > i && sh.alv[k]) {
-                        const double bk = fredc(sh.colI[k] * xi, F);
-                        S[i * n + k] = (float)fcan(bk, F);
-                        u = (float)bk;
-                        v = (float)sh.colI[k];
+                        const double ck = (double)sh.colI[k];
+                        S[i * n + k] = (float)fcan(fredc(ck * xi, F), F);
+                        v = (float)ck;
                     }
-                    sh.u[np][k] = u;
                     sh.v[k][np] = v;
                 }
-                if (tid == 0) { sh.bx[r] = x; sh.bt[r] = 1; sh.order[r] = i; sh.alv[i] = 0; }
+                if (tid == 0) {
+                    sh.bx[r] = (float)x; sh.bt[r] = 1; sh.order[r] = (int16_t)i; sh.alv[i] = 0;
+                    sh.ta[np] = (float)xi; sh.tb[np] = 0.0f; sh.tp[np] = np;
+                }
                 np += 1;
                 r += 1;
             } else {       // 2x2 pivot on (i, j), j > i
-                for (int k = tid; k < n; k += 1024) {
+                if (k < n) {
                     double c = 0.0;
                     if (k >= i && sh.alv[k]) {
                         const int hi = k > j ? k : j, lo = k > j ? j : k;
                         double a = (double)S[lo * n + hi];
-                        for (int t = 0; t < np; ++t) a = fma(-(double)sh.u[t][hi], (double)sh.v[lo][t], a);
+                        for (int t = 0; t < np; ++t) a = fma(-urow(sh.v[hi], sh, t, F), (double)sh.v[lo][t], a);
                         c = fredc(a, F);
                     }
-                    sh.colJ[k] = c;
+                    sh.colJ[k] = (float)c;
                 }
                 __syncthreads();
-                const double x = fcan(sh.colI[j], F), y = fcan(sh.colJ[j], F);
-                const double xi = g.itab ? (double)g.itab[(int)x] : finv(x, F);
+                const double x = fcan((double)sh.colI[j], F), y = fcan((double)sh.colJ[j], F);
+                const double xi = inverse(x, F, itab);
                 double w, d22, lji;
                 if (F.ip == 2) { w = y; d22 = y; lji = 0.0; }
                 else { w = fmulm(y, F.inv2, F); d22 = 0.0; lji = fmulm(w, xi, F); }
-                // per row: b_k = c_k / x, e_k = d_k - w b_k, a_k = e_k / x, f_k = d22 b_k;
-                // terms (e + f) b^T and c a^T; L(k, i) = a_k, L(k, j) = b_k
-                for (int k = tid; k < n; k += 1024) {
-                    float u0 = 0.0f, v0 = 0.0f, u1 = 0.0f, v1 = 0.0f;
+                // per row: b_k = c_k / x, e_k = d_k - w b_k, a_k = e_k / x; terms
+                // (e + f) b^T and c a^T with f = d22 b; L(k, i) = a_k, L(k, j) = b_k
+                if (k < n) {
+                    float vb = 0.0f, va = 0.0f;
                     if (k > i && k != j && sh.alv[k]) {
-                        const double ck = sh.colI[k], dk = sh.colJ[k];
+                        const double ck = (double)sh.colI[k], dk = (double)sh.colJ[k];
                         const double bk = fredc(ck * xi, F);
                         const double ek = fredc(dk - fredc(w * bk, F), F);
                         const double ak = fredc(ek * xi, F);
-                        const double fk = fredc(d22 * bk, F);
                         S[i * n + k] = (float)fcan(ak, F);
                         if (k > j) S[j * n + k] = (float)fcan(bk, F);
                         else S[k * n + j] = (float)fcan(bk, F);
-                        u0 = (float)fredc(ek + fk, F);
-                        v0 = (float)bk;
-                        u1 = (float)ck;
-                        v1 = (float)ak;
+                        vb = (float)bk;
+                        va = (float)ak;
                     }
-                    sh.u[np][k] = u0;
-                    sh.v[k][np] = v0;
-                    sh.u[np + 1][k] = u1;
-                    sh.v[k][np + 1] = v1;
+                    sh.v[k][np] = vb;
+                    sh.v[k][np + 1] = va;
                 }
                 if (tid == 0) {
-                    sh.bx[r] = x; sh.by[r] = (F.ip == 2) ? y : 0.0; sh.bt[r] = 2; sh.bt[r + 1] = 0;
-                    sh.order[r] = i; sh.order[r + 1] = j;
+                    sh.bx[r] = (float)x; sh.by[r] = (F.ip == 2) ? (float)y : 0.0f; sh.bt[r] = 2; sh.bt[r + 1] = 0;
+                    sh.order[r] = (int16_t)i; sh.order[r + 1] = (int16_t)j;
+                    sh.ta[np] = (float)d22; sh.tb[np] = (float)x; sh.tp[np] = np + 1;
+                    sh.ta[np + 1] = 0.0f; sh.tb[np + 1] = (float)x; sh.tp[np + 1] = np;
                     S[i * n + j] = (float)lji;
                     sh.alv[i] = 0; sh.alv[j] = 0;
                 }
@@ -278,7 +299,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             __syncthreads();
         }
         // ---- output in place: order = pivots then zero rows
-        for (int q = tid; q < n; q += 1024) sh.sig[q] = q < r ? sh.order[q] : sh.zeros[q - r];
+        for (int q = tid; q < n; q += NTH) sh.sig[q] = q < r ? sh.order[q] : sh.zeros[q - r];
         __syncthreads();
         for (int q = wave; q < n; q += NWAVE)
             for (int c = lane; c < q; c += 64) {
@@ -293,27 +314,27 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             int q = 0;
             for (int t = 0; t < r;) {
                 if (sh.bt[t] == 1) {
-                    sh.colJ[q] = sh.bx[t]; sh.colI[q] = 0.0;
+                    sh.colJ[q] = sh.bx[t]; sh.colI[q] = 0.0f;
                     q += 1; t += 1;
                 } else {
-                    sh.colJ[q] = 0.0; sh.colI[q] = sh.bx[t];
-                    sh.colJ[q + 1] = sh.by[t]; sh.colI[q + 1] = 0.0;
+                    sh.colJ[q] = 0.0f; sh.colI[q] = sh.bx[t];
+                    sh.colJ[q + 1] = sh.by[t]; sh.colI[q + 1] = 0.0f;
                     q += 2; t += 2;
                 }
             }
-            for (; q < n; ++q) { sh.colJ[q] = 0.0; sh.colI[q] = 0.0; }
+            for (; q < n; ++q) { sh.colJ[q] = 0.0f; sh.colI[q] = 0.0f; }
             g.rank[mi] = r;
             g.status[mi] = 0;
         }
         __syncthreads();
-        for (int q = tid; q < n; q += 1024) {
-            st_out(A, g.dtype, (int64_t)q * lda + q, sh.colJ[q]);
-            st_out(g.e[mi], g.dtype, q, sh.colI[q]);
+        for (int q = tid; q < n; q += NTH) {
+            st_out(A, g.dtype, (int64_t)q * lda + q, (double)sh.colJ[q]);
+            st_out(g.e[mi], g.dtype, q, (double)sh.colI[q]);
             g.perm[mi][q] = sh.sig[q];
             g.rpm[mi][q] = -1;
         }
         __syncthreads();
-        for (int t = tid; t < r; t += 1024) {
+        for (int t = tid; t < r; t += NTH) {
             if (sh.bt[t] == 1) g.rpm[mi][sh.order[t]] = sh.order[t];
             else if (sh.bt[t] == 2) { g.rpm[mi][sh.order[t]] = sh.order[t + 1]; g.rpm[mi][sh.order[t + 1]] = sh.order[t]; }
         }
@@ -327,6 +348,8 @@ __global__ void k_zero_counter(int32_t* q) { *q = 0; }
 
 int batched_nb_max() { return NB_MAX; }
 
+int batched_wg_per_cu() { return WG_PER_CU; }
+
 size_t batched_slot_bytes() { return (size_t)NB_MAX * NB_MAX * sizeof(float); }
 
 void launch_factor_batched(hipStream_t s, const Field& F, const uint32_t* itab, int64_t batch, const int64_t* n,
@@ -335,10 +358,10 @@ void launch_factor_batched(hipStream_t s, const Field& F, const uint32_t* itab, 
                            int slots, int32_t* queue) {
     BatchArgs g{};
     g.batch = batch; g.n = n; g.A = A; g.lda = lda; g.dtype = dtype; g.e = e; g.perm = perm; g.rpm = rpm;
-    g.rank = rank; g.status = status; g.ws = (float*)ws; g.queue = queue; g.F = F; g.itab = itab;
+    g.rank = rank; g.status = status; g.ws = (float*)ws; g.queue = queue; g.F = F;
     g.check_range = check_range;
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, queue);
-    hipLaunchKernelGGL(k_factor_batched, dim3((unsigned)slots), dim3(1024), 0, s, g);
+    hipLaunchKernelGGL(k_factor_batched, dim3((unsigned)slots), dim3(NTH), 0, s, g, itab);
 }
 
 }  // namespace pldl

@@ -136,6 +136,7 @@ void i8_run(hipStream_t s, const Field& F, const I8Product& pr, double* C, int64
 // per matrix at a time (slots workgroups, each with a private slot of
 // batched_slot_bytes() in ws); queue is a device counter the launch resets.
 int batched_nb_max();
+int batched_wg_per_cu();
 size_t batched_slot_bytes();
 void launch_factor_batched(hipStream_t s, const Field& F, const uint32_t* itab, int64_t batch, const int64_t* n,
                            void* const* A, const int64_t* lda, int32_t dtype, void* const* e, int32_t* const* perm,

@@ -1115,7 +1115,7 @@ int pldl_factor_batched(pldl_ctx* ctx, uint32_t p, int64_t batch, const int64_t*
         if (!ctx->bws) {
             hipDeviceProp_t prop;
             HIPCHK(hipGetDeviceProperties(&prop, ctx->device));
-            const int slots = std::max(1, 2 * prop.multiProcessorCount);
+            const int slots = std::max(1, batched_wg_per_cu() * prop.multiProcessorCount);
             if (hipMalloc((void**)&ctx->bws, (size_t)slots * batched_slot_bytes()) != hipSuccess ||
                 hipMalloc((void**)&ctx->bqueue, 256) != hipSuccess) {
                 (void)hipGetLastError();
