@@ -68,6 +68,12 @@ constexpr int PLDUQ_THREADS = 1024;
 constexpr int NZB_MAX = 2048;
 
 // Pivot columns of a PLDUQ slab (T row indices); a slab has at most 64 pivots.
+// Device state of a PLDUQ slab (int32 words; see k_plduq_leaf): rows with a
+// pivot so far, next column, done flag, pending leaf (its rank, chunk end and
+// pivot columns), scan-hint count for the next leaf, committed pivot columns.
+constexpr int SS_R = 0, SS_CUR = 1, SS_DONE = 2, SS_PEND = 3, SS_RLAST = 4, SS_CE = 5, SS_NH = 6, SS_PN = 7,
+              SS_ITER = 8, SS_PCOL = 16, SS_CCOL = 80, SS_WORDS = 144;
+
 struct PivList {
     int32_t col[64];
     int32_t n;

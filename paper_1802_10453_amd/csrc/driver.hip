@@ -290,6 +290,7 @@ struct Engine {
     int path = PLDL_PATH_F64;         // products on FP64 or INT8-split matrix cores
     I8Space* i8 = nullptr;
     double i8_min_flops = 0.0;        // smaller products stay on FP64 (split passes would dominate)
+    int slab_leaves = 2;              // leaves the last PLDUQ slab took (first batch of the next)
     Engine(Workspace& w, hipStream_t s, uint32_t p, int64_t n_, int t, Prof* pr)
         : st(s), F(make_field(p)), n(n_), ld(std::max<int64_t>(n_, 1)), t_leaf(t), ws(w), W(w.W), prof(pr) {}
 
@@ -301,8 +302,8 @@ struct Engine {
     MatV vcol(int64_t r0, int64_t c0) { return MatV{W + r0 * ld + c0, 1, ld}; }  // W[r0+j][c0+i]
 
     // words the device wrote into `info` (device memory): copied back after the queued work
-    int32_t* read_info(int cnt) {
-        HIPCHK(hipMemcpyAsync(ws.hinfo, ws.info, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    int32_t* read_info(int cnt, int off = 0) {
+        HIPCHK(hipMemcpyAsync(ws.hinfo, ws.info + off, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, st));
         return read_host();
     }
     // words the device wrote straight into the pinned host words: only a wait
@@ -693,39 +694,43 @@ struct Engine {
     // [c0, c1), for the slab's rows.
     int64_t plduq_slab(int64_t a0, int64_t a1, int64_t c0, int64_t c1, const int32_t* hint, int nhint) {
         const int64_t m = a1 - a0;
-        PivList piv{};   // the slab's pivot columns, in pivot order
-        int64_t R = 0, cur = c0;
-        const int32_t* h = hint;
-        int nh = nhint;
         int32_t* nzb = ws.info + 1024;
-        while (R < m && cur < c1) {
-            LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_leaf, dim3(1), dim3(PLDUQ_THREADS), 0, st, T, ldT, a0 + R, (int)(m - R), cur, c1, F,
-                   itab, h, nh, ws.sig, ws.hinfo_dev, pR);
-            const int32_t* hi = read_host();
-            const int64_t r = hi[0], cs = hi[1], w = hi[2];
-            if (r == 0) break;   // the active rows are zero on [cur, c1)
-            REQUIRE(R + r <= 64);
-            PivList cp{};
-            for (int64_t s = 0; s < r; ++s) cp.col[s] = hi[16 + s];
-            cp.n = (int32_t)r;
-            const int64_t ce = cs + w, nr = c1 - ce, ma = m - R;
-            const int64_t items = nr + piv.n;
-            if (items > 0) {
-                const bool more = ma > r && nr > 0;
-                const int64_t nb = std::min<int64_t>((items + 3) / 4, NZB_MAX);
-                LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_rupdate, dim3((unsigned)nb), dim3(256), 0, st, T, ldT, a0 + R, (int)ma, (int)r,
-                       cp, ce, nr, F, itab, more ? nzb : nullptr, ws.sig, piv);
-                h = more ? nzb : nullptr;
-                nh = (int)nb;
-            } else {
-                h = nullptr;
-                nh = 0;
+        int32_t* ss = ws.info + 256;   // slab state (device words SS_*)
+        LAUNCH(PLDL_CLASS_OTHER, k_slab_init, dim3(1), dim3(256), 0, st, ss, c0);
+        // the update's grid covers every column it may visit (those right of the
+        // first leaf's chunk plus the slab's pivot columns); it is launched before
+        // the leaf's chunk is known, so it is sized for the whole range
+        const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((c1 - c0 + 64 + 3) / 4, NZB_MAX));
+        // Leaves and updates are queued in batches and the state is read once per
+        // batch: the kernels of a finished slab return at once.  The first batch is
+        // the previous slab's leaf count (neighbouring slabs see similar rank
+        // profiles), the next ones double.  Each leaf but the last takes at least
+        // one pivot, so at most m + 1 leaves run.
+        int32_t* hs = nullptr;
+        int batch = slab_leaves;
+        for (int64_t queued = 0;;) {
+            for (int b = 0; b < batch; ++b) {
+                LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_leaf, dim3(1), dim3(PLDUQ_THREADS), 0, st, T, ldT, a0, (int)m, c1, F,
+                       itab, hint, nhint, nzb, ws.sig, ss, pR);
+                LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_rupdate, dim3((unsigned)nb), dim3(256), 0, st, T, ldT, a0, (int)m, c1,
+                       F, itab, nzb, ws.sig, ss);
             }
-            for (int64_t s = 0; s < r; ++s) piv.col[piv.n + s] = cp.col[s];
-            piv.n += (int32_t)r;
-            R += r;
-            cur = ce;
+            queued += batch;
+            hs = read_info(SS_WORDS, 256);
+            const int64_t Rc = hs[SS_R] + (hs[SS_PEND] ? hs[SS_RLAST] : 0);
+            const int64_t cc = hs[SS_PEND] ? hs[SS_CE] : hs[SS_CUR];
+            if (hs[SS_DONE] || Rc >= m || cc >= c1) break;
+            REQUIRE(queued <= m + 1);
+            batch = std::min(batch * 2, 32);
         }
+        slab_leaves = std::max(1, std::min(hs[SS_ITER], 16));
+        // the slab's pivot columns in pivot order: committed ones, then the pending leaf's
+        PivList piv{};
+        for (int q = 0; q < hs[SS_PN]; ++q) piv.col[piv.n++] = hs[SS_PCOL + q];
+        if (hs[SS_PEND] && !hs[SS_DONE])
+            for (int q = 0; q < hs[SS_RLAST]; ++q) piv.col[piv.n++] = hs[SS_CCOL + q];
+        const int64_t R = piv.n;
+        REQUIRE(R <= m);
         if (R > 0) {
             PivList srt = piv;
             std::sort(srt.col, srt.col + srt.n);

@@ -14,6 +14,8 @@
 // leave CUs idle), 4 waves in a 2x2 grid, K tiles of 16 staged through
 // double-buffered LDS (one barrier per K tile), the next K tile's global loads
 // in flight while the current one feeds the matrix cores.
+#include <type_traits>
+
 #include "common.h"
 
 namespace pldl {
@@ -74,8 +76,14 @@ __global__ __launch_bounds__(NT) void k_gemm(GemmKArgs g) {
 #pragma unroll
         for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
+    // Global loads run PD K tiles ahead of the matrix cores through PD register
+    // sets (two for the small tile, whose K tiles carry little work to hide a
+    // memory latency behind; one for the big tile, bounded by registers); LDS is
+    // double-buffered with one barrier per K tile.
+    constexpr int PD = BM == 64 ? 2 : 1;
     int since = 0;
-    double ra[AE], rb[BE];
+    double ra[PD][AE], rb[PD][BE];
+    uint32_t va[PD], vb[PD];
 #pragma unroll 1
     for (int seg = 0; seg < 2; ++seg) {
         const int64_t K = g.K[seg];
@@ -86,55 +94,64 @@ __global__ __launch_bounds__(NT) void k_gemm(GemmKArgs g) {
         // valid row/column) so that all of them are in flight together; the
         // validity masks are applied when the values are written to LDS.
         const int64_t mlast = g.m - 1, nlast = g.n - 1, klast = K - 1;
-        uint32_t va = 0, vb = 0;
-        auto load = [&](int64_t kt) {
-            va = 0; vb = 0;
+        auto load = [&](auto slot_c, int64_t kt) {
+            constexpr int sl = decltype(slot_c)::value;
+            va[sl] = 0; vb[sl] = 0;
 #pragma unroll
             for (int e = 0; e < AE; ++e) {
                 const int64_t gi = i0 + a_r0 + a_dr * e, gk = kt + a_c0 + a_dc * e;
                 const bool ok = gi <= mlast && gk <= klast;
-                va |= (ok ? 1u : 0u) << e;
-                ra[e] = A.p[min(gi, mlast) * A.rs + min(gk, klast) * A.cs];
+                va[sl] |= (ok ? 1u : 0u) << e;
+                ra[sl][e] = A.p[min(gi, mlast) * A.rs + min(gk, klast) * A.cs];
             }
 #pragma unroll
             for (int e = 0; e < BE; ++e) {
                 const int64_t gk = kt + b_k0 + b_dk * e, gj = j0 + b_c0 + b_dc * e;
                 const bool ok = gk <= klast && gj <= nlast && !(mask_b && gk > gj);
-                vb |= (ok ? 1u : 0u) << e;
-                rb[e] = B.p[min(gk, klast) * B.rs + min(gj, nlast) * B.cs];
+                vb[sl] |= (ok ? 1u : 0u) << e;
+                rb[sl][e] = B.p[min(gk, klast) * B.rs + min(gj, nlast) * B.cs];
             }
         };
-        auto store = [&](int buf) {
+        auto store = [&](auto slot_c, int buf) {
+            constexpr int sl = decltype(slot_c)::value;
 #pragma unroll
             for (int e = 0; e < AE; ++e)
-                As[buf][a_c0 + a_dc * e][a_r0 + a_dr * e] = ((va >> e) & 1u) ? fcen(ra[e], F) : 0.0;
+                As[buf][a_c0 + a_dc * e][a_r0 + a_dr * e] = ((va[sl] >> e) & 1u) ? fcen(ra[sl][e], F) : 0.0;
 #pragma unroll
             for (int e = 0; e < BE; ++e)
-                Bs[buf][b_k0 + b_dk * e][b_c0 + b_dc * e] = ((vb >> e) & 1u) ? fcen(rb[e], F) : 0.0;
+                Bs[buf][b_k0 + b_dk * e][b_c0 + b_dc * e] = ((vb[sl] >> e) & 1u) ? fcen(rb[sl][e], F) : 0.0;
         };
+        using S0 = std::integral_constant<int, 0>;
+        using S1 = std::integral_constant<int, (PD > 1 ? 1 : 0)>;
+        const int64_t nt = (K + BK - 1) / BK;
         __syncthreads();   // LDS of a previous segment fully consumed
-        load(0);
-        store(0);
+        // tile 0 to LDS; tile tau waits in register set tau % PD
+        load(S0{}, 0);
+        store(S0{}, 0);
+        if (nt > 1) load(S1{}, BK);
+        if (PD > 1 && nt > 2) load(S0{}, 2 * BK);
         __syncthreads();
         int cur = 0;
-#pragma unroll 1
-        for (int64_t kt = 0; kt < K; kt += BK) {
-            const bool more = kt + BK < K;
-            if (more) load(kt + BK);
+        // one K tile: feed the matrix cores from LDS, move tile t+1 from its register
+        // set to the other buffer, refill that set with tile t+1+PD
+        auto body = [&](int64_t t, auto slot_c) {
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 4) {
                 double a[FM], b[FN];
 #pragma unroll
-                for (int t = 0; t < FM; ++t) a[t] = As[cur][kk + lk][wm * WM + t * 16 + lr];
+                for (int q = 0; q < FM; ++q) a[q] = As[cur][kk + lk][wm * WM + q * 16 + lr];
 #pragma unroll
-                for (int t = 0; t < FN; ++t) b[t] = Bs[cur][kk + lk][wn * WN + t * 16 + lr];
+                for (int q = 0; q < FN; ++q) b[q] = Bs[cur][kk + lk][wn * WN + q * 16 + lr];
 #pragma unroll
                 for (int x = 0; x < FM; ++x)
 #pragma unroll
                     for (int y = 0; y < FN; ++y)
                         acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
             }
-            if (more) store(cur ^ 1);
+            if (t + 1 < nt) {
+                store(slot_c, cur ^ 1);
+                if (t + 1 + PD < nt) load(slot_c, (t + 1 + PD) * BK);
+            }
             __syncthreads();
             cur ^= 1;
             since += BK;
@@ -147,6 +164,11 @@ __global__ __launch_bounds__(NT) void k_gemm(GemmKArgs g) {
                         for (int r = 0; r < 4; ++r) acc[x][y][r] = fred(acc[x][y][r], F);
                 since = 0;
             }
+        };
+#pragma unroll 1
+        for (int64_t t = 0; t < nt; t += PD) {
+            body(t, S1{});                        // tile t+1 sits in set (t+1) % PD
+            if (PD > 1 && t + 1 < nt) body(t + 1, S0{});
         }
     }
     // epilogue: v_mfma_f64_16x16x4f64 result layout: lane l, register r holds D[l/16 + 4r][l%16]

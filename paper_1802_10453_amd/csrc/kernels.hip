@@ -270,14 +270,18 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
 // Output, in place: the LU pack of the chunk with its rows in the new order
 // (pivot rows first, in pivot order, then the others in their previous order;
 // the same reordering applied to pR[a0 .. a0+m)) and its columns in place,
-// rsig (new row -> old row, for the rest of these rows) and
-// info = {rank, chunk start, chunk width} and info[16 ..] = T rows of the r
-// pivot columns.
+// rsig (new row -> old row, for the rest of these rows), and in the slab
+// state ss its rank, the end of its chunk and the T rows of its r pivot
+// columns (pending: the next leaf commits them, after the update has used
+// them).  The leaf takes its rows (a0s + R, ms - R rows), first column and scan
+// hint from the state, and returns at once when the slab is done (all rows
+// pivots, columns exhausted, or the active rows zero on what is left), so the
+// host can queue several leaves and updates ahead without reading anything.
 // ===========================================================================
-__global__ __launch_bounds__(PLDUQ_THREADS) void k_plduq_leaf(double* T, int64_t ld, int64_t a0, int m, int64_t c0,
+__global__ __launch_bounds__(PLDUQ_THREADS) void k_plduq_leaf(double* T, int64_t ld, int64_t a0s, int ms,
                                                      int64_t c1, Field F, const uint32_t* itab,
-                                                     const int32_t* hint, int nhint, int32_t* rsig,
-                                                     int32_t* info, int32_t* pR) {
+                                                     const int32_t* hint0, int nhint0, const int32_t* nzb,
+                                                     int32_t* rsig, int32_t* ss, int32_t* pR) {
     constexpr int NT = PLDUQ_THREADS, NG = NT / 64;          // threads, column groups (one per wave)
     constexpr int CW = PLDUQ_CHUNK, KC = CW / NG;            // chunk width, columns per thread
     static_assert(KC <= 64 && CW % 64 == 0 && CW <= 1024, "live mask and search sizes");
@@ -288,7 +292,31 @@ __global__ __launch_bounds__(PLDUQ_THREADS) void k_plduq_leaf(double* T, int64_t
     __shared__ double pinvx[64];
     __shared__ int rord[64], cord[64], rposs[64];
     __shared__ unsigned long long wmask[2][NG];
+    __shared__ int sst[4];
     const int tid = threadIdx.x, row = tid & 63, cg = tid >> 6, lane = tid & 63;
+    // ---- slab state: commit the previous leaf (its update has run), stop when done
+    if (tid == 0) {
+        int done = ss[SS_DONE];
+        if (!done && ss[SS_PEND]) {
+            const int rl = ss[SS_RLAST], pn = ss[SS_PN];
+            for (int q = 0; q < rl; ++q) ss[SS_PCOL + pn + q] = ss[SS_CCOL + q];
+            ss[SS_PN] = pn + rl;
+            ss[SS_R] += rl;
+            ss[SS_CUR] = ss[SS_CE];
+            ss[SS_PEND] = 0;
+        }
+        if (!done && (ss[SS_R] >= ms || ss[SS_CUR] >= c1)) ss[SS_DONE] = done = 1;
+        sst[0] = done;
+        sst[1] = ss[SS_R];
+        sst[2] = ss[SS_CUR];
+        sst[3] = ss[SS_ITER];
+    }
+    __syncthreads();
+    if (sst[0]) return;
+    const int64_t a0 = a0s + sst[1], c0 = sst[2];
+    const int m = ms - sst[1];
+    const int32_t* hint = sst[3] == 0 ? hint0 : (ss[SS_NH] > 0 ? nzb : nullptr);
+    const int nhint = sst[3] == 0 ? nhint0 : ss[SS_NH];
     double y[KC];
     int64_t cs = c0;
     if (hint) {   // the minimum of the nhint candidates left by the preceding update
@@ -322,8 +350,8 @@ __global__ __launch_bounds__(PLDUQ_THREADS) void k_plduq_leaf(double* T, int64_t
         if (__syncthreads_or(nzf)) break;
         cs += CW;
     }
-    if (w <= 0) {  // all rows are zero on [c0, c1)
-        if (tid == 0) { info[0] = 0; info[1] = (int32_t)c1; info[2] = 0; }
+    if (w <= 0) {  // all rows are zero on [c0, c1): the slab is done
+        if (tid == 0) { ss[SS_DONE] = 1; ss[SS_ITER] = sst[3] + 1; }
         return;
     }
     for (int e = tid; e < CW; e += NT) { ispc[e] = 0; cpiv[e] = -1; }
@@ -417,8 +445,8 @@ __global__ __launch_bounds__(PLDUQ_THREADS) void k_plduq_leaf(double* T, int64_t
     for (int e = tid; e < w; e += NT)
         if (cpiv[e] >= 0) cord[cpiv[e]] = e;
     __syncthreads();
-    if (tid == 0) { info[0] = r; info[1] = (int32_t)cs; info[2] = w; }
-    if (tid < r) info[16 + tid] = (int32_t)(cs + cord[tid]);   // T row of pivot tid's column
+    if (tid == 0) { ss[SS_RLAST] = r; ss[SS_CE] = (int32_t)(cs + w); ss[SS_PEND] = 1; ss[SS_ITER] = sst[3] + 1; }
+    if (tid < r) ss[SS_CCOL + tid] = (int32_t)(cs + cord[tid]);   // T row of pivot tid's column
     if (tid < m) rsig[tid] = rord[tid];
     // pR follows the new row order (all old entries read before any write)
     const int pr_old = (tid < m) ? pR[a0 + rord[tid]] : 0;
@@ -457,38 +485,54 @@ __global__ __launch_bounds__(PLDUQ_THREADS) void k_plduq_leaf(double* T, int64_t
 // with lane t on slab row t.  The leaf reordered the rows of its tile (rsig:
 // new row -> old row); each column is gathered through rsig on load, so the
 // reordering and the update share one pass.  The tile's pivot columns sit at T
-// rows piv.col[0 .. r) (pivot rows first): entry (s, t > s) is the multiplier of
+// rows ccol[0 .. r) of the slab state (pivot rows first): entry (s, t > s) is the multiplier of
 // row t for pivot s, entry (s, s) is D_s.  For each column: u_s = y_s -
 // sum_{s' < s} L[s][s'] u_s' (column elimination, one wave shuffle per pivot),
 // the other rows y_t -= M[t][s] u_s, then u_s <- u_s / D_s.  At most 64
 // products accumulate before the final reduction (below 2^53 for p < 2^23).
-// The pivot columns of the slab's earlier tiles (prev.col) hold these rows'
+// The pivot columns of the slab's earlier tiles (pcol of the state) hold these rows'
 // multipliers: they are only reordered.  With nzblk, workgroup b writes to
 // nzblk[b] the first of its columns left nonzero on rows r .. m-1 (NZ_NONE if
 // none): the next leaf's scan starts at the minimum.
 // ===========================================================================
-__global__ __launch_bounds__(256) void k_plduq_rupdate(double* T, int64_t ld, int64_t a0, int m, int r, PivList piv,
-                                                       int64_t ce, int64_t nr, Field F, const uint32_t* itab,
-                                                       int32_t* nzblk, const int32_t* rsig, PivList prev) {
+__global__ __launch_bounds__(256) void k_plduq_rupdate(double* T, int64_t ld, int64_t a0s, int ms, int64_t c1,
+                                                       Field F, const uint32_t* itab, int32_t* nzblk,
+                                                       const int32_t* rsig, int32_t* ss) {
     __shared__ double Lc[64][64];   // Lc[s][t]: multiplier of row t > s for pivot s, 0 for t <= s
     __shared__ double dinv[64];
     __shared__ int wfirst[4];
+    __shared__ int pcol[64], ccol[64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // the leaf's results, not yet committed to the slab state (the next leaf does that)
+    if (ss[SS_DONE] || !ss[SS_PEND]) return;
+    const int R = ss[SS_R], r = ss[SS_RLAST], pn = ss[SS_PN];
+    const int64_t a0 = a0s + R, ce = ss[SS_CE], nr = c1 - ce;
+    const int m = ms - R;
+    const bool more = m > r && nr > 0;   // rows stay active: the next leaf wants a hint
+    if (!more) nzblk = nullptr;
+    if (blockIdx.x == 0 && tid == 0) ss[SS_NH] = more ? (int)gridDim.x : 0;
+    const int64_t stride = (int64_t)gridDim.x * 4, items = nr + pn;
+    if ((int64_t)blockIdx.x * 4 >= items) {   // the grid is sized for the slab's first leaf
+        if (nzblk && tid == 0) nzblk[blockIdx.x] = NZ_NONE;
+        return;
+    }
+    if (tid < r) ccol[tid] = ss[SS_CCOL + tid];
+    if (tid < pn) pcol[tid] = ss[SS_PCOL + tid];
+    __syncthreads();
     for (int e = tid; e < r * 64; e += 256) {
         const int sp = e >> 6, t = e & 63;
-        Lc[sp][t] = (t > sp && t < m) ? fcen(T[(int64_t)piv.col[sp] * ld + a0 + t], F) : 0.0;
+        Lc[sp][t] = (t > sp && t < m) ? fcen(T[(int64_t)ccol[sp] * ld + a0 + t], F) : 0.0;
     }
     if (tid < r) {
-        const double d = T[(int64_t)piv.col[tid] * ld + a0 + tid];
+        const double d = T[(int64_t)ccol[tid] * ld + a0 + tid];
         dinv[tid] = itab ? (double)itab[(int)d] : finv(d, F);
     }
     __syncthreads();
     const int src = (lane < m) ? rsig[lane] : 0;
     int first = NZ_NONE;
-    const int64_t stride = (int64_t)gridDim.x * 4, items = nr + prev.n;
     for (int64_t jj = (int64_t)blockIdx.x * 4 + wave; jj < items; jj += stride) {
         if (jj >= nr) {   // an earlier pivot column: reorder only
-            double* col = T + (int64_t)prev.col[jj - nr] * ld + a0;
+            double* col = T + (int64_t)pcol[jj - nr] * ld + a0;
             const double v = (lane < m) ? col[src] : 0.0;
             if (lane < m) col[lane] = v;
             continue;
@@ -530,6 +574,12 @@ __global__ void k_slab_colsrc(PivList ord, PivList srt, int64_t c0, int64_t len,
         }
     }
     src[q] = (int32_t)pos;
+}
+
+// A fresh slab state: no pivots, scan from column c0.
+__global__ void k_slab_init(int32_t* ss, int64_t c0) {
+    const int q = threadIdx.x;
+    if (q < SS_WORDS) ss[q] = q == SS_CUR ? (int32_t)c0 : 0;
 }
 
 // inv[snap[q]] = q (snap: a segment of an index array before a reordering)
