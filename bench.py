@@ -45,11 +45,12 @@ def eff_ops(n, r):
 
 def cpu_baseline(workload_p):
     """The oracle (plain CPU elimination, OpenMP over the trailing update) on a bounded
-    sample of the same input family: n = 2048, rank 1536, random rank profile."""
+    sample of the same input family: n = 4608, rank 3456, random rank profile (about
+    10 s of host work on 16 cores)."""
     import oracle.oracle as orc
     from paper_1802_10453_amd import inputs
-    n, p = 2048, workload_p
-    r = 1536
+    n, p = 4608, workload_p
+    r = 3456
     A, _ = inputs.rank_profile_matrix_input(n, p, r // 2, r // 4, inputs.SEED_BASE + 100, check=8)
     orc.lib()
     t0 = time.perf_counter()
@@ -88,7 +89,7 @@ def measured_traffic(path, workload, n, p, r):
         return None
 
 
-def cpu_baseline_batched(mats, params, p, sample=64):
+def cpu_baseline_batched(mats, params, p, sample=2048):
     """The oracle on the first `sample` matrices of the same batch."""
     import oracle.oracle as orc
     orc.lib()
