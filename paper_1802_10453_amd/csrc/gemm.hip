@@ -10,10 +10,11 @@
 // exact in any order; the accumulators are reduced mod p every F.kred products
 // (delayed reduction), and once more in the epilogue.
 //
-// Structure: workgroup tile BM x BN (128x128, or 64x64 when the big tiles would
-// leave CUs idle), 4 waves in a 2x2 grid, K tiles of 16 staged through
-// double-buffered LDS (one barrier per K tile), the next K tile's global loads
-// in flight while the current one feeds the matrix cores.
+// Structure: workgroup tile BM x BN (128x128 with 16 waves in a 2x8 grid, or
+// 64x64 with 16 waves in a 4x4 grid when the big tiles would leave CUs idle), K
+// tiles of 16 staged through double-buffered LDS (one barrier per K tile),
+// later K tiles' global loads in flight while the current one feeds the matrix
+// cores.
 #include <type_traits>
 
 #include "common.h"
@@ -21,7 +22,11 @@
 namespace pldl {
 
 namespace {
-constexpr int BK = 16, NT = 256, PAD = 16;
+constexpr int BK = 16, PAD = 16;
+// waves of a workgroup (up to BN/16 along n, the rest along m): more waves than
+// SIMDs let one wave's loads and barrier waits overlap another's matrix-core work
+constexpr int BIG_WAVES = 16, SMALL_WAVES = 16;
+template <int BM> constexpr int gemm_threads() { return 64 * (BM == 128 ? BIG_WAVES : SMALL_WAVES); }
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 struct GemmKArgs {
@@ -38,8 +43,11 @@ struct GemmKArgs {
 };
 
 template <int BM, int BN, bool A_ROW, bool B_ROW, bool LOWER_C, bool B_UPPER>
-__global__ __launch_bounds__(NT) void k_gemm(GemmKArgs g) {
-    constexpr int WM = BM / 2, WN = BN / 2;      // wave tile
+__global__ __launch_bounds__(gemm_threads<BM>()) void k_gemm(GemmKArgs g) {
+    constexpr int NT = gemm_threads<BM>(), NW = NT / 64;
+    constexpr int WGN = NW / 2 < BN / 16 ? NW / 2 : BN / 16, WGM = NW / WGN;   // wave grid
+    constexpr int WM = BM / WGM, WN = BN / WGN;  // wave tile
+    static_assert(WM % 16 == 0 && WN % 16 == 0 && WGM * WGN == NW, "wave grid");
     constexpr int FM = WM / 16, FN = WN / 16;    // 16x16 MFMA blocks per wave
     constexpr int AE = BM * BK / NT, BE = BN * BK / NT;
     __shared__ double As[2][BK][BM + PAD];
@@ -59,7 +67,7 @@ __global__ __launch_bounds__(NT) void k_gemm(GemmKArgs g) {
     }
     const int64_t i0 = (int64_t)ti * BM, j0 = (int64_t)tj * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WGN, wn = wave % WGN;
     const int lr = lane & 15, lk = lane >> 4;
 
     // per-thread load coordinates inside a tile (element e adds a fixed step)
@@ -196,7 +204,8 @@ __global__ __launch_bounds__(NT) void k_gemm(GemmKArgs g) {
         if (lane == 0) red[wave] = first_nz;
         __syncthreads();
         if (tid == 0) {
-            int v = min(min(red[0], red[1]), min(red[2], red[3]));
+            int v = red[0];
+            for (int q = 1; q < NW; ++q) v = min(v, red[q]);
             if (v < (1 << 30)) atomicMin(g.nzrow, g.nzoff + v);
         }
     }
@@ -206,11 +215,11 @@ __global__ __launch_bounds__(NT) void k_gemm(GemmKArgs g) {
 template <int BM, int BN, bool AR, bool BR>
 void dispatch(hipStream_t s, const GemmKArgs& g, int blocks, bool lower_c, bool b_upper) {
     if (lower_c) {
-        if (b_upper) hipLaunchKernelGGL((k_gemm<BM, BN, AR, BR, true, true>), dim3(blocks), dim3(NT), 0, s, g);
-        else hipLaunchKernelGGL((k_gemm<BM, BN, AR, BR, true, false>), dim3(blocks), dim3(NT), 0, s, g);
+        if (b_upper) hipLaunchKernelGGL((k_gemm<BM, BN, AR, BR, true, true>), dim3(blocks), dim3(gemm_threads<BM>()), 0, s, g);
+        else hipLaunchKernelGGL((k_gemm<BM, BN, AR, BR, true, false>), dim3(blocks), dim3(gemm_threads<BM>()), 0, s, g);
     } else {
-        if (b_upper) hipLaunchKernelGGL((k_gemm<BM, BN, AR, BR, false, true>), dim3(blocks), dim3(NT), 0, s, g);
-        else hipLaunchKernelGGL((k_gemm<BM, BN, AR, BR, false, false>), dim3(blocks), dim3(NT), 0, s, g);
+        if (b_upper) hipLaunchKernelGGL((k_gemm<BM, BN, AR, BR, false, true>), dim3(blocks), dim3(gemm_threads<BM>()), 0, s, g);
+        else hipLaunchKernelGGL((k_gemm<BM, BN, AR, BR, false, false>), dim3(blocks), dim3(gemm_threads<BM>()), 0, s, g);
     }
 }
 
