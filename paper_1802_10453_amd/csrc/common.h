@@ -150,6 +150,6 @@ void launch_factor_batched(hipStream_t s, const Field& F, const uint32_t* itab, 
                            int slots, int32_t* queue);
 
 // Products below this many flops stay on FP64 inside a factorization.
-constexpr double I8_MIN_FLOPS = 67108864.0;
+constexpr double I8_MIN_FLOPS = 134217728.0;   // 2^27: below it the limb split costs more than it saves
 
 }  // namespace pldl
