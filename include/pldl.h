@@ -218,7 +218,7 @@ int pldl_plduq(pldl_ctx *ctx, uint32_t p, int64_t m, int64_t n, double *Y, int64
  * planes (L = 1 for p < 2^8, 2 for p < 2^15, else 3) into a context buffer
  * grown on demand, and runs the L^2 byte products on v_mfma_i32_16x16x64_i8;
  * results are identical to the FP64 path (both are exact).  Inside
- * pldl_factor, products below 2^26 flops and those that detect the first
+ * pldl_factor, products below 2^27 flops and those that detect the first
  * nonzero row of their result stay on FP64.  Returns -2 for another value.
  */
 int pldl_set_path(pldl_ctx *ctx, int32_t path);
