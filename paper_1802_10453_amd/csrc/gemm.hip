@@ -22,7 +22,7 @@
 namespace pldl {
 
 namespace {
-constexpr int BK = 16, PAD = 16;
+constexpr int BK = 16, PAD = 2;   // LDS row padding (doubles): breaks the bank conflicts of the transposed tile stores
 // waves of a workgroup (up to BN/16 along n, the rest along m): more waves than
 // SIMDs let one wave's loads and barrier waits overlap another's matrix-core work
 constexpr int BIG_WAVES = 16, SMALL_WAVES = 16;
