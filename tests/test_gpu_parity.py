@@ -193,6 +193,44 @@ def test_plduq_parity(ctx, p):
         assert (rec == Y[np.ix_(rows, cols)].astype(object)).all()
 
 
+def _staircase(g, p, m, step, n):
+    """Row i is zero before column step*i (a staircase): every column chunk of a
+    slab holds the first nonzero of one more row, so a 64-row slab takes about
+    one leaf per row, and the leaves' queued batches run out several times."""
+    Y = g.integers(0, p, size=(m, n)).astype(np.uint32)
+    for i in range(m):
+        Y[i, : min(n, step * i)] = 0
+    return Y
+
+
+@pytest.mark.parametrize("p", [2, 8388593])
+def test_plduq_many_leaves_per_slab(ctx, p):
+    g = inputs.rng(p + 29)
+    for (m, step, n) in [(64, 256, 64 * 256 + 5), (130, 300, 130 * 300), (70, 40, 3000)]:
+        print(f"[plduq-staircase] p={p} m={m} step={step} n={n}", flush=True)
+        Y = _staircase(g, p, m, step, n)
+        if m > 3:
+            Y[2] = 0   # a zero row among them
+        res = ctx.plduq(p, dev(Y))
+        ref = orc.plduq(p, Y)
+        r = res["rank"]
+        assert r == ref["rank"]
+        rows, cols = res["rows"].cpu().numpy(), res["cols"].cpu().numpy()
+        assert sorted(zip(rows[:r].tolist(), cols[:r].tolist())) == \
+            sorted(zip(ref["rows"][:r].tolist(), ref["cols"][:r].tolist()))
+        assert sorted(rows.tolist()) == list(range(m)) and sorted(cols.tolist()) == list(range(n))
+        # L D U = Y[rows, cols] mod p, in int64 (r p^2 < 2^63 for these sizes)
+        LU = host(res["LU"]).astype(np.int64)
+        L = np.tril(LU[:, :r], -1)
+        L[np.arange(r), np.arange(r)] = 1
+        U = np.triu(LU[:r, :], 1)
+        U[np.arange(r), np.arange(r)] = 1
+        d = np.diag(LU)[:r]
+        assert (d != 0).all() and (LU[r:, r:] == 0).all()
+        rec = ((L * d[None, :]) % p) @ U % p
+        assert (rec == Y[np.ix_(rows, cols)].astype(np.int64)).all()
+
+
 # ---------------------------------------------------------------- base case alone (canonical order)
 @pytest.mark.parametrize("p", PRIMES)
 def test_base_case_canonical(ctx, p):
