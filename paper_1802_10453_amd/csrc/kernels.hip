@@ -292,31 +292,28 @@ __global__ __launch_bounds__(PLDUQ_THREADS) void k_plduq_leaf(double* T, int64_t
     __shared__ double pinvx[64];
     __shared__ int rord[64], cord[64], rposs[64];
     __shared__ unsigned long long wmask[2][NG];
-    __shared__ int sst[4];
+    __shared__ int sw[SS_WORDS];
     const int tid = threadIdx.x, row = tid & 63, cg = tid >> 6, lane = tid & 63;
-    // ---- slab state: commit the previous leaf (its update has run), stop when done
-    if (tid == 0) {
-        int done = ss[SS_DONE];
-        if (!done && ss[SS_PEND]) {
-            const int rl = ss[SS_RLAST], pn = ss[SS_PN];
-            for (int q = 0; q < rl; ++q) ss[SS_PCOL + pn + q] = ss[SS_CCOL + q];
-            ss[SS_PN] = pn + rl;
-            ss[SS_R] += rl;
-            ss[SS_CUR] = ss[SS_CE];
-            ss[SS_PEND] = 0;
-        }
-        if (!done && (ss[SS_R] >= ms || ss[SS_CUR] >= c1)) ss[SS_DONE] = done = 1;
-        sst[0] = done;
-        sst[1] = ss[SS_R];
-        sst[2] = ss[SS_CUR];
-        sst[3] = ss[SS_ITER];
-    }
+    // ---- slab state: one parallel read into LDS, then every thread takes the same
+    // decisions: commit the previous leaf (its update has run), stop when done
+    if (tid < SS_WORDS) sw[tid] = ss[tid];
     __syncthreads();
-    if (sst[0]) return;
-    const int64_t a0 = a0s + sst[1], c0 = sst[2];
-    const int m = ms - sst[1];
-    const int32_t* hint = sst[3] == 0 ? hint0 : (ss[SS_NH] > 0 ? nzb : nullptr);
-    const int nhint = sst[3] == 0 ? nhint0 : ss[SS_NH];
+    const int done0 = sw[SS_DONE], rl = sw[SS_RLAST], pn = sw[SS_PN];
+    const bool commit = !done0 && sw[SS_PEND];
+    const int R = sw[SS_R] + (commit ? rl : 0);
+    const int64_t c0 = commit ? sw[SS_CE] : sw[SS_CUR];
+    const bool done = done0 || R >= ms || c0 >= c1;
+    if (commit && tid < rl) ss[SS_PCOL + pn + tid] = sw[SS_CCOL + tid];
+    if (tid == 0) {
+        if (commit) { ss[SS_PN] = pn + rl; ss[SS_R] = R; ss[SS_CUR] = (int32_t)c0; ss[SS_PEND] = 0; }
+        if (done && !done0) ss[SS_DONE] = 1;
+    }
+    if (done) return;
+    const int iter = sw[SS_ITER];
+    const int64_t a0 = a0s + R;
+    const int m = ms - R;
+    const int32_t* hint = iter == 0 ? hint0 : (sw[SS_NH] > 0 ? nzb : nullptr);
+    const int nhint = iter == 0 ? nhint0 : sw[SS_NH];
     double y[KC];
     int64_t cs = c0;
     if (hint) {   // the minimum of the nhint candidates left by the preceding update
@@ -351,7 +348,7 @@ __global__ __launch_bounds__(PLDUQ_THREADS) void k_plduq_leaf(double* T, int64_t
         cs += CW;
     }
     if (w <= 0) {  // all rows are zero on [c0, c1): the slab is done
-        if (tid == 0) { ss[SS_DONE] = 1; ss[SS_ITER] = sst[3] + 1; }
+        if (tid == 0) { ss[SS_DONE] = 1; ss[SS_ITER] = iter + 1; }
         return;
     }
     for (int e = tid; e < CW; e += NT) { ispc[e] = 0; cpiv[e] = -1; }
@@ -445,7 +442,7 @@ __global__ __launch_bounds__(PLDUQ_THREADS) void k_plduq_leaf(double* T, int64_t
     for (int e = tid; e < w; e += NT)
         if (cpiv[e] >= 0) cord[cpiv[e]] = e;
     __syncthreads();
-    if (tid == 0) { ss[SS_RLAST] = r; ss[SS_CE] = (int32_t)(cs + w); ss[SS_PEND] = 1; ss[SS_ITER] = sst[3] + 1; }
+    if (tid == 0) { ss[SS_RLAST] = r; ss[SS_CE] = (int32_t)(cs + w); ss[SS_PEND] = 1; ss[SS_ITER] = iter + 1; }
     if (tid < r) ss[SS_CCOL + tid] = (int32_t)(cs + cord[tid]);   // T row of pivot tid's column
     if (tid < m) rsig[tid] = rord[tid];
     // pR follows the new row order (all old entries read before any write)
