@@ -349,13 +349,12 @@ struct Engine {
         prof->end(st);
     }
 
-    // Symmetric permutation of [lo, hi): new lo+q <- old lo+sig[q] (sig NULL: the
-    // rotation moving the first rot1 positions after the others).
+    // Symmetric permutation of [lo, hi): new lo+q <- old lo+sig[q].
     // parts: 1 = rows x [0,lo), 2 = block, 4 = rows below x range, 8 = orig.
-    void perm_sym(int64_t lo, int64_t hi, const int32_t* sig, int parts, int64_t rot1 = -1) {
+    void perm_sym(int64_t lo, int64_t hi, const int32_t* sig, int parts) {
         const int64_t s = hi - lo;
         if (s <= 1) return;
-        REQUIRE(lo >= 0 && hi <= n && (sig || (rot1 > 0 && rot1 < s)));
+        REQUIRE(lo >= 0 && hi <= n && sig);
         PermGeom g{};
         g.n = n; g.lo = lo; g.hi = hi; g.s = s; g.parts = parts;
         g.nb0 = nblk(std::max<int64_t>(lo, 1));
@@ -369,13 +368,9 @@ struct Engine {
         REQUIRE(blocks < ((int64_t)1 << 31));
         double elems = (double)(g.B0 ? s * lo : 0) + (double)(g.B1 ? s * (s + 1) / 2 : 0) + (double)(g.B2 ? s * (n - hi) : 0);
         prof->begin(st, PLDL_CLASS_PERM, 0.0, 16.0 * elems);
-        hipLaunchKernelGGL(k_perm_sym, dim3((unsigned)blocks), dim3(256), 0, st, W, ld, g, sig, rot1, ws.tmp1, ws.orig, ws.tmpo, 0);
-        hipLaunchKernelGGL(k_perm_sym, dim3((unsigned)blocks), dim3(256), 0, st, W, ld, g, sig, rot1, ws.tmp1, ws.orig, ws.tmpo, 1);
+        hipLaunchKernelGGL(k_perm_sym, dim3((unsigned)blocks), dim3(256), 0, st, W, ld, g, sig, ws.tmp1, ws.orig, ws.tmpo, 0);
+        hipLaunchKernelGGL(k_perm_sym, dim3((unsigned)blocks), dim3(256), 0, st, W, ld, g, sig, ws.tmp1, ws.orig, ws.tmpo, 1);
         prof->end(st);
-    }
-    void rotate(int64_t a, int64_t b, int64_t c) {
-        if (a == b || b == c) return;
-        perm_sym(a, c, nullptr, 15, b - a);
     }
 
     // ---- TRSM (Section 3) ---------------------------------------------------

@@ -23,8 +23,6 @@ __global__ void k_tcolperm(double* T, int64_t ld, int64_t j0, int64_t len, const
 __global__ void k_trowperm(double* T, int64_t ld, int64_t j0, int64_t nj, int64_t i0, int64_t len,
                            const int32_t* src, double* tmp, int phase);
 __global__ void k_inv_table(uint32_t* tab, Field F);
-__global__ void k_mat_gather(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t rows, int64_t cols,
-                             const int32_t* rsig, int64_t roff, const int32_t* csig, int64_t coff);
 __global__ void k_transpose(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t rows, int64_t cols);
 __global__ void k_idx_gather(const int32_t* idx, int64_t a, int64_t len, const int32_t* sig, int32_t* tmp);
 __global__ void k_idx_copy(int32_t* idx, int64_t a, int64_t len, const int32_t* tmp);
@@ -33,18 +31,16 @@ __global__ void k_zlp_sigma_total(int32_t* sig, int64_t mz, int64_t nc, int64_t 
 __global__ void k_trinv_blocks(MatV T, int64_t r, int lower, double* N, Field F);
 __global__ void k_trss_leaf(double* W, int64_t ld, int64_t s0, int64_t u0, int r, Field F);
 struct PermGeom { int64_t n, lo, hi, s, nb0, nb1, B0, B1, B2, B3; int parts; };
-__global__ void k_perm_sym(double* W, int64_t ld, PermGeom g, const int32_t* sig, int64_t rot1, double* tmp,
+__global__ void k_perm_sym(double* W, int64_t ld, PermGeom g, const int32_t* sig, double* tmp,
                            int32_t* orig, int32_t* tmpo, int dir);
 __global__ void k_scale_pack(double* X, int64_t ld, int64_t rows, int64_t cols, const double* P, int64_t ldp,
                              int by_row, const uint32_t* itab, Field F);
-__global__ void k_sigma_rotate(int32_t* sig, int64_t len1, int64_t len2);
 __global__ void k_sigma_merge(const int32_t* orig, int64_t a, int64_t n1, int64_t n2, int32_t* sig);
 __global__ void k_block_dinv(const double* dd, const double* de, int64_t lo, int64_t r, Field F, double* xinv,
                              double* yy, int8_t* kind);
 __global__ void k_scal_dinv(double* X, int64_t ldx, int64_t rows, int64_t r, const double* xinv, const double* yy,
                             const int8_t* kind, double* T, int64_t ldt, Field F);
 __global__ void k_pack_dinv(const double* W, int64_t ld, int64_t c0, int64_t a0, int64_t r, Field F, double* dinv);
-__global__ void k_scale_by(double* X, int64_t ld, int64_t rows, int64_t cols, const double* dinv, int by_row, Field F);
 __global__ void k_mul_cols(const double* X, int64_t ldx, int64_t rows, int64_t cols, const double* dinv, int lower,
                            double* out, int64_t ldo, Field F);
 __global__ void k_copy2d(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t rows, int64_t cols);

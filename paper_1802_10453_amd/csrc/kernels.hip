@@ -646,16 +646,6 @@ __global__ void k_transpose(double* dst, int64_t ldd, const double* src, int64_t
     dst[j * ldd + i] = src[i * lds + j];
 }
 
-// dst[i][j] = src[roff + rsig[i]][coff + csig[j]] (a NULL sigma is the identity)
-__global__ void k_mat_gather(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t rows, int64_t cols,
-                             const int32_t* rsig, int64_t roff, const int32_t* csig, int64_t coff) {
-    int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    int64_t i = blockIdx.y;
-    if (j >= cols || i >= rows) return;
-    int64_t si = rsig ? roff + rsig[i] : i;
-    int64_t sj = csig ? coff + csig[j] : j;
-    dst[i * ldd + j] = src[si * lds + sj];
-}
 
 // idx[a+q] <- idx[a+sig[q]] for q < len (through tmp)
 __global__ void k_idx_gather(const int32_t* idx, int64_t a, int64_t len, const int32_t* sig, int32_t* tmp) {
@@ -839,14 +829,11 @@ __global__ __launch_bounds__(256) void k_trinv_blocks(MatV T, int64_t r, int low
 
 // ===========================================================================
 // Permutations.  A sigma maps new local position q to old local position
-// sig[q]; a NULL sigma with rot1 >= 0 stands for the rotation that moves the
-// first rot1 positions after the others.  Out-of-range sigma entries (a bug
-// upstream) are clamped so that no access leaves the range.
+// sig[q].  Out-of-range sigma entries (a bug upstream) are clamped so that no
+// access leaves the range.
 // ===========================================================================
-__device__ __forceinline__ int64_t sigma_at(const int32_t* sig, int64_t q, int64_t sz, int64_t rot1) {
-    int64_t v;
-    if (sig) v = sig[q];
-    else { int64_t len2 = sz - rot1; v = q < len2 ? rot1 + q : q - len2; }
+__device__ __forceinline__ int64_t sigma_at(const int32_t* sig, int64_t q, int64_t sz) {
+    const int64_t v = sig[q];
     return (v < 0 || v >= sz) ? 0 : v;
 }
 
@@ -854,7 +841,7 @@ __device__ __forceinline__ int64_t sigma_at(const int32_t* sig, int64_t q, int64
 // part 0 rows [lo,hi) x cols [0,lo); part 1 the lower block; part 2 rows
 // [hi,n) x cols [lo,hi); part 3 orig.  One flat grid: block b is decoded into
 // (part, row, column block); `dir` 0 gathers into tmp, 1 scatters back.
-__global__ __launch_bounds__(256) void k_perm_sym(double* W, int64_t ld, PermGeom g, const int32_t* sig, int64_t rot1,
+__global__ __launch_bounds__(256) void k_perm_sym(double* W, int64_t ld, PermGeom g, const int32_t* sig,
                                                  double* tmp, int32_t* orig, int32_t* tmpo, int dir) {
     int64_t b = blockIdx.x;
     const int64_t s = g.s, lo = g.lo, hi = g.hi;
@@ -866,13 +853,13 @@ __global__ __launch_bounds__(256) void k_perm_sym(double* W, int64_t ld, PermGeo
     if (part == 0) {
         int64_t row = b / g.nb0, c = (b - row * g.nb0) * 256 + threadIdx.x;
         if (c >= lo) return;
-        if (dir == 0) tmp[row * lo + c] = W[(lo + sigma_at(sig, row, s, rot1)) * ld + c];
+        if (dir == 0) tmp[row * lo + c] = W[(lo + sigma_at(sig, row, s)) * ld + c];
         else W[(lo + row) * ld + c] = tmp[row * lo + c];
     } else if (part == 1) {
         int64_t row = b / g.nb1, c = (b - row * g.nb1) * 256 + threadIdx.x;
         if (c > row) return;
         if (dir == 0) {
-            int64_t x = lo + sigma_at(sig, row, s, rot1), y = lo + sigma_at(sig, c, s, rot1);
+            int64_t x = lo + sigma_at(sig, row, s), y = lo + sigma_at(sig, c, s);
             tmp[s * lo + row * s + c] = (x >= y) ? W[x * ld + y] : W[y * ld + x];
         } else {
             W[(lo + row) * ld + lo + c] = tmp[s * lo + row * s + c];
@@ -880,22 +867,16 @@ __global__ __launch_bounds__(256) void k_perm_sym(double* W, int64_t ld, PermGeo
     } else if (part == 2) {
         int64_t row = b / g.nb1, c = (b - row * g.nb1) * 256 + threadIdx.x;
         if (c >= s) return;
-        if (dir == 0) tmp[s * lo + s * s + row * s + c] = W[(hi + row) * ld + lo + sigma_at(sig, c, s, rot1)];
+        if (dir == 0) tmp[s * lo + s * s + row * s + c] = W[(hi + row) * ld + lo + sigma_at(sig, c, s)];
         else W[(hi + row) * ld + lo + c] = tmp[s * lo + s * s + row * s + c];
     } else {
         int64_t c = b * 256 + threadIdx.x;
         if (c >= s) return;
-        if (dir == 0) tmpo[c] = orig[lo + sigma_at(sig, c, s, rot1)];
+        if (dir == 0) tmpo[c] = orig[lo + sigma_at(sig, c, s)];
         else orig[lo + c] = tmpo[c];
     }
 }
 
-// sigma of the rotation [len1 | len2] -> [len2 | len1]
-__global__ void k_sigma_rotate(int32_t* sig, int64_t len1, int64_t len2) {
-    int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (q >= len1 + len2) return;
-    sig[q] = (int32_t)(q < len2 ? len1 + q : q - len2);
-}
 
 // Merge two runs of positions [a, a+n1) and [a+n1, a+n1+n2), each sorted by
 // original index, into one sorted run: sig[rank] = local index.
@@ -982,16 +963,6 @@ __global__ void k_scale_pack(double* X, int64_t ld, int64_t rows, int64_t cols, 
     X[i * ld + j] = fmulm(X[i * ld + j], di, F);
 }
 
-// X[k][j] *= dinv[k]  (rows x cols block, row k scaled)   -- by_row = 1
-// X[j][k] *= dinv[k]  (column k scaled)                   -- by_row = 0
-__global__ void k_scale_by(double* X, int64_t ld, int64_t rows, int64_t cols, const double* dinv, int by_row,
-                           Field F) {
-    int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    int64_t i = blockIdx.y;
-    if (j >= cols || i >= rows) return;
-    double d = by_row ? dinv[i] : dinv[j];
-    X[i * ld + j] = fmulm(X[i * ld + j], d, F);
-}
 
 // out[i][k] = X[i][k] * dinv[k] for k < kmax(i) (lower: k <= i) -- G1, G2 of Algorithm 3
 __global__ void k_mul_cols(const double* X, int64_t ldx, int64_t rows, int64_t cols, const double* dinv, int lower,
