@@ -60,6 +60,8 @@ __device__ __forceinline__ double finv(double a, const Field& F) {
 // ---------------------------------------------------------------------------
 // "No nonzero seen" value of the first-nonzero slots (a column index above any n).
 constexpr int32_t NZ_NONE = 0x7F7F7F7F;
+// Threads of the base-case leaf (128 x 128 block, 4 rows x 4096/BC_THREADS columns each).
+constexpr int BC_THREADS = 1024;
 // Column chunk a PLDUQ leaf eliminates and the leaf's workgroup size (each
 // thread holds PLDUQ_CHUNK / (PLDUQ_THREADS / 64) entries in registers).
 constexpr int PLDUQ_CHUNK = 256;

@@ -440,7 +440,7 @@ struct Engine {
     int64_t bc(int64_t lo, int64_t hi) {
         int s = (int)(hi - lo);
         REQUIRE(s >= 1 && s <= 128);
-        LAUNCH(PLDL_CLASS_BASE_CASE, k_bc_leaf, dim3(1), dim3(1024), 0, st, W, ld, lo, s, F, itab, ws.dd, ws.de, ws.sig,
+        LAUNCH(PLDL_CLASS_BASE_CASE, k_bc_leaf, dim3(1), dim3(BC_THREADS), 0, st, W, ld, lo, s, F, itab, ws.dd, ws.de, ws.sig,
                ws.hinfo_dev, ws.hinfo_dev + 1);
         int32_t* h = read_host();
         int64_t r = h[0];

@@ -12,8 +12,8 @@ namespace pldl {
 
 // ===========================================================================
 // Base case (Section 5, Algorithm 4): rank-profile-revealing elimination of a
-// symmetric block of order s <= 128 held in registers (one workgroup, 1024
-// threads, each owning a 4x4 tile of the full symmetric matrix; the owners of
+// symmetric block of order s <= 128 held in registers (one workgroup, BC_THREADS
+// threads, each owning a 4 x (4096 / BC_THREADS) tile of the full symmetric matrix; the owners of
 // one column form one wave).
 //
 // Pivot search as in Section 5: the current row i is the first unprocessed
@@ -26,7 +26,7 @@ namespace pldl {
 // 3 (p-1)^2/4 per step and are reduced only when their column becomes a pivot
 // column), which computes the same unique (P, L, D).
 // ===========================================================================
-__global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t lo, int s, Field F,
+__global__ __launch_bounds__(BC_THREADS) void k_bc_leaf(double* W, int64_t ld, int64_t lo, int s, Field F,
                                                   const uint32_t* itab, double* dd, double* de,
                                                   int32_t* sig_out, int32_t* rank_out, int32_t* hsig) {
     __shared__ double colI[2][128], colJ[2][128];  // centered reduced columns, 0 on eliminated rows
@@ -35,15 +35,17 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
     __shared__ int bt[128];
     __shared__ uint32_t Mo[128][129];
 
-    // thread -> 4x4 tile: the owners of a column (one tx) all sit in one wave, so the
-    // per-pivot column work (publish, multipliers written back) runs in one wave only
+    // thread -> 4 x TW tile: the owners of a column (one tx) all sit in one wave, so
+    // the per-pivot column work (publish, multipliers written back) runs in one wave only
+    constexpr int TW = 4096 / BC_THREADS;   // columns per thread (4 rows each, 128 x 128)
+    static_assert(TW * BC_THREADS == 4096 && TW <= 32, "base-case tile");
     const int tid = threadIdx.x, ty = tid & 31, tx = tid >> 5, lane = tid & 63;
-    const int r0 = ty * 4, c0 = tx * 4;
-    double m[4][4];
+    const int r0 = ty * 4, c0 = tx * TW;
+    double m[4][TW];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < TW; ++b) {
             int i = r0 + a, j = c0 + b;
             double v = 0.0;
             if (i < s && j < s) v = (i >= j) ? W[(lo + i) * ld + lo + j] : W[(lo + j) * ld + lo + i];
@@ -53,17 +55,18 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
     uint64_t al0 = (s >= 64) ? ~0ull : ((1ull << s) - 1ull);
     uint64_t al1 = (s >= 128) ? ~0ull : (s > 64 ? ((1ull << (s - 64)) - 1ull) : 0ull);
     auto alive = [&](int k) -> bool { return k < 64 ? ((al0 >> k) & 1ull) : ((al1 >> (k - 64)) & 1ull); };
-    // this thread's rows r0 .. r0+3 and columns c0 .. c0+3 that are alive, as 4-bit masks
+    // this thread's rows r0 .. r0+3 and columns c0 .. c0+TW-1 that are alive, as bit masks
     uint32_t rbits = 0, cbits = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 4; ++q)
         if (r0 + q < s) rbits |= 1u << q;
+#pragma unroll
+    for (int q = 0; q < TW; ++q)
         if (c0 + q < s) cbits |= 1u << q;
-    }
     auto kill = [&](int k) {
         if (k < 64) al0 &= ~(1ull << k); else al1 &= ~(1ull << (k - 64));
         if ((k >> 2) == ty) rbits &= ~(1u << (k & 3));
-        if ((k >> 2) == tx) cbits &= ~(1u << (k & 3));
+        if (k / TW == tx) cbits &= ~(1u << (k % TW));
     };
     auto ralive = [&](int q) -> bool { return (rbits >> q) & 1u; };
     auto calive = [&](int q) -> bool { return (cbits >> q) & 1u; };
@@ -74,14 +77,14 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
         const int bI = step & 1;
         ++step;
         // owners of column i publish the reduced column
-        if (tx == (i >> 2)) {
+        if (tx == i / TW) {
             double colv[4];
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
                 int k = r0 + a;
                 double v = 0.0;
 #pragma unroll
-                for (int b = 0; b < 4; ++b) v = (b == (i & 3)) ? m[a][b] : v;
+                for (int b = 0; b < TW; ++b) v = (b == i % TW) ? m[a][b] : v;
                 v = ralive(a) ? fredc(v, F) : 0.0;
                 colv[a] = v;
             }
@@ -110,37 +113,37 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
             const double xi = itab ? (double)itab[(int)x] : finv(x, F);
             if (tid == 0) { bx[r] = x; bt[r] = 1; order[r] = i; }
             kill(i);
-            double vb[4], vc[4];
+            double vb[4], vc[TW];
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
                 int k = r0 + a;
                 vb[a] = ralive(a) ? fredc(colI[bI][k] * xi, F) : 0.0;
             }
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
+            for (int b = 0; b < TW; ++b) {
                 int l = c0 + b;
                 vc[b] = calive(b) ? colI[bI][l] : 0.0;
             }
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) m[a][b] = fma(-vb[a], vc[b], m[a][b]);
-            if (tx == (i >> 2)) {
+                for (int b = 0; b < TW; ++b) m[a][b] = fma(-vb[a], vc[b], m[a][b]);
+            if (tx == i / TW) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
-                    for (int b = 0; b < 4; ++b)
-                        if (b == (i & 3)) m[a][b] = fcan(vb[a], F);
+                    for (int b = 0; b < TW; ++b)
+                        if (b == i % TW) m[a][b] = fcan(vb[a], F);
             }
             r += 1;
         } else {  // 2x2 pivot on (i, j)
-            if (tx == (j >> 2)) {
+            if (tx == j / TW) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
                     int k = r0 + a;
                     double v = 0.0;
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) v = (b == (j & 3)) ? m[a][b] : v;
+                    for (int b = 0; b < TW; ++b) v = (b == j % TW) ? m[a][b] : v;
                     colJ[bI][k] = ralive(a) ? fredc(v, F) : 0.0;
                 }
             }
@@ -168,9 +171,9 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
                 rf[a] = fredc(d22 * bk, F);
                 cb[a] = bk;  // reused below for this thread's rows when writing L
             }
-            double lb[4], la[4];
+            double lb[TW], la[TW];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
+            for (int b = 0; b < TW; ++b) {
                 int l = c0 + b;
                 bool al = calive(b);
                 double ci = al ? colI[bI][l] : 0.0, cj = al ? colJ[bI][l] : 0.0;
@@ -183,33 +186,33 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
+                for (int b = 0; b < TW; ++b) {
                     double t = m[a][b];
                     t = fma(-re[a], lb[b], t);
                     t = fma(-rc[a], la[b], t);
                     t = fma(-rf[a], lb[b], t);
                     m[a][b] = t;
                 }
-            if (tx == (i >> 2)) {
+            if (tx == i / TW) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
-                    for (int b = 0; b < 4; ++b)
-                        if (b == (i & 3)) m[a][b] = fcan(ra[a], F);
+                    for (int b = 0; b < TW; ++b)
+                        if (b == i % TW) m[a][b] = fcan(ra[a], F);
             }
-            if (tx == (j >> 2)) {
+            if (tx == j / TW) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
-                    for (int b = 0; b < 4; ++b)
-                        if (b == (j & 3)) m[a][b] = fcan(cb[a], F);
+                    for (int b = 0; b < TW; ++b)
+                        if (b == j % TW) m[a][b] = fcan(cb[a], F);
             }
-            if (tx == (i >> 2) && ty == (j >> 2)) {
+            if (tx == i / TW && ty == (j >> 2)) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
-                    for (int b = 0; b < 4; ++b)
-                        if (a == (j & 3) && b == (i & 3)) m[a][b] = lji;
+                    for (int b = 0; b < TW; ++b)
+                        if (a == (j & 3) && b == i % TW) m[a][b] = lji;
             }
             r += 2;
         }
@@ -220,9 +223,9 @@ __global__ __launch_bounds__(1024) void k_bc_leaf(double* W, int64_t ld, int64_t
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) Mo[r0 + a][c0 + b] = (uint32_t)fred(m[a][b], F);
+        for (int b = 0; b < TW; ++b) Mo[r0 + a][c0 + b] = (uint32_t)fred(m[a][b], F);
     __syncthreads();
-    for (int e = tid; e < s * s; e += 1024) {
+    for (int e = tid; e < s * s; e += BC_THREADS) {
         int q = e / s, c = e - q * s;
         if (c >= q) continue;   // strict lower part: L (the diagonal holds D, written below)
         W[(lo + q) * ld + lo + c] = (c < r) ? (double)Mo[sig[q]][sig[c]] : 0.0;
