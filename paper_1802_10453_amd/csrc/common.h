@@ -58,29 +58,6 @@ __device__ __forceinline__ double finv(double a, const Field& F) {
 }
 
 // ---------------------------------------------------------------------------
-// "No nonzero seen" value of the first-nonzero slots (a column index above any n).
-constexpr int32_t NZ_NONE = 0x7F7F7F7F;
-// Threads of the base-case leaf (128 x 128 block, 4 rows x 4096/BC_THREADS columns each).
-constexpr int BC_THREADS = 1024;
-// Column chunk a PLDUQ leaf eliminates and the leaf's workgroup size (each
-// thread holds PLDUQ_CHUNK / (PLDUQ_THREADS / 64) entries in registers).
-constexpr int PLDUQ_CHUNK = 256;
-constexpr int PLDUQ_THREADS = 1024;
-// Most workgroups of a PLDUQ right-part update (one first-nonzero candidate each).
-constexpr int NZB_MAX = 2048;
-
-// Pivot columns of a PLDUQ slab (T row indices); a slab has at most 64 pivots.
-// Device state of a PLDUQ slab (int32 words; see k_plduq_leaf): rows with a
-// pivot so far, next column, done flag, pending leaf (its rank, chunk end and
-// pivot columns), scan-hint count for the next leaf, committed pivot columns.
-constexpr int SS_R = 0, SS_CUR = 1, SS_DONE = 2, SS_PEND = 3, SS_RLAST = 4, SS_CE = 5, SS_NH = 6, SS_PN = 7,
-              SS_ITER = 8, SS_PCOL = 16, SS_CCOL = 80, SS_WORDS = 144;
-
-struct PivList {
-    int32_t col[64];
-    int32_t n;
-};
-
 // ---------------------------------------------------------------------------
 // Strided matrix view: element (i, j) at p[i*rs + j*cs].  One of the strides
 // is 1 for every view the library forms (row-major: cs = 1; column-major: rs = 1).
