@@ -293,7 +293,7 @@ __global__ __launch_bounds__(PLDUQ_THREADS) void k_plduq_leaf(double* T, int64_t
     __shared__ int ispc[CW], cpiv[CW];
     __shared__ int rpiv[64];
     __shared__ double pinvx[64];
-    __shared__ int rord[64], cord[64], rposs[64];
+    __shared__ int rord[64], cord[64], rposs[64], prl[64];
     __shared__ unsigned long long wmask[2][NG];
     __shared__ int sw[SS_WORDS];
     const int tid = threadIdx.x, row = tid & 63, cg = tid >> 6, lane = tid & 63;
@@ -317,6 +317,8 @@ __global__ __launch_bounds__(PLDUQ_THREADS) void k_plduq_leaf(double* T, int64_t
     const int m = ms - R;
     const int32_t* hint = iter == 0 ? hint0 : (sw[SS_NH] > 0 ? nzb : nullptr);
     const int nhint = iter == 0 ? nhint0 : sw[SS_NH];
+    // this leaf's rows' original indices, read now and reordered at the end
+    const int pr_pre = (tid < m) ? pR[a0 + tid] : 0;
     double y[KC];
     int64_t cs = c0;
     if (hint) {   // the minimum of the nhint candidates left by the preceding update
@@ -444,12 +446,13 @@ __global__ __launch_bounds__(PLDUQ_THREADS) void k_plduq_leaf(double* T, int64_t
     // the pivot columns in pivot order (the other columns stay where they are)
     for (int e = tid; e < w; e += NT)
         if (cpiv[e] >= 0) cord[cpiv[e]] = e;
+    if (tid < 64) prl[tid] = pr_pre;
     __syncthreads();
     if (tid == 0) { ss[SS_RLAST] = r; ss[SS_CE] = (int32_t)(cs + w); ss[SS_PEND] = 1; ss[SS_ITER] = iter + 1; }
     if (tid < r) ss[SS_CCOL + tid] = (int32_t)(cs + cord[tid]);   // T row of pivot tid's column
     if (tid < m) rsig[tid] = rord[tid];
-    // pR follows the new row order (all old entries read before any write)
-    const int pr_old = (tid < m) ? pR[a0 + rord[tid]] : 0;
+    // pR follows the new row order (the old entries were read at the start)
+    const int pr_old = (tid < m) ? prl[rord[tid]] : 0;
     // the tile, already in registers, is written with its rows in the new order
     // (columns stay in place: the slab moves its pivot columns once, at its end)
     if (row < m) {
@@ -472,7 +475,6 @@ __global__ __launch_bounds__(PLDUQ_THREADS) void k_plduq_leaf(double* T, int64_t
             if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
         }
     }
-    __syncthreads();
     if (tid < m) pR[a0 + tid] = pr_old;
 }
 
