@@ -83,6 +83,24 @@ __global__ __launch_bounds__(gemm_threads<BM>()) void k_gemm(GemmKArgs g) {
     for (int a = 0; a < FM; ++a)
 #pragma unroll
         for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    // The small tile reads its C entries now (clamped in bounds, used only where
+    // the epilogue stores), so that their latency overlaps the K loop instead of
+    // adding to it: a small product has few K tiles.  C is written only in the
+    // epilogue, so an in-place product (C the A operand) reads the same values.
+    constexpr bool PRE_C = BM == 64;
+    double cpre[PRE_C ? FM : 1][PRE_C ? FN : 1][4];
+    if (PRE_C) {
+#pragma unroll
+        for (int x = 0; x < FM; ++x)
+#pragma unroll
+            for (int y = 0; y < FN; ++y)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = min(i0 + wm * WM + x * 16 + lk + 4 * r, g.m - 1);
+                    const int64_t col = min(j0 + wn * WN + y * 16 + lr, g.n - 1);
+                    cpre[x][y][r] = g.C[row * g.ldc + col];
+                }
+    }
 
     // Global loads run PD K tiles ahead of the matrix cores through PD register
     // sets (two for the small tile, whose K tiles carry little work to hide a
@@ -191,7 +209,8 @@ __global__ __launch_bounds__(gemm_threads<BM>()) void k_gemm(GemmKArgs g) {
                 const int64_t col = j0 + wn * WN + y * 16 + lr;
                 if (row < g.m && col < g.n && (!LOWER_C || col <= row)) {
                     double* c = g.C + row * g.ldc + col;
-                    double v = fred(*c - fred(acc[x][y][r], F), F);
+                    const double cv = PRE_C ? cpre[PRE_C ? x : 0][PRE_C ? y : 0][r] : *c;
+                    double v = fred(cv - fred(acc[x][y][r], F), F);
                     *c = v;
                     if (v != 0.0 && row < first_nz) first_nz = (int)row;
                 }
