@@ -855,20 +855,16 @@ __global__ __launch_bounds__(256) void k_perm_sym(double* W, int64_t ld, PermGeo
     else if ((b -= g.B0) < g.B1) part = 1;
     else if ((b -= g.B1) < g.B2) part = 2;
     else { b -= g.B2; part = 3; }
-    // positions that sigma leaves in place are skipped in both passes
     if (part == 0) {
         int64_t row = b / g.nb0, c = (b - row * g.nb0) * 256 + threadIdx.x;
-        const int64_t sr = sigma_at(sig, row, s);
-        if (c >= lo || sr == row) return;
-        if (dir == 0) tmp[row * lo + c] = W[(lo + sr) * ld + c];
+        if (c >= lo) return;
+        if (dir == 0) tmp[row * lo + c] = W[(lo + sigma_at(sig, row, s)) * ld + c];
         else W[(lo + row) * ld + c] = tmp[row * lo + c];
     } else if (part == 1) {
         int64_t row = b / g.nb1, c = (b - row * g.nb1) * 256 + threadIdx.x;
         if (c > row) return;
-        const int64_t sr = sigma_at(sig, row, s), sc = sigma_at(sig, c, s);
-        if (sr == row && sc == c) return;
         if (dir == 0) {
-            int64_t x = lo + sr, y = lo + sc;
+            int64_t x = lo + sigma_at(sig, row, s), y = lo + sigma_at(sig, c, s);
             tmp[s * lo + row * s + c] = (x >= y) ? W[x * ld + y] : W[y * ld + x];
         } else {
             W[(lo + row) * ld + lo + c] = tmp[s * lo + row * s + c];
@@ -876,19 +872,16 @@ __global__ __launch_bounds__(256) void k_perm_sym(double* W, int64_t ld, PermGeo
     } else if (part == 2) {
         int64_t row = b / g.nb1, c = (b - row * g.nb1) * 256 + threadIdx.x;
         if (c >= s) return;
-        const int64_t sc = sigma_at(sig, c, s);
-        if (sc == c) return;
-        if (dir == 0) tmp[s * lo + s * s + row * s + c] = W[(hi + row) * ld + lo + sc];
+        if (dir == 0) tmp[s * lo + s * s + row * s + c] = W[(hi + row) * ld + lo + sigma_at(sig, c, s)];
         else W[(hi + row) * ld + lo + c] = tmp[s * lo + s * s + row * s + c];
     } else {
         int64_t c = b * 256 + threadIdx.x;
         if (c >= s) return;
-        const int64_t sc = sigma_at(sig, c, s);
-        if (sc == c) return;
-        if (dir == 0) tmpo[c] = orig[lo + sc];
+        if (dir == 0) tmpo[c] = orig[lo + sigma_at(sig, c, s)];
         else orig[lo + c] = tmpo[c];
     }
 }
+
 
 // Merge two runs of positions [a, a+n1) and [a+n1, a+n1+n2), each sorted by
 // original index, into one sorted run: sig[rank] = local index.
