@@ -700,10 +700,13 @@ struct Engine {
         // batch: the kernels of a finished slab return at once.  The first batch is
         // the previous slab's leaf count (neighbouring slabs see similar rank
         // profiles), the next ones double.  Each leaf but the last takes at least
-        // one pivot, so at most m + 1 leaves run.
+        // one pivot and moves past at least one chunk, so at most
+        // min(m, chunks) + 1 leaves run: no batch goes beyond that.
+        const int64_t max_leaves = std::min<int64_t>(m, (c1 - c0 + PLDUQ_CHUNK - 1) / PLDUQ_CHUNK) + 1;
         int32_t* hs = nullptr;
         int batch = slab_leaves;
         for (int64_t queued = 0;;) {
+            batch = (int)std::max<int64_t>(1, std::min<int64_t>(batch, max_leaves - queued));
             for (int b = 0; b < batch; ++b) {
                 LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_leaf, dim3(1), dim3(PLDUQ_THREADS), 0, st, T, ldT, a0, (int)m, c1, F,
                        itab, hint, nhint, nzb, ws.sig, ss, pR);
@@ -715,7 +718,7 @@ struct Engine {
             const int64_t Rc = hs[SS_R] + (hs[SS_PEND] ? hs[SS_RLAST] : 0);
             const int64_t cc = hs[SS_PEND] ? hs[SS_CE] : hs[SS_CUR];
             if (hs[SS_DONE] || Rc >= m || cc >= c1) break;
-            REQUIRE(queued <= m + 1);
+            REQUIRE(queued < max_leaves);
             batch = std::min(batch * 2, 32);
         }
         slab_leaves = std::max(1, std::min(hs[SS_ITER], 16));
