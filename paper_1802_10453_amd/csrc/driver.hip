@@ -691,7 +691,6 @@ struct Engine {
         const int64_t m = a1 - a0;
         int32_t* nzb = ws.info + 1024;
         int32_t* ss = ws.info + 256;   // slab state (device words SS_*)
-        LAUNCH(PLDL_CLASS_OTHER, k_slab_init, dim3(1), dim3(256), 0, st, ss, c0);
         // the update's grid covers every column it may visit (those right of the
         // first leaf's chunk plus the slab's pivot columns); it is launched before
         // the leaf's chunk is known, so it is sized for the whole range
@@ -708,8 +707,10 @@ struct Engine {
         for (int64_t queued = 0;;) {
             batch = (int)std::max<int64_t>(1, std::min<int64_t>(batch, max_leaves - queued));
             for (int b = 0; b < batch; ++b) {
-                LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_leaf, dim3(1), dim3(PLDUQ_THREADS), 0, st, T, ldT, a0, (int)m, c1, F,
-                       itab, hint, nhint, nzb, ws.sig, ss, pR);
+                // the slab's first leaf starts a fresh state at c0
+                const int64_t cinit = (queued == 0 && b == 0) ? c0 : -1;
+                LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_leaf, dim3(1), dim3(PLDUQ_THREADS), 0, st, T, ldT, a0, (int)m, cinit,
+                       c1, F, itab, hint, nhint, nzb, ws.sig, ss, pR);
                 LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_rupdate, dim3((unsigned)nb), dim3(256), 0, st, T, ldT, a0, (int)m, c1,
                        F, itab, nzb, ws.sig, ss);
             }

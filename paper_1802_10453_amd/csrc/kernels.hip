@@ -282,7 +282,7 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_leaf(double* W, int64_t ld, i
 // host can queue several leaves and updates ahead without reading anything.
 // ===========================================================================
 __global__ __launch_bounds__(PLDUQ_THREADS) void k_plduq_leaf(double* T, int64_t ld, int64_t a0s, int ms,
-                                                     int64_t c1, Field F, const uint32_t* itab,
+                                                     int64_t cinit, int64_t c1, Field F, const uint32_t* itab,
                                                      const int32_t* hint0, int nhint0, const int32_t* nzb,
                                                      int32_t* rsig, int32_t* ss, int32_t* pR) {
     constexpr int NT = PLDUQ_THREADS, NG = NT / 64;          // threads, column groups (one per wave)
@@ -297,9 +297,14 @@ __global__ __launch_bounds__(PLDUQ_THREADS) void k_plduq_leaf(double* T, int64_t
     __shared__ unsigned long long wmask[2][NG];
     __shared__ int sw[SS_WORDS];
     const int tid = threadIdx.x, row = tid & 63, cg = tid >> 6, lane = tid & 63;
-    // ---- slab state: one parallel read into LDS, then every thread takes the same
+    // ---- slab state: one parallel read into LDS (or a fresh state from column
+    // cinit for the slab's first leaf), then every thread takes the same
     // decisions: commit the previous leaf (its update has run), stop when done
-    if (tid < SS_WORDS) sw[tid] = ss[tid];
+    if (tid < SS_WORDS) sw[tid] = cinit >= 0 ? (tid == SS_CUR ? (int32_t)cinit : 0) : ss[tid];
+    if (cinit >= 0 && tid == 0) {
+        ss[SS_R] = 0; ss[SS_PN] = 0; ss[SS_DONE] = 0; ss[SS_PEND] = 0; ss[SS_NH] = 0; ss[SS_ITER] = 0;
+        ss[SS_CUR] = (int32_t)cinit;
+    }
     __syncthreads();
     const int done0 = sw[SS_DONE], rl = sw[SS_RLAST], pn = sw[SS_PN];
     const bool commit = !done0 && sw[SS_PEND];
@@ -576,12 +581,6 @@ __global__ void k_slab_colsrc(PivList ord, PivList srt, int64_t c0, int64_t len,
         }
     }
     src[q] = (int32_t)pos;
-}
-
-// A fresh slab state: no pivots, scan from column c0.
-__global__ void k_slab_init(int32_t* ss, int64_t c0) {
-    const int q = threadIdx.x;
-    if (q < SS_WORDS) ss[q] = q == SS_CUR ? (int32_t)c0 : 0;
 }
 
 // inv[snap[q]] = q (snap: a segment of an index array before a reordering)
