@@ -712,10 +712,10 @@ struct Engine {
                 LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_leaf, dim3(1), dim3(PLDUQ_THREADS), 0, st, T, ldT, a0, (int)m, cinit,
                        c1, F, itab, hint, nhint, nzb, ws.sig, ss, pR);
                 LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_rupdate, dim3((unsigned)nb), dim3(256), 0, st, T, ldT, a0, (int)m, c1,
-                       F, itab, nzb, ws.sig, ss);
+                       F, itab, nzb, ws.sig, ss, b == batch - 1 ? ws.hinfo_dev : nullptr);
             }
             queued += batch;
-            hs = read_info(SS_WORDS, 256);
+            hs = read_host();   // the batch's last update wrote the state there
             const int64_t Rc = hs[SS_R] + (hs[SS_PEND] ? hs[SS_RLAST] : 0);
             const int64_t cc = hs[SS_PEND] ? hs[SS_CE] : hs[SS_CUR];
             if (hs[SS_DONE] || Rc >= m || cc >= c1) break;

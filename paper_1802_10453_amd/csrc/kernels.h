@@ -37,7 +37,7 @@ __global__ void k_plduq_leaf(double* T, int64_t ld, int64_t a0s, int ms, int64_t
                              const int32_t* hint0, int nhint0, const int32_t* nzb, int32_t* rsig, int32_t* ss,
                              int32_t* pR);
 __global__ void k_plduq_rupdate(double* T, int64_t ld, int64_t a0s, int ms, int64_t c1, Field F, const uint32_t* itab,
-                                int32_t* nzblk, const int32_t* rsig, int32_t* ss);
+                                int32_t* nzblk, const int32_t* rsig, int32_t* ss, int32_t* hstate);
 __global__ void k_slab_colsrc(PivList ord, PivList srt, int64_t c0, int64_t len, int32_t* src);
 __global__ void k_inv_scatter(const int32_t* snap, int64_t len, int32_t* inv);
 __global__ void k_src_gather(const int32_t* cur, int64_t len, const int32_t* inv, int32_t* src);

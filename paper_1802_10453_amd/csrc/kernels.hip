@@ -504,12 +504,15 @@ __global__ __launch_bounds__(PLDUQ_THREADS) void k_plduq_leaf(double* T, int64_t
 // ===========================================================================
 __global__ __launch_bounds__(256) void k_plduq_rupdate(double* T, int64_t ld, int64_t a0s, int ms, int64_t c1,
                                                        Field F, const uint32_t* itab, int32_t* nzblk,
-                                                       const int32_t* rsig, int32_t* ss) {
+                                                       const int32_t* rsig, int32_t* ss, int32_t* hstate) {
     __shared__ double Lc[64][64];   // Lc[s][t]: multiplier of row t > s for pivot s, 0 for t <= s
     __shared__ double dinv[64];
     __shared__ int wfirst[4];
     __shared__ int pcol[64], ccol[64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // the last update of a queued batch hands the state (as the leaf left it) to
+    // the host, through host memory mapped into the device address space
+    if (hstate && blockIdx.x == 0 && tid < SS_WORDS) hstate[tid] = ss[tid];
     // the leaf's results, not yet committed to the slab state (the next leaf does that)
     if (ss[SS_DONE] || !ss[SS_PEND]) return;
     const int R = ss[SS_R], r = ss[SS_RLAST], pn = ss[SS_PN];
