@@ -380,9 +380,18 @@ struct Engine {
     // single row tile (left solve), so every workgroup of k_gemm reads all of
     // its operand rows (columns) before it writes them, and the INT8 path reads
     // the limb planes it made beforehand.
+    static unsigned ts_grid(int64_t nrhs) {
+        const int64_t per = (int64_t)TS_COLS * (TS_THREADS / 64);
+        return (unsigned)((nrhs + per - 1) / per);
+    }
     // B (m x r, row-major) <- B T^{-1}, T unit upper (view)
     void trsm_ru(MatV B, int64_t m, int64_t r, MatV T) {
         if (m <= 0 || r <= 0) return;
+        if (r <= 64) {   // one block: substitution, no inverse
+            LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trsm_small, dim3(ts_grid(m)), dim3(TS_THREADS), 0, st, B.p, B.rs, m, (int)r, T,
+                   1, F);
+            return;
+        }
         const int64_t nb = (r + 63) / 64;
         ensure_tinv(nb * 64);
         LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trinv_blocks, dim3((unsigned)nb), dim3(256), 0, st, T, r, 0, ws.tinv, F);
@@ -401,6 +410,11 @@ struct Engine {
     // B (r x ncols, row-major) <- T^{-1} B, T unit lower (view)
     void trsm_ll(MatV B, int64_t r, int64_t ncols, MatV T) {
         if (r <= 0 || ncols <= 0) return;
+        if (r <= 64) {   // one block: substitution, no inverse
+            LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trsm_small, dim3(ts_grid(ncols)), dim3(TS_THREADS), 0, st, B.p, B.rs, ncols,
+                   (int)r, T, 0, F);
+            return;
+        }
         const int64_t nb = (r + 63) / 64;
         ensure_tinv(nb * 64);
         LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trinv_blocks, dim3((unsigned)nb), dim3(256), 0, st, T, r, 1, ws.tinv, F);

@@ -38,6 +38,8 @@ __global__ void k_plduq_leaf(double* T, int64_t ld, int64_t a0s, int ms, int64_t
                              int32_t* pR);
 __global__ void k_plduq_rupdate(double* T, int64_t ld, int64_t a0s, int ms, int64_t c1, Field F, const uint32_t* itab,
                                 int32_t* nzblk, const int32_t* rsig, int32_t* ss, int32_t* hstate);
+constexpr int TS_THREADS = 256, TS_COLS = 2;   // small TRSM: workgroup size, right-hand sides per wave
+__global__ void k_trsm_small(double* B, int64_t ldb, int64_t nrhs, int r, MatV T, int right, Field F);
 __global__ void k_slab_colsrc(PivList ord, PivList srt, int64_t c0, int64_t len, int32_t* src);
 __global__ void k_inv_scatter(const int32_t* snap, int64_t len, int32_t* inv);
 __global__ void k_src_gather(const int32_t* cur, int64_t len, const int32_t* inv, int32_t* src);

@@ -759,6 +759,62 @@ __device__ void mm64(const Blk& A, bool transA, const Blk& B, Blk& D, const Fiel
 }
 
 // ===========================================================================
+// Triangular solve of order r <= 64 (Section 3's TRSM on a single block) by
+// substitution.  Left: B (r x nrhs) <- T^{-1} B with T unit lower; right:
+// B (nrhs x r) <- B T^{-1} with T unit upper.  Both read, for each right-hand
+// side v, v_i -= sum_{j<i} M[i][j] v_j with M = T (left) or T^T (right).
+// A wave solves TS_COLS right-hand sides with lane i holding row i of each:
+// step j broadcasts the finished v_j (reduced, read from lane j) and every
+// lane applies its own M[i][j] (M strictly lower, in LDS, so lanes at or
+// above j add zero).  A lane accumulates at most 63 centered products before
+// its value is reduced (below 2^53).  B is row-major with leading dimension
+// ldb; T is a view (unit diagonal not read).
+// ===========================================================================
+__global__ __launch_bounds__(TS_THREADS) void k_trsm_small(double* B, int64_t ldb, int64_t nrhs, int r, MatV T,
+                                                           int right, Field F) {
+    __shared__ double Ms[64][65];
+    for (int e = threadIdx.x; e < 64 * 64; e += TS_THREADS) {
+        const int i = e >> 6, j = e & 63;
+        double v = 0.0;
+        if (j < i && i < r) v = right ? T.p[(int64_t)j * T.rs + (int64_t)i * T.cs] : T.p[(int64_t)i * T.rs + (int64_t)j * T.cs];
+        Ms[i][j] = fcen(v, F);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t c0 = ((int64_t)blockIdx.x * (TS_THREADS / 64) + (threadIdx.x >> 6)) * TS_COLS;
+    if (c0 >= nrhs) return;
+    double acc[TS_COLS];
+#pragma unroll
+    for (int k = 0; k < TS_COLS; ++k) {
+        const int64_t c = c0 + k;
+        double v = 0.0;
+        if (lane < r && c < nrhs) v = right ? B[c * ldb + lane] : B[(int64_t)lane * ldb + c];
+        acc[k] = fcen(v, F);
+    }
+    for (int j = 0; j + 1 < r; ++j) {
+        const double m = Ms[lane][j];
+#pragma unroll
+        for (int k = 0; k < TS_COLS; ++k) {
+            const double y = fredc(acc[k], F);
+            const int64_t yb = __double_as_longlong(y);
+            const int lo = __builtin_amdgcn_readlane((int)yb, j);
+            const int hi = __builtin_amdgcn_readlane((int)(yb >> 32), j);
+            const double vj = __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+            acc[k] = fma(-m, vj, acc[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < TS_COLS; ++k) {
+        const int64_t c = c0 + k;
+        if (lane < r && c < nrhs) {
+            const double v = fred(acc[k], F);
+            if (right) B[c * ldb + lane] = v;
+            else B[(int64_t)lane * ldb + c] = v;
+        }
+    }
+}
+
+// ===========================================================================
 // TRSS leaf (Problem 1) of order r <= 64: the upper triangular X with
 // X^T U + U^T X = C (U unit upper, C symmetric).  With V = U^{-1} and Z = X V
 // (upper triangular) the equation reads Z + Z^T = V^T C V =: M, so Z is the
