@@ -394,7 +394,7 @@ struct Engine {
         }
         const int64_t nb = (r + 63) / 64;
         ensure_tinv(nb * 64);
-        LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trinv_blocks, dim3((unsigned)nb), dim3(256), 0, st, T, r, 0, ws.tinv, F);
+        LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trinv_blocks, dim3((unsigned)nb), dim3(1024), 0, st, T, r, 0, ws.tinv, F);
         trsm_ru_rec(B, m, r, T, ws.tinv);
     }
     void trsm_ru_rec(MatV B, int64_t m, int64_t r, MatV T, double* Nb) {
@@ -417,7 +417,7 @@ struct Engine {
         }
         const int64_t nb = (r + 63) / 64;
         ensure_tinv(nb * 64);
-        LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trinv_blocks, dim3((unsigned)nb), dim3(256), 0, st, T, r, 1, ws.tinv, F);
+        LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trinv_blocks, dim3((unsigned)nb), dim3(1024), 0, st, T, r, 1, ws.tinv, F);
         trsm_ll_rec(B, r, ncols, T, ws.tinv);
     }
     void trsm_ll_rec(MatV B, int64_t r, int64_t ncols, MatV T, double* Nb) {

@@ -864,29 +864,47 @@ __global__ __launch_bounds__(256) void k_trss_leaf(double* W, int64_t ld, int64_
 // triangular T (order r) gets N_k = I - T_kk^{-1}, row-major 64 x 64 (strict
 // lower part for a lower T, strict upper part for an upper T), so that
 // T_kk^{-1} X = X - N_k X and X T_kk^{-1} = X - X N_k.  One workgroup per
-// block; a lower block is inverted through its transpose ((T^T)^{-1} =
-// (T^{-1})^T).
+// block.  With L = T_kk (lower) or T_kk^T (upper; (T^T)^{-1} = (T^{-1})^T),
+// X = L^{-1} comes from L X = I by substitution: wave w solves columns
+// 4w .. 4w+3 with lane i holding row i; step j broadcasts the finished X[j][c]
+// (reduced, read from lane j) and each lane subtracts its L[i][j] times it.
+// Column c is zero above row c, so wave w starts at step 4w.  Rows at or past
+// the block's order act as the identity (N zero there).
 // ===========================================================================
-__global__ __launch_bounds__(256) void k_trinv_blocks(MatV T, int64_t r, int lower, double* N, Field F) {
-    __shared__ Blk Us, Vs, Ss;
+__global__ __launch_bounds__(1024) void k_trinv_blocks(MatV T, int64_t r, int lower, double* N, Field F) {
+    __shared__ double Ls[64][65];
     const int tid = threadIdx.x;
     const int64_t o = (int64_t)blockIdx.x * 64;
     const int rb = (int)min((int64_t)64, r - o);
-    for (int e = tid; e < 64 * 64; e += 256) {
-        const int a = e >> 6, b = e & 63;   // Us[a][b], a < b: T[a][b] (upper) or T[b][a] (lower)
-        double v = 0.0;
-        if (a < b && b < rb) v = lower ? T.p[(o + b) * T.rs + (o + a) * T.cs] : T.p[(o + a) * T.rs + (o + b) * T.cs];
-        Us[a][b] = fcen(v, F);
+    for (int e = tid; e < 64 * 64; e += 1024) {
+        const int hi = e >> 6, lw = e & 63;   // the source row's contiguous index runs fastest
+        const int a = lower ? hi : lw, b = lower ? lw : hi;
+        double v = 0.0;   // L[a][b], b < a
+        if (b < a && a < rb) v = lower ? T.p[(o + a) * T.rs + (o + b) * T.cs] : T.p[(o + b) * T.rs + (o + a) * T.cs];
+        Ls[a][b] = fcen(v, F);
     }
     __syncthreads();
-    tri_inv64(Us, Vs, Ss, F);
+    const int lane = tid & 63, c0 = 4 * (tid >> 6);
+    double acc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] = (lane == c0 + k) ? 1.0 : 0.0;
+    for (int j = c0; j + 1 < rb; ++j) {
+        const double m = Ls[lane][j];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t yb = __double_as_longlong(fredc(acc[k], F));
+            const int ylo = __builtin_amdgcn_readlane((int)yb, j);
+            const int yhi = __builtin_amdgcn_readlane((int)(yb >> 32), j);
+            acc[k] = fma(-m, __longlong_as_double(((int64_t)yhi << 32) | (uint32_t)ylo), acc[k]);
+        }
+    }
     double* Nk = N + (int64_t)blockIdx.x * 4096;
-    for (int e = tid; e < 64 * 64; e += 256) {
-        const int a = e >> 6, b = e & 63;
-        double v = 0.0;
-        if (lower) { if (a > b) v = fcan(fredc(-Vs[b][a], F), F); }
-        else if (a < b) v = fcan(fredc(-Vs[a][b], F), F);
-        Nk[a * 64 + b] = v;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = c0 + k;
+        const double v = (lane > c) ? fred(-acc[k], F) : 0.0;
+        if (lower) Nk[lane * 64 + c] = v;
+        else Nk[c * 64 + lane] = v;
     }
 }
 
