@@ -298,6 +298,8 @@ def main():
                             modp_tflops=round(g["flops"] / (g["ms"] / 1e3) / 1e12, 3) if g["ms"] > 0 else 0.0)
         roofline["launches"] = g["launches"]
         roofline["avg_launch_ms"] = round(g["ms"] / max(g["launches"], 1), 4)
+        # each operand read once, C read and written: the floor `traffic` is compared with
+        roofline["alg_bytes_per_launch"] = round(g["bytes"] / max(g["launches"], 1), 1)
     if full is not None:
         tot_ms = sum(v["ms"] for k2, v in full.items() if k2 != "host_sync")
         log("[bench] per-class GPU time of one extra step with every launch event-timed (ms; the events "

@@ -240,7 +240,9 @@ int pldl_set_path(pldl_ctx *ctx, int32_t path);
 typedef struct {
     int64_t launches;  /* number of launches (or synchronisations)               */
     double flops;      /* algorithmic mod-p flops (2 per multiply-add), classes 0, 8 */
-    double bytes;      /* algorithmic HBM bytes (read + write), class 5            */
+    double bytes;      /* algorithmic HBM bytes (read + write): class 5; classes
+                          0 and 8 count each operand read once and C read and
+                          written (8 B per FP64 residue, L B per INT8 limb set) */
     double ops8;       /* class 8: INT8 MFMA operations (L^2 byte products per
                           mod-p product, 2 per multiply-add)                        */
     double ms;         /* summed GPU duration of the launches (event-timed)        */

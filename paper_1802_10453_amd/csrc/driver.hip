@@ -81,7 +81,7 @@ struct Prof {
     int nts = 0;
     double wall_khz = 0.0;
     hipStream_t ts_stream = nullptr;
-    struct TRec { int cls; double flops, ops8; };
+    struct TRec { int cls; double flops, bytes, ops8; };
     std::vector<TRec> trecs;
 
     hipEvent_t ev() {
@@ -98,7 +98,7 @@ struct Prof {
     // the launch must fill (product classes only) instead of recording events.
     Stamp begin(hipStream_t st, int c, double flops = 0.0, double bytes = 0.0, double ops8 = 0.0) {
         if (!on || !((mask >> c) & 1u)) return Stamp{};
-        if (light) return stamp(st, c, flops, ops8);
+        if (light) return stamp(st, c, flops, bytes, ops8);
         open_a = ev();
         HIPCHK(hipEventRecord(open_a, st));
         open_cls = c; open_f = flops; open_b = bytes; open_o = ops8;
@@ -111,7 +111,7 @@ struct Prof {
         recs.push_back(Rec{open_a, b, open_cls, open_f, open_b, open_o});
         open_cls = -1;
     }
-    Stamp stamp(hipStream_t st, int c, double flops, double ops8) {
+    Stamp stamp(hipStream_t st, int c, double flops, double bytes, double ops8) {
         if (!ts0) {
             int dev = 0, khz = 0;
             HIPCHK(hipGetDevice(&dev));
@@ -123,7 +123,7 @@ struct Prof {
         }
         if (nts == NTS || (ts_stream && ts_stream != st)) harvest_stamps();
         ts_stream = st;
-        trecs.push_back(TRec{c, flops, ops8});
+        trecs.push_back(TRec{c, flops, bytes, ops8});
         const int k = nts++;
         return Stamp{ts0 + k, ts1 + k};
     }
@@ -140,7 +140,7 @@ struct Prof {
         HIPCHK(hipMemcpy(b.data(), ts1, nts * sizeof(unsigned long long), hipMemcpyDeviceToHost));
         for (int k = 0; k < nts; ++k) {
             pldl_kstat& s = tot.cls[trecs[k].cls];
-            s.launches += 1; s.flops += trecs[k].flops; s.ops8 += trecs[k].ops8;
+            s.launches += 1; s.flops += trecs[k].flops; s.bytes += trecs[k].bytes; s.ops8 += trecs[k].ops8;
             if (b[k] > a[k]) s.ms += (double)(b[k] - a[k]) / wall_khz;
         }
         nts = 0;
@@ -330,6 +330,10 @@ struct Engine {
     // (the limb split is timed as class OTHER, the INT8 product as class GEMM)
     void mm(double* C, int64_t ldc, int64_t m, int64_t nn, const GemmSeg* segs, int nseg, bool lower, bool b_upper,
             int32_t* nzrow, int32_t nzoff, double flops) {
+        double opnd = 0.0;   // operand elements, each read once
+        for (int q = 0; q < nseg; ++q)
+            if (segs[q].k > 0) opnd += (double)segs[q].k * ((double)m + (double)nn);
+        const double outs = lower ? (double)m * (double)(m + 1) / 2.0 : (double)m * (double)nn;
         if (path == PLDL_PATH_I8 && !nzrow && flops >= i8_min_flops) {
             i8->ensure(i8_workspace_bytes((uint32_t)F.ip, m, nn, segs, nseg), st);
             I8Product pr;
@@ -338,13 +342,14 @@ struct Engine {
             prof->end(st);
             if (ok) {
                 const int L = pr.L;
-                const Stamp sp = prof->begin(st, PLDL_CLASS_GEMM_I8, flops, 0.0, flops * (double)(L * L));
+                const Stamp sp = prof->begin(st, PLDL_CLASS_GEMM_I8, flops, (double)L * opnd + 16.0 * outs,
+                                             flops * (double)(L * L));
                 i8_run(st, F, pr, C, ldc, lower, sp);
                 prof->end(st);
                 return;
             }
         }
-        const Stamp sp = prof->begin(st, PLDL_CLASS_GEMM, flops);
+        const Stamp sp = prof->begin(st, PLDL_CLASS_GEMM, flops, 8.0 * opnd + 16.0 * outs);
         launch_gemm(st, F, m, nn, C, ldc, segs, nseg, lower, b_upper, nzrow, nzoff, sp);
         prof->end(st);
     }
