@@ -773,11 +773,20 @@ __device__ void mm64(const Blk& A, bool transA, const Blk& B, Blk& D, const Fiel
 __global__ __launch_bounds__(TS_THREADS) void k_trsm_small(double* B, int64_t ldb, int64_t nrhs, int r, MatV T,
                                                            int right, Field F) {
     __shared__ double Ms[64][65];
-    for (int e = threadIdx.x; e < 64 * 64; e += TS_THREADS) {
-        const int i = e >> 6, j = e & 63;
-        double v = 0.0;
-        if (j < i && i < r) v = right ? T.p[(int64_t)j * T.rs + (int64_t)i * T.cs] : T.p[(int64_t)i * T.rs + (int64_t)j * T.cs];
-        Ms[i][j] = fcen(v, F);
+    constexpr int NL = 64 * 64 / TS_THREADS;
+    double tv[NL] = {};
+    if (r >= 2)   // every load issued before the first wait; a position outside the strict triangle reads M[1][0]
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+            const int e = threadIdx.x + t * TS_THREADS, i0 = e >> 6, j0 = e & 63;
+            const bool in = j0 < i0 && i0 < r;
+            const int64_t i = in ? i0 : 1, j = in ? j0 : 0;
+            tv[t] = right ? T.p[j * T.rs + i * T.cs] : T.p[i * T.rs + j * T.cs];
+        }
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+        const int e = threadIdx.x + t * TS_THREADS, i = e >> 6, j = e & 63;
+        Ms[i][j] = (j < i && i < r) ? fcen(tv[t], F) : 0.0;
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -876,12 +885,21 @@ __global__ __launch_bounds__(1024) void k_trinv_blocks(MatV T, int64_t r, int lo
     const int tid = threadIdx.x;
     const int64_t o = (int64_t)blockIdx.x * 64;
     const int rb = (int)min((int64_t)64, r - o);
-    for (int e = tid; e < 64 * 64; e += 1024) {
-        const int hi = e >> 6, lw = e & 63;   // the source row's contiguous index runs fastest
+    double tv[4] = {};
+    if (rb >= 2)   // L[a][b], b < a; every load issued before the first wait (outside the strict triangle: L[1][0])
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int e = tid + t * 1024, hi = e >> 6, lw = e & 63;   // the source row's contiguous index runs fastest
+            const int a0 = lower ? hi : lw, b0 = lower ? lw : hi;
+            const bool in = b0 < a0 && a0 < rb;
+            const int64_t a = in ? a0 : 1, b = in ? b0 : 0;
+            tv[t] = lower ? T.p[(o + a) * T.rs + (o + b) * T.cs] : T.p[(o + b) * T.rs + (o + a) * T.cs];
+        }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int e = tid + t * 1024, hi = e >> 6, lw = e & 63;
         const int a = lower ? hi : lw, b = lower ? lw : hi;
-        double v = 0.0;   // L[a][b], b < a
-        if (b < a && a < rb) v = lower ? T.p[(o + a) * T.rs + (o + b) * T.cs] : T.p[(o + b) * T.rs + (o + a) * T.cs];
-        Ls[a][b] = fcen(v, F);
+        Ls[a][b] = (b < a && a < rb) ? fcen(tv[t], F) : 0.0;
     }
     __syncthreads();
     const int lane = tid & 63, c0 = 4 * (tid >> 6);
