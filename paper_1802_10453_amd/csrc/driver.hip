@@ -379,9 +379,10 @@ struct Engine {
     }
 
     // ---- TRSM (Section 3) ---------------------------------------------------
-    // Recursive halving (on multiples of 64) down to 64-blocks; the blocks'
-    // inverses come from one launch, and each leaf is one product applied in
-    // place: the output has a single column tile (right solve, r <= 64) or a
+    // A triangle of order <= 64 is one substitution launch (k_trsm_small).
+    // Larger ones: recursive halving (on multiples of 64) down to 64-blocks; the
+    // blocks' inverses come from one launch, and each leaf is one product applied
+    // in place: the output has a single column tile (right solve, r <= 64) or a
     // single row tile (left solve), so every workgroup of k_gemm reads all of
     // its operand rows (columns) before it writes them, and the INT8 path reads
     // the limb planes it made beforehand.
