@@ -45,13 +45,32 @@ extern "C" {
 
 typedef struct pldl_ctx pldl_ctx;
 
+/* What a pldl_factor call did, for reproducing it (filled when sched_out is
+ * not NULL).  The factorization is a function of (A, p, threshold_used,
+ * split_rule); path_used and the product counts change no result (both
+ * product paths are exact). */
+typedef struct {
+    int32_t threshold_used;   /* base-case order t of the cascade (Section 5)           */
+    int32_t split_rule;       /* granule g of the recursive split: a range of order N
+                                 >= 2g splits at m = floor(N/2) rounded down to a
+                                 multiple of g (g = 64); smaller ones at floor(N/2)   */
+    int32_t path_used;        /* PLDL_PATH_F64 or PLDL_PATH_I8                          */
+    int32_t i8_min_log2_flops;/* INT8 path: products of fewer flops stay on FP64 (2^k) */
+    int64_t products_f64;     /* products run on the FP64 matrix cores                  */
+    int64_t products_i8;      /* products run on the INT8 matrix cores                  */
+    int64_t launches;         /* kernel launches and stream memory operations queued    */
+    int64_t host_waits;       /* host synchronisations of the stream inside the call    */
+} pldl_schedule;
+
 typedef struct {
     int32_t path;          /* PLDL_PATH_*                                              */
     int32_t threshold;     /* base-case order t of the cascade (Section 5), 1..128;
                               0 = the context's autotuned value (pldl_autotune), else 128 */
     int32_t standard_form; /* p == 2 only: turn relaxed 2x2 blocks into the standard
                               form of Section 2.3 (after the rank profile is taken)     */
-    int32_t check_range;   /* nonzero: reject inputs with an entry >= p (PLDL_ERANGE)   */
+    int32_t check_range;   /* nonzero: reject inputs with an entry >= p (PLDL_ERANGE);
+                              zero: such entries are read mod p (a negative or
+                              fractional FP64 entry as 0)                              */
 } pldl_opts;
 
 /* Create a context bound to HIP device `device`.  *ctx receives the handle. */
@@ -86,12 +105,19 @@ const char *pldl_last_error(const pldl_ctx *ctx);
  *         rook placement with r ones).
  *  rank   host int64*: receives r (the call synchronises `stream`).
  *  opts   may be NULL (defaults).
+ *  sched_out  host, may be NULL: receives the schedule the call used
+ *         (threshold, split rule, product path and counts, launches, waits).
+ * Errors: -1 ctx NULL; -3 n outside [0, 65535]; -4 A NULL; -5 lda < max(1, n);
+ * -6 unknown dtype; -7 e NULL; -8 perm NULL; -9 rpm NULL; -10 rank NULL;
+ * -11 opts invalid (path or threshold outside [0, 128]); PLDL_EUNSUPPORTED_P
+ * for p outside [2, 2^23); PLDL_ERANGE when opts->check_range is set and an
+ * input entry is >= p (nothing else is written); PLDL_ENOMEM, PLDL_EHIP.
  * With standard_form set and p == 2, perm/L/diag/e are returned in the standard
  * form of Section 2.3 while rpm still holds R.
  */
 int pldl_factor(pldl_ctx *ctx, uint32_t p, int64_t n, void *A, int64_t lda, int32_t dtype,
                 void *e, int32_t *perm, int32_t *rpm, int64_t *rank, const pldl_opts *opts,
-                void *stream);
+                pldl_schedule *sched_out, void *stream);
 
 /*
  * pldl_factor_batched -- `batch` independent factorizations (each as

@@ -128,6 +128,9 @@ void launch_factor_batched(hipStream_t s, const Field& F, const uint32_t* itab, 
                            int32_t* const* rpm, int64_t* rank, int32_t* status, int check_range, void* ws,
                            int slots, int32_t* queue);
 
+// Longest K (summed over the segments of one product) the INT8 split accumulates
+// exactly in INT32: a shift class gains at most 2^15 per k, 65535 * 2^15 < 2^31.
+constexpr int64_t I8_MAX_KTOT = 65535;
 // Products below this many flops stay on FP64 inside a factorization.
 constexpr double I8_MIN_FLOPS = 134217728.0;   // 2^27: below it the limb split costs more than it saves
 

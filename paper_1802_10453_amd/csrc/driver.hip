@@ -83,6 +83,9 @@ struct Prof {
     hipStream_t ts_stream = nullptr;
     struct TRec { int cls; double flops, bytes, ops8; };
     std::vector<TRec> trecs;
+    // counts of the current call (pldl_schedule): dispatches queued, host waits, products per path
+    int64_t n_launch = 0, n_wait = 0, n_f64 = 0, n_i8 = 0;
+    void reset_counts() { n_launch = n_wait = n_f64 = n_i8 = 0; }
 
     hipEvent_t ev() {
         if (pool.empty()) {
@@ -176,6 +179,7 @@ struct Prof {
 #define LAUNCH(CLS, KERNEL, GRID, BLOCK, SHM, STREAM, ...)                  \
     do {                                                                   \
         prof->begin(STREAM, CLS);                                          \
+        prof->n_launch++;                                                  \
         hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, __VA_ARGS__); \
         prof->end(STREAM);                                                 \
     } while (0)
@@ -264,8 +268,9 @@ struct I8Space {
         p = nullptr;
         cap = 0;
     }
-    void ensure(size_t bytes, hipStream_t st) {
-        if (bytes <= cap) return;
+    // returns true when it had to wait for the stream (a larger buffer)
+    bool ensure(size_t bytes, hipStream_t st) {
+        if (bytes <= cap) return false;
         HIPCHK(hipStreamSynchronize(st));   // the old planes may still be read
         release();
         size_t want = std::max(bytes, cap + cap / 2);
@@ -275,6 +280,7 @@ struct I8Space {
             throw Err(PLDL_ENOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
         }
         cap = want;
+        return true;
     }
 };
 
@@ -304,12 +310,14 @@ struct Engine {
     // words the device wrote into `info` (device memory): copied back after the queued work
     int32_t* read_info(int cnt, int off = 0) {
         HIPCHK(hipMemcpyAsync(ws.hinfo, ws.info + off, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        prof->n_launch++;
         return read_host();
     }
     // words the device wrote straight into the pinned host words: only a wait
     int32_t* read_host() {
         auto t0 = std::chrono::steady_clock::now();
         HIPCHK(hipStreamSynchronize(st));
+        prof->n_wait++;
         if (prof->on && !prof->light) {   // (stamps are collected when their slots run out, or at pldl_profile)
             prof->host_wait(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
             prof->harvest();
@@ -324,18 +332,31 @@ struct Engine {
         if (s0.k > 0 && s1.k > 0) REQUIRE((s0.A.cs == 1) == (s1.A.cs == 1) && (s0.B.cs == 1) == (s1.B.cs == 1));
         double kk = (double)std::max<int64_t>(s0.k, 0) + (double)std::max<int64_t>(s1.k, 0);
         double outs = lower ? (double)m * (double)(m + 1) / 2.0 : (double)m * (double)nn;
-        mm(C, ld, m, nn, segs, 2, lower, b_upper, nullptr, 0, 2.0 * outs * kk);
+        double flops = 2.0 * outs * kk;
+        if (b_upper && s0.k > 0 && !lower) {
+            // segment 0's B is upper triangular: output column j sums min(j + 1, k) products
+            const double k0 = (double)s0.k, nc = (double)nn;
+            const double tri = nc <= k0 ? nc * (nc + 1) / 2.0 : k0 * (k0 + 1) / 2.0 + (nc - k0) * k0;
+            flops -= 2.0 * (double)m * (nc * k0 - tri);
+        }
+        mm(C, ld, m, nn, segs, 2, lower, b_upper, nullptr, 0, flops);
     }
     // one product on the selected matrix cores (INT8 split needs no first-nonzero detection)
-    // (the limb split is timed as class OTHER, the INT8 product as class GEMM)
+    // (the limb split is timed as class OTHER, the INT8 product as class GEMM).  flops: the
+    // useful work recorded by the profile (structural zeros of a triangular operand left
+    // out); the path is chosen on the work the matrix cores do (every product of the tiles).
     void mm(double* C, int64_t ldc, int64_t m, int64_t nn, const GemmSeg* segs, int nseg, bool lower, bool b_upper,
             int32_t* nzrow, int32_t nzoff, double flops) {
         double opnd = 0.0;   // operand elements, each read once
+        double ksum = 0.0;
         for (int q = 0; q < nseg; ++q)
-            if (segs[q].k > 0) opnd += (double)segs[q].k * ((double)m + (double)nn);
+            if (segs[q].k > 0) {
+                opnd += (double)segs[q].k * ((double)m + (double)nn);
+                ksum += (double)segs[q].k;
+            }
         const double outs = lower ? (double)m * (double)(m + 1) / 2.0 : (double)m * (double)nn;
-        if (path == PLDL_PATH_I8 && !nzrow && flops >= i8_min_flops) {
-            i8->ensure(i8_workspace_bytes((uint32_t)F.ip, m, nn, segs, nseg), st);
+        if (path == PLDL_PATH_I8 && !nzrow && 2.0 * outs * ksum >= i8_min_flops) {
+            if (i8->ensure(i8_workspace_bytes((uint32_t)F.ip, m, nn, segs, nseg), st)) prof->n_wait++;
             I8Product pr;
             prof->begin(st, PLDL_CLASS_OTHER);
             const bool ok = i8_prepare(st, F, m, nn, segs, nseg, b_upper, i8->p, i8->cap, &pr);
@@ -346,12 +367,17 @@ struct Engine {
                                              flops * (double)(L * L));
                 i8_run(st, F, pr, C, ldc, lower, sp);
                 prof->end(st);
+                for (int q = 0; q < nseg; ++q) prof->n_launch += (segs[q].k > 0) ? 2 : 0;
+                prof->n_launch++;
+                prof->n_i8++;
                 return;
             }
         }
         const Stamp sp = prof->begin(st, PLDL_CLASS_GEMM, flops, 8.0 * opnd + 16.0 * outs);
         launch_gemm(st, F, m, nn, C, ldc, segs, nseg, lower, b_upper, nzrow, nzoff, sp);
         prof->end(st);
+        prof->n_launch++;
+        prof->n_f64++;
     }
 
     // Symmetric permutation of [lo, hi): new lo+q <- old lo+sig[q].
@@ -376,6 +402,7 @@ struct Engine {
         hipLaunchKernelGGL(k_perm_sym, dim3((unsigned)blocks), dim3(256), 0, st, W, ld, g, sig, ws.tmp1, ws.orig, ws.tmpo, 0);
         hipLaunchKernelGGL(k_perm_sym, dim3((unsigned)blocks), dim3(256), 0, st, W, ld, g, sig, ws.tmp1, ws.orig, ws.tmpo, 1);
         prof->end(st);
+        prof->n_launch += 2;
     }
 
     // ---- TRSM (Section 3) ---------------------------------------------------
@@ -404,8 +431,9 @@ struct Engine {
         trsm_ru_rec(B, m, r, T, ws.tinv);
     }
     void trsm_ru_rec(MatV B, int64_t m, int64_t r, MatV T, double* Nb) {
-        if (r <= 64) {   // B <- B - B N
-            gemm_ld(B.p, B.rs, m, r, GemmSeg{MatV{B.p, B.rs, 1}, MatV{Nb, 64, 1}, r});
+        if (r <= 64) {   // B <- B - B N (N strictly upper: column j sums j products)
+            gemm_ld(B.p, B.rs, m, r, GemmSeg{MatV{B.p, B.rs, 1}, MatV{Nb, 64, 1}, r}, nullptr, 0,
+                    (double)m * (double)r * (double)(r - 1));
             return;
         }
         int64_t r1 = std::max<int64_t>(64, (r / 2) / 64 * 64);
@@ -427,8 +455,9 @@ struct Engine {
         trsm_ll_rec(B, r, ncols, T, ws.tinv);
     }
     void trsm_ll_rec(MatV B, int64_t r, int64_t ncols, MatV T, double* Nb) {
-        if (r <= 64) {   // B <- B - N B
-            gemm_ld(B.p, B.rs, r, ncols, GemmSeg{MatV{Nb, 64, 1}, MatV{B.p, B.rs, 1}, r});
+        if (r <= 64) {   // B <- B - N B (N strictly lower: row i sums i products)
+            gemm_ld(B.p, B.rs, r, ncols, GemmSeg{MatV{Nb, 64, 1}, MatV{B.p, B.rs, 1}, r}, nullptr, 0,
+                    (double)ncols * (double)r * (double)(r - 1));
             return;
         }
         int64_t r1 = std::max<int64_t>(64, (r / 2) / 64 * 64);
@@ -441,6 +470,7 @@ struct Engine {
     void ensure_tinv(int64_t rows) {
         if (rows <= ws.tinv_rows) return;
         HIPCHK(hipStreamSynchronize(st));
+        prof->n_wait++;
         HIPCHK(hipFree(ws.tinv));
         ws.tinv = nullptr;
         ws.tinv_rows = 0;
@@ -451,9 +481,12 @@ struct Engine {
         }
         ws.tinv_rows = rows;
     }
-    void gemm_ld(double* C, int64_t ldc, int64_t m, int64_t nn, GemmSeg s0, int32_t* nzrow = nullptr, int32_t nzoff = 0) {
+    // flops < 0: the dense count 2 m nn k (else the useful flops of a structured operand)
+    void gemm_ld(double* C, int64_t ldc, int64_t m, int64_t nn, GemmSeg s0, int32_t* nzrow = nullptr, int32_t nzoff = 0,
+                 double flops = -1.0) {
         if (m <= 0 || nn <= 0 || s0.k <= 0) return;
-        mm(C, ldc, m, nn, &s0, 1, false, false, nzrow, nzoff, 2.0 * (double)m * (double)nn * (double)s0.k);
+        mm(C, ldc, m, nn, &s0, 1, false, false, nzrow, nzoff,
+           flops >= 0.0 ? flops : 2.0 * (double)m * (double)nn * (double)s0.k);
     }
 
     // ---- base case (Section 5) ------------------------------------------------
@@ -520,6 +553,7 @@ struct Engine {
         double* delta = ws.dvec;          // Delta (rY) then the pack diagonal d (rY)
         if (rY > 0) {
             HIPCHK(hipMemsetAsync(delta, 0, rY * sizeof(double), st));
+            prof->n_launch++;
             LAUNCH(PLDL_CLASS_OTHER, k_save_pack_diag, dim3(nblk(rY)), dim3(256), 0, st, W, ld, s0, lo, rY, delta + rY);
             if (F.ip == 2) {
                 REQUIRE(rY <= 8192);
@@ -599,7 +633,10 @@ struct Engine {
     }
     int32_t* snapshot(const int32_t* src, int64_t len) {
         int32_t* p = ipush(std::max<int64_t>(len, 1));
-        if (len > 0) HIPCHK(hipMemcpyAsync(p, src, len * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+        if (len > 0) {
+            HIPCHK(hipMemcpyAsync(p, src, len * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+            prof->n_launch++;
+        }
         return p;
     }
     // src[q] = old position of the entry now at q, from a snapshot of an index segment
@@ -623,6 +660,7 @@ struct Engine {
         hipLaunchKernelGGL(k_tcolperm, g, dim3(256), 0, st, T, ldT, j0, len, src, i0, ni, ws.tmp1, 0);
         hipLaunchKernelGGL(k_tcolperm, g, dim3(256), 0, st, T, ldT, j0, len, src, i0, ni, ws.tmp1, 1);
         prof->end(st);
+        prof->n_launch += 2;
     }
     // reorder T columns [i0, i0+len) (Y rows) by src, within T rows [j0, j0+nj)
     void trowperm(int64_t j0, int64_t nj, int64_t i0, int64_t len, const int32_t* src) {
@@ -633,6 +671,7 @@ struct Engine {
         hipLaunchKernelGGL(k_trowperm, g, dim3(256), 0, st, T, ldT, j0, nj, i0, len, src, ws.tmp1, 0);
         hipLaunchKernelGGL(k_trowperm, g, dim3(256), 0, st, T, ldT, j0, nj, i0, len, src, ws.tmp1, 1);
         prof->end(st);
+        prof->n_launch += 2;
     }
     // idx[a + q] <- idx[a + src[q]]
     void idx_reorder(int32_t* idx, int64_t a, int64_t len, const int32_t* src) {
@@ -895,7 +934,7 @@ int pldl_destroy(pldl_ctx* ctx) {
 const char* pldl_last_error(const pldl_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 int pldl_factor(pldl_ctx* ctx, uint32_t p, int64_t n, void* A, int64_t lda, int32_t dtype, void* e, int32_t* perm,
-                int32_t* rpm, int64_t* rank, const pldl_opts* opts, void* stream) {
+                int32_t* rpm, int64_t* rank, const pldl_opts* opts, pldl_schedule* sched_out, void* stream) {
     if (!ctx) return -1;
     if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
     if (n < 0 || n > 65535) return fail(ctx, -3, "n out of range [0, 65535]");
@@ -912,16 +951,32 @@ int pldl_factor(pldl_ctx* ctx, uint32_t p, int64_t n, void* A, int64_t lda, int3
         return fail(ctx, -11, "unknown path");
     if (o.threshold < 0 || o.threshold > 128) return fail(ctx, -11, "threshold must be in [0, 128]");
     int t = o.threshold ? o.threshold : ctx->tuned_threshold(p, n);
-    if (n == 0) { *rank = 0; return PLDL_OK; }
+    const int path_used = o.path == PLDL_PATH_AUTO ? ctx->path : o.path;
+    ctx->prof.reset_counts();
+    auto fill_sched = [&]() {
+        if (!sched_out) return;
+        pldl_schedule sc{};
+        sc.threshold_used = t;
+        sc.split_rule = 64;
+        sc.path_used = path_used;
+        sc.i8_min_log2_flops = (int32_t)std::lround(std::log2(I8_MIN_FLOPS));
+        sc.products_f64 = ctx->prof.n_f64;
+        sc.products_i8 = ctx->prof.n_i8;
+        sc.launches = ctx->prof.n_launch;
+        sc.host_waits = ctx->prof.n_wait;
+        *sched_out = sc;
+    };
+    if (n == 0) { *rank = 0; fill_sched(); return PLDL_OK; }
     hipStream_t st = as_stream(stream);
-    return guarded(ctx, [&]() {
+    const int rc = guarded(ctx, [&]() {
         ctx->ws.ensure(n);
         Engine E(ctx->ws, st, p, n, t, &ctx->prof);
-        ctx->setup(E, o.path == PLDL_PATH_AUTO ? ctx->path : o.path, I8_MIN_FLOPS);
+        ctx->setup(E, path_used, I8_MIN_FLOPS);
         E.itab = ctx->inv_table(p, st);
         Prof* prof = &ctx->prof;
         Workspace& ws = ctx->ws;
         HIPCHK(hipMemsetAsync(ws.info, 0, sizeof(int32_t) * 4, st));
+        prof->n_launch++;
         dim3 g(nblk(n), (unsigned)n);
         if (dtype == PLDL_U32)
             LAUNCH(PLDL_CLASS_OTHER, k_load_input<uint32_t>, g, dim3(256), 0, st, (const uint32_t*)A, lda, ws.W, E.ld, n, E.F, ws.info + 2);
@@ -934,6 +989,7 @@ int pldl_factor(pldl_ctx* ctx, uint32_t p, int64_t n, void* A, int64_t lda, int3
         LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(n)), dim3(256), 0, st, ws.orig, n);
         HIPCHK(hipMemsetAsync(ws.dd, 0, sizeof(double) * n, st));
         HIPCHK(hipMemsetAsync(ws.de, 0, sizeof(double) * n, st));
+        prof->n_launch += 2;
         int64_t r = E.recall(0, n);
         LAUNCH(PLDL_CLASS_OTHER, k_rpm, dim3(nblk(n)), dim3(256), 0, st, ws.orig, ws.de, n, r, rpm);
         if (o.standard_form && p == 2) {
@@ -948,8 +1004,11 @@ int pldl_factor(pldl_ctx* ctx, uint32_t p, int64_t n, void* A, int64_t lda, int3
             LAUNCH(PLDL_CLASS_OTHER, k_store_output<double>, g, dim3(256), 0, st, (double*)A, lda, ws.W, E.ld, n, ws.dd, ws.de, (double*)e, ws.orig, perm);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
+        prof->n_wait++;
         *rank = r;
     });
+    if (rc == PLDL_OK) fill_sched();
+    return rc;
 }
 
 int pldl_gemm(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t transA,
@@ -1288,7 +1347,7 @@ int pldl_autotune(pldl_ctx* ctx, uint32_t p, const int64_t* n_list, int64_t coun
                             pldl_opts o{PLDL_PATH_AUTO, t, 0, 0};
                             int64_t rk = 0;
                             const auto t0 = std::chrono::steady_clock::now();
-                            const int frc = pldl_factor(ctx, p, n, Aw, n, PLDL_F64, ev, perm, rpm, &rk, &o, stream);
+                            const int frc = pldl_factor(ctx, p, n, Aw, n, PLDL_F64, ev, perm, rpm, &rk, &o, nullptr, stream);
                             const double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
                             if (frc != PLDL_OK) throw Err(frc, "factorization during tuning failed: " + ctx->err);
                             ms[cls] = std::min(ms[cls], el);

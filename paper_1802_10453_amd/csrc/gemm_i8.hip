@@ -9,9 +9,14 @@
 //   p < 2^23, the top digit then has |a_{L-1}| <= 64),
 //
 // so that A B = sum_s 256^s C_s with C_s = sum_{t+u=s} A_t B_u.  Every C_s is
-// accumulated exactly in INT32 by v_mfma_i32_16x16x64_i8 (at most
-// L * K * 2^14 < 2^31 for K <= 32768) and recombined once, in the epilogue:
-// sum_s w_s (C_s mod p) with w_s = 256^s mod p, reduced in FP64.
+// accumulated exactly in INT32 by v_mfma_i32_16x16x64_i8 and recombined once,
+// in the epilogue: sum_s w_s (C_s mod p) with w_s = 256^s mod p, reduced in
+// FP64.  Bound: a digit pair contributes at most 2^14 per k (2^13 when one
+// digit is a top digit, |top| <= 64), so a shift class gains at most 2^15 per
+// k for every L (L = 3, s = 1: two pairs of full digits; s = 2: one pair of
+// full digits and two with a top digit).  Both segments of SYRD2K accumulate
+// into the same registers, hence the condition K0 + K1 <= 65535
+// (65535 * 2^15 < 2^31); a longer product falls back to FP64.
 //
 // Operands are first split into K-contiguous limb planes (one pass, 8 bytes
 // read and L bytes written per element; K padded to a multiple of 64 with
@@ -19,6 +24,7 @@
 // MFMA fragment is then 16 contiguous bytes per lane: lane l takes row l%16
 // (of A) or column l%16 (of B^T) and the k-group l/16 of each 64-wide K step,
 // the same k map on both sides as the instruction requires.
+#include <algorithm>
 #include <cmath>
 
 #include "common.h"
@@ -238,8 +244,9 @@ bool i8_prepare(hipStream_t s, const Field& F, int64_t m, int64_t n, const GemmS
     const uint32_t p = (uint32_t)F.ip;
     const int L = i8_limbs(p);
     if (i8_workspace_bytes(p, m, n, segs, nseg) > ws_bytes) return false;
-    for (int i = 0; i < nseg && i < 2; ++i)
-        if (segs[i].k > 32768) return false;   // INT32 accumulation bound
+    int64_t ktot = 0;   // both segments share the INT32 accumulators
+    for (int i = 0; i < nseg && i < 2; ++i) ktot += std::max<int64_t>(segs[i].k, 0);
+    if (ktot > I8_MAX_KTOT) return false;
     *out = I8Product{};
     out->m = m; out->n = n; out->L = L;
     int8_t* cur = ws;

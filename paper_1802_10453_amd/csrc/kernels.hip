@@ -1223,7 +1223,11 @@ __global__ void k_load_input(const T* A, int64_t lda, double* W, int64_t ld, int
     int64_t i = blockIdx.y;
     if (i >= n || j > i) return;
     double v = (double)A[i * lda + j];
-    if (!(v >= 0.0 && v < F.p && v == floor(v))) { atomicExch(err, 1); v = 0.0; }
+    if (!(v >= 0.0 && v < F.p && v == floor(v))) {
+        atomicExch(err, 1);
+        // read mod p when the range is not checked (a negative or fractional entry as 0)
+        v = (v >= 0.0 && v == floor(v) && v < 9007199254740992.0) ? fmod(v, F.p) : 0.0;
+    }
     W[i * ld + j] = v;
 }
 

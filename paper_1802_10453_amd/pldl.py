@@ -25,6 +25,7 @@ _vp, _i64, _i32, _u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.
 PLDL_U32, PLDL_F64 = 0, 1
 PLDL_PATH_AUTO, PLDL_PATH_F64, PLDL_PATH_I8 = 0, 1, 2
 ERRORS = {1: "PLDL_ERANGE", 2: "PLDL_EUNSUPPORTED_P", 3: "PLDL_EHIP", 4: "PLDL_ENOMEM", 5: "PLDL_EINTERNAL"}
+ERRORS_BY_NAME = {v: k for k, v in ERRORS.items()}
 
 
 CLASS_NAMES = ("gemm", "trsm_leaf", "base_case", "plduq_leaf", "trss_leaf", "perm", "other", "host_sync", "gemm_i8")
@@ -43,12 +44,20 @@ class pldl_opts(ctypes.Structure):
     _fields_ = [("path", _i32), ("threshold", _i32), ("standard_form", _i32), ("check_range", _i32)]
 
 
+class pldl_schedule(ctypes.Structure):
+    _fields_ = [("threshold_used", _i32), ("split_rule", _i32), ("path_used", _i32), ("i8_min_log2_flops", _i32),
+                ("products_f64", _i64), ("products_i8", _i64), ("launches", _i64), ("host_waits", _i64)]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
 _lib.pldl_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int]
 _lib.pldl_destroy.argtypes = [_vp]
 _lib.pldl_last_error.argtypes = [_vp]
 _lib.pldl_last_error.restype = ctypes.c_char_p
 _lib.pldl_factor.argtypes = [_vp, _u32, _i64, _vp, _i64, _i32, _vp, _vp, _vp, ctypes.POINTER(_i64),
-                             ctypes.POINTER(pldl_opts), _vp]
+                             ctypes.POINTER(pldl_opts), ctypes.POINTER(pldl_schedule), _vp]
 _lib.pldl_gemm.argtypes = [_vp, _u32, _i64, _i64, _i64, _vp, _i64, _i32, _vp, _i64, _i32, _vp, _i64, _i32, _vp]
 _lib.pldl_trsm.argtypes = [_vp, _u32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp]
 _lib.pldl_syrdk.argtypes = [_vp, _u32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _i64, _vp]
@@ -126,7 +135,7 @@ class Context:
     def factor(self, A: torch.Tensor, p: int, threshold: int = 0, standard_form: bool = False,
                check_range: bool = True, path: int = PLDL_PATH_AUTO):
         """Factor the symmetric A (lower triangle; int32 holding uint32 residues, or float64)
-        in place.  Returns dict(perm, rpm, e, rank)."""
+        in place.  Returns dict(perm, rpm, e, rank, schedule)."""
         n = A.shape[0]
         assert A.dim() == 2 and A.shape[1] == n and A.is_cuda
         if A.dtype == torch.int32:
@@ -140,10 +149,11 @@ class Context:
         rpm = torch.zeros(max(n, 1), dtype=torch.int32, device=A.device)
         rank = _i64(0)
         o = pldl_opts(int(path), int(threshold), int(bool(standard_form)), int(bool(check_range)))
+        sc = pldl_schedule()
         rc = _lib.pldl_factor(self._h, int(p), n, _ptr(A), _ld(A) if n else 1, dt, _ptr(e), _ptr(perm), _ptr(rpm),
-                              ctypes.byref(rank), ctypes.byref(o), _stream())
+                              ctypes.byref(rank), ctypes.byref(o), ctypes.byref(sc), _stream())
         self._check(rc)
-        return dict(perm=perm[:n], rpm=rpm[:n], e=e[:n], rank=int(rank.value))
+        return dict(perm=perm[:n], rpm=rpm[:n], e=e[:n], rank=int(rank.value), schedule=sc.as_dict())
 
     def char2_to_standard(self, A: torch.Tensor, e: torch.Tensor, perm: torch.Tensor):
         """pldl_char2_to_standard on pldl_factor's outputs (p = 2), in place."""
@@ -188,11 +198,15 @@ class Context:
         self._check(rc)
         return args
 
-    def factor_raw(self, p, n, A_ptr, lda, dtype, e_ptr, perm_ptr, rpm_ptr, opts=None):
-        """Direct call with raw device pointers (used by the boundary tests)."""
+    def factor_raw(self, p, n, A_ptr, lda, dtype, e_ptr, perm_ptr, rpm_ptr, opts=None, rank_out=True,
+                   schedule=None):
+        """pldl_factor with raw device pointers and no checks on this side, returning the
+        status code instead of raising (the argument-error tests use it)."""
         rank = _i64(0)
-        rc = _lib.pldl_factor(self._h, p, n, A_ptr, lda, dtype, e_ptr, perm_ptr, rpm_ptr, ctypes.byref(rank),
-                              ctypes.byref(opts) if opts is not None else None, _stream())
+        rc = _lib.pldl_factor(self._h, p, n, A_ptr, lda, dtype, e_ptr, perm_ptr, rpm_ptr,
+                              ctypes.byref(rank) if rank_out else None,
+                              ctypes.byref(opts) if opts is not None else None,
+                              ctypes.byref(schedule) if schedule is not None else None, _stream())
         return rc, int(rank.value)
 
     def profile(self, mode: int) -> dict:

@@ -89,3 +89,24 @@ def structure(res, p):
             q += 2
     assert (dd[r:] == 0).all() and (de[r:] == 0).all()
     assert (rpm[perm[r:]] == -1).all()
+
+
+def freivalds_f2(A, res, nvec=64, seed=0):
+    """Over F_2: A V == P L D L^T P^T V for nvec random 0/1 columns at once (the
+    matrix products run in float64, exact: every sum is below n < 2^53).  A wrong
+    factorization passes with probability at most 2^-nvec."""
+    n = A.shape[0]
+    g = np.random.Generator(np.random.PCG64(seed))
+    V = g.integers(0, 2, size=(n, nvec)).astype(np.float64)
+    perm = res["perm"].astype(np.int64)
+    Lf = res["L"].astype(np.float64)
+    dd, de = res["dd"].astype(np.float64), res["de"].astype(np.float64)
+    lhs = np.mod(A.astype(np.float64) @ V, 2.0)
+    U = np.mod(Lf.T @ V[perm], 2.0)                     # L^T P^T V
+    T = dd[:, None] * U
+    T[1:] += de[:-1, None] * U[:-1]
+    T[:-1] += de[:-1, None] * U[1:]
+    Y = np.mod(Lf @ np.mod(T, 2.0), 2.0)
+    rhs = np.zeros_like(Y)
+    rhs[perm] = Y
+    assert (lhs == rhs).all(), "Freivalds reconstruction check over F_2 failed"

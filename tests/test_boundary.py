@@ -38,7 +38,7 @@ def test_null_context_rejected_without_device():
     lib.pldl_factor.restype = ctypes.c_int
     rank = ctypes.c_int64(0)
     rc = lib.pldl_factor(None, ctypes.c_uint32(65521), ctypes.c_int64(4), None, ctypes.c_int64(4), 0, None, None,
-                         None, ctypes.byref(rank), None, None)
+                         None, ctypes.byref(rank), None, None, None)
     assert rc == -1
     lib.pldl_last_error.restype = ctypes.c_char_p
     assert lib.pldl_last_error(None) == b"null context"

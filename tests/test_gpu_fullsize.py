@@ -14,7 +14,7 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 import oracle.oracle as orc  # noqa: E402
 from paper_1802_10453_amd import inputs  # noqa: E402
 
-from gpu_helpers import freivalds, gpu_factor, structure  # noqa: E402
+from gpu_helpers import freivalds, freivalds_f2, gpu_factor, structure  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -46,18 +46,34 @@ def test_c2_full_size(ctx, c2_input, path):
     assert res["rank"] == cfg["f"] + 2 * cfg["c"]
     assert (res["rpm"] == rpm).all()
     structure(res, cfg["p"])
-    freivalds(A, cfg["p"], res, trials=2)
+    freivalds(A, cfg["p"], res, trials=3)
 
 
 def test_c4_full_size(ctx):
+    """The n = 8192 characteristic-2 workload: R against the closed form, (L, D, e)
+    against the oracle's replay of the GPU's P (bit-exact), A = P L D L^T P^T by 64
+    random vectors over F_2, and the Section 2.3 standard form against the
+    oracle's transform of that replay, element by element."""
     cfg = inputs.C4
     print("[fullsize] generating the n=8192 characteristic-2 input", flush=True)
     A, rpm = inputs.config_input(cfg, device="cuda", check=8)
     res = gpu_factor(ctx, A, 2)
-    assert res["rank"] == cfg["f"] + 2 * cfg["c"]
+    r = cfg["f"] + 2 * cfg["c"]
+    assert res["rank"] == r
     assert (res["rpm"] == rpm).all()
     structure(res, 2)
-    freivalds(A, 2, res, trials=2)
+    freivalds_f2(A, res, nvec=64)
+    print("[fullsize] oracle replay of the GPU pivot order (n=8192)", flush=True)
+    rc, rp = orc.replay(A, 2, res["perm"], res["rpm"], r)
+    assert rc == 0
+    for key in ("L", "dd", "de"):
+        assert (rp[key] == res[key]).all(), key
+    std = gpu_factor(ctx, A, 2, standard_form=True)
+    assert (std["perm"][:r] != res["perm"][:r]).any(), "the workload has relaxed blocks to transform"
+    perm_s, L_s, dd_s, de_s = orc.char2_standard(rp["perm"], rp["L"], rp["dd"], rp["de"])
+    assert (std["perm"] == perm_s).all() and (std["rpm"] == rpm).all()
+    assert (std["L"] == L_s).all() and (std["dd"] == dd_s).all() and (std["de"] == de_s).all()
+    freivalds_f2(A, std, nvec=64, seed=1)
 
 
 def test_c3_full_batch(ctx):

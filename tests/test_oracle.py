@@ -491,3 +491,69 @@ def test_effective_ops_formula():
     # Section 6: r^3/3 + n^2 r - r^2 n; full rank gives n^3/3
     assert orc.effective_ops(30, 30) == pytest.approx(30 ** 3 / 3)
     assert orc.effective_ops(16384, 12288) == pytest.approx(1.4431e12, rel=1e-4)
+
+
+# ---------------------------------------------------------------- reconstruction routine
+def _random_factors(g, n, p, char2_relaxed=False):
+    """A random (perm, L, D) with 1x1 and 2x2 blocks (relaxed ones in characteristic 2),
+    built directly: no elimination involved."""
+    perm = g.permutation(n).astype(np.int32)
+    L = np.tril(g.integers(0, p, size=(n, n)), -1).astype(np.uint32)
+    L[np.arange(n), np.arange(n)] = 1
+    dd = np.zeros(n, dtype=np.uint32)
+    de = np.zeros(n, dtype=np.uint32)
+    q = 0
+    r = int(g.integers(0, n + 1))
+    while q < r:
+        if q + 1 < r and g.integers(0, 2):
+            de[q] = int(g.integers(1, p))
+            if char2_relaxed:
+                dd[q + 1] = int(g.integers(0, p))
+            q += 2
+        else:
+            dd[q] = int(g.integers(1, p))
+            q += 1
+    return perm, L, dd, de
+
+
+@pytest.mark.parametrize("p", [2, 3, 65521, 8388593])
+def test_reconstruct_matches_independent_product(p):
+    """orc_reconstruct (the checker of the standard-form tests) equals P L D L^T P^T
+    computed with Python integers, for random factors with a nontrivial P (an
+    inverted permutation convention gives a different matrix on these inputs)."""
+    g = inputs.rng(4242 + p)
+    for t in range(6):
+        n = int(g.integers(1, 24))
+        perm, L, dd, de = _random_factors(g, n, p, char2_relaxed=(p == 2))
+        ref = reconstruct_indep(p, perm, L, dd, de)
+        got = orc.reconstruct(p, perm, L, dd, de)
+        assert (got.astype(object) == ref).all()
+        inv = np.argsort(perm).astype(np.int32)
+        if n >= 3 and not (inv == perm).all():
+            bad = reconstruct_indep(p, inv, L, dd, de)
+            # the check separates the two conventions whenever they give different matrices
+            if not (bad == ref).all():
+                assert not (got.astype(object) == bad).all()
+
+
+@pytest.mark.parametrize("name", ["antidiagonal_2x2", "lemma1_char2", "hand_3x3"])
+def test_reconstruct_golden(name):
+    g = _gold()[name]
+    A = np.array(g["A"], dtype=np.uint32)
+    out = orc.reconstruct(g["p"], g["perm"], np.array(g["L"], dtype=np.uint32), g["dd"], g["de"])
+    assert (out == A).all()
+    if "standard_form" in g:
+        s = g["standard_form"]
+        out = orc.reconstruct(2, s["perm"], np.array(s["L"], dtype=np.uint32), s["dd"], s["de"])
+        assert (out == A).all()
+
+
+def test_reconstruct_of_search_on_generator_inputs():
+    for p in (2, 65521):
+        for seed in range(3):
+            if p == 2:
+                A, _, _ = inputs.char2_input(40, 8, 6, 90 + seed)
+            else:
+                A, _ = inputs.rank_profile_matrix_input(40, p, 12, 6, 90 + seed)
+            f = orc.search(A, p)
+            assert (orc.reconstruct(p, f["perm"], f["L"], f["dd"], f["de"]) == A).all()
