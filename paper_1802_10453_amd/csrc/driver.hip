@@ -61,6 +61,8 @@ struct Err : std::runtime_error {
     } while (0)
 
 static inline unsigned nblk(int64_t x, int b = 256) { return (unsigned)((x + b - 1) / b); }
+// mapped host words written by the PLDUQ slab launch: rank, abort flag
+constexpr int HW_SLAB = 256;
 
 // ---------------------------------------------------------------------------
 // Profiling: HIP events around each launch, harvested at host synchronisations.
@@ -198,6 +200,8 @@ struct Workspace {
     int64_t ipool_len = 0;             // ints of the stack part
     int32_t* ipool_scratch = nullptr;  // two halves: inverse map, reorder source
     int64_t ipool_scratch_len = 0;
+    PsShared* ps = nullptr;        // words shared by the workgroups of a PLDUQ slab launch
+    int32_t ps_gen = 0;            // generation of the last slab launch (flags compare equal to it)
     int32_t* hinfo = nullptr;      // pinned host words (rank, error flag, sigma, pivot columns)
     int32_t* hinfo_dev = nullptr;  // the same words as seen from the device: leaves write them directly
     void release() {
@@ -206,6 +210,7 @@ struct Workspace {
         if (kind) (void)hipFree(kind);
         int32_t* is[] = {orig, sig, tmpo, info, pidx, ipool};
         for (int32_t* p : is) if (p) (void)hipFree(p);
+        if (ps) (void)hipFree(ps);
         if (hinfo) (void)hipHostFree(hinfo);
         *this = Workspace();
     }
@@ -248,6 +253,12 @@ struct Workspace {
             throw Err(PLDL_ENOMEM, "alloc");
         }
         ipool_scratch = ipool + ipool_len;
+        if (hipMalloc((void**)&ps, sizeof(PsShared)) != hipSuccess || hipMemset(ps, 0, sizeof(PsShared)) != hipSuccess) {
+            (void)hipGetLastError();
+            release();
+            throw Err(PLDL_ENOMEM, "alloc");
+        }
+        ps_gen = 0;
         if (hipHostMalloc((void**)&hinfo, 1024 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
             hipHostGetDevicePointer((void**)&hinfo_dev, hinfo, 0) != hipSuccess) {
             (void)hipGetLastError();
@@ -296,7 +307,6 @@ struct Engine {
     int path = PLDL_PATH_F64;         // products on FP64 or INT8-split matrix cores
     I8Space* i8 = nullptr;
     double i8_min_flops = 0.0;        // smaller products stay on FP64 (split passes would dominate)
-    int slab_leaves = 2;              // leaves the last PLDUQ slab took (first batch of the next)
     Engine(Workspace& w, hipStream_t s, uint32_t p, int64_t n_, int t, Prof* pr)
         : st(s), F(make_field(p)), n(n_), ld(std::max<int64_t>(n_, 1)), t_leaf(t), ws(w), W(w.W), prof(pr) {}
 
@@ -686,41 +696,33 @@ struct Engine {
 
     // rows [a0, a1) and columns [c0, c1) of Y.  Row slabs of <= 64 rows; the
     // bottom half of a row split is updated with the top half's pivots (TRSM,
-    // GEMM) and continues on the columns the top half left.  hint (device
-    // ints, may be NULL; the minimum of nhint entries): a lower bound on the
-    // first column of these rows holding a nonzero, left by the preceding update.
-    int64_t plduq_t(int64_t a0, int64_t a1, int64_t c0, int64_t c1, const int32_t* hint = nullptr, int nhint = 0) {
+    // GEMM) and continues on the columns the top half left.
+    int64_t plduq_t(int64_t a0, int64_t a1, int64_t c0, int64_t c1) {
         const int64_t m = a1 - a0;
         if (m <= 0 || c1 <= c0) return 0;
         REQUIRE(a1 <= TC && c1 <= TR);
-        if (m <= 64) return plduq_slab(a0, a1, c0, c1, hint, nhint);
-        int32_t* nzh = ws.info + 8;
+        if (m <= 64) return plduq_slab(a0, a1, c0, c1);
         const int64_t ip_save = ip_top;
         const int64_t am = a0 + std::max<int64_t>(64, (m / 2) / 64 * 64);
         int32_t* snapC = snapshot(pC + c0, c1 - c0);
-        const int64_t r1 = plduq_t(a0, am, c0, c1, hint, nhint);
-        const int32_t* bhint = nullptr;
+        const int64_t r1 = plduq_t(a0, am, c0, c1);
         if (r1 > 0) {
             const int64_t mb = a1 - am, ncr = c1 - c0 - r1;
             // the bottom rows take the top half's column order
             tcolperm(c0, c1 - c0, reorder_src(snapC, pC + c0, c1 - c0), am, mb);
             // Wb^T = U_t^{-T} Y_b1^T  (U_t^T unit lower at T[c0.., a0..])
             trsm_ll(MatV{T + c0 * ldT + am, ldT, 1}, r1, mb, MatV{T + c0 * ldT + a0, ldT, 1});
-            // Y_b2^T -= V_t^T Wb^T, recording the first column left nonzero on the bottom rows
-            if (ncr > 0) {
-                HIPCHK(hipMemsetAsync(nzh, 0x7F, sizeof(int32_t), st));
+            // Y_b2^T -= V_t^T Wb^T
+            if (ncr > 0)
                 gemm_ld(T + (c0 + r1) * ldT + am, ldT, ncr, mb,
-                        GemmSeg{MatV{T + (c0 + r1) * ldT + a0, ldT, 1}, MatV{T + c0 * ldT + am, ldT, 1}, r1}, nzh,
-                        (int32_t)(c0 + r1));
-                bhint = nzh;
-            }
+                        GemmSeg{MatV{T + (c0 + r1) * ldT + a0, ldT, 1}, MatV{T + c0 * ldT + am, ldT, 1}, r1});
             // L_b^T = D_t^{-1} Wb^T
             LAUNCH(PLDL_CLASS_OTHER, k_scale_pack, dim3(nblk(mb), (unsigned)r1), dim3(256), 0, st, T + c0 * ldT + am, ldT, r1, mb,
                    T + c0 * ldT + a0, ldT, 1, itab, F);
         }
         int32_t* snapC2 = snapshot(pC + c0 + r1, c1 - c0 - r1);
         int32_t* snapR2 = snapshot(pR + am, a1 - am);
-        const int64_t r2 = plduq_t(am, a1, c0 + r1, c1, bhint, 1);
+        const int64_t r2 = plduq_t(am, a1, c0 + r1, c1);
         if (r2 > 0) {
             // the top rows take the bottom half's column order, the bottom rows' multipliers its row order
             tcolperm(c0 + r1, c1 - c0 - r1, reorder_src(snapC2, pC + c0 + r1, c1 - c0 - r1), a0, am - a0);
@@ -738,66 +740,26 @@ struct Engine {
         return r1 + r2;
     }
 
-    // A slab (<= 64 rows): leaves over 256-column chunks from left to right.  Each
-    // leaf eliminates the first chunk that is not zero on the slab's active rows
-    // (those without a pivot yet), moves its pivot rows to the front of them and
-    // writes its chunk in the new order; the update that follows carries that row
-    // order to the rest of the slab (the columns on the right, and the earlier
-    // pivot columns that hold multipliers) and eliminates the new pivots from the
-    // right part.  At the end the slab's pivot columns are moved to the front of
-    // [c0, c1), for the slab's rows.
-    int64_t plduq_slab(int64_t a0, int64_t a1, int64_t c0, int64_t c1, const int32_t* hint, int nhint) {
+    // A slab (<= 64 rows) in one launch (k_plduq_slab): chunks of PS_CHUNK
+    // columns, one workgroup each, pivots chunk by chunk from left to right and
+    // in row order inside a chunk; on return the slab's pivot rows and pivot
+    // columns come first (pivot order), pR / pC updated.  The host reads the
+    // slab's rank from mapped host words (one wait per slab).
+    int64_t plduq_slab(int64_t a0, int64_t a1, int64_t c0, int64_t c1) {
         const int64_t m = a1 - a0;
-        int32_t* nzb = ws.info + 1024;
-        int32_t* ss = ws.info + 256;   // slab state (device words SS_*)
-        // the update's grid covers every column it may visit (those right of the
-        // first leaf's chunk plus the slab's pivot columns); it is launched before
-        // the leaf's chunk is known, so it is sized for the whole range
-        const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((c1 - c0 + 64 + 3) / 4, NZB_MAX));
-        // Leaves and updates are queued in batches and the state is read once per
-        // batch: the kernels of a finished slab return at once.  The first batch is
-        // the previous slab's leaf count (neighbouring slabs see similar rank
-        // profiles), the next ones double.  Each leaf but the last takes at least
-        // one pivot and moves past at least one chunk, so at most
-        // min(m, chunks) + 1 leaves run: no batch goes beyond that.
-        const int64_t max_leaves = std::min<int64_t>(m, (c1 - c0 + PLDUQ_CHUNK - 1) / PLDUQ_CHUNK) + 1;
-        int32_t* hs = nullptr;
-        int batch = slab_leaves;
-        for (int64_t queued = 0;;) {
-            batch = (int)std::max<int64_t>(1, std::min<int64_t>(batch, max_leaves - queued));
-            for (int b = 0; b < batch; ++b) {
-                // the slab's first leaf starts a fresh state at c0
-                const int64_t cinit = (queued == 0 && b == 0) ? c0 : -1;
-                LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_leaf, dim3(1), dim3(PLDUQ_THREADS), 0, st, T, ldT, a0, (int)m, cinit,
-                       c1, F, itab, hint, nhint, nzb, ws.sig, ss, pR);
-                LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_rupdate, dim3((unsigned)nb), dim3(256), 0, st, T, ldT, a0, (int)m, c1,
-                       F, itab, nzb, ws.sig, ss, b == batch - 1 ? ws.hinfo_dev : nullptr);
-            }
-            queued += batch;
-            hs = read_host();   // the batch's last update wrote the state there
-            const int64_t Rc = hs[SS_R] + (hs[SS_PEND] ? hs[SS_RLAST] : 0);
-            const int64_t cc = hs[SS_PEND] ? hs[SS_CE] : hs[SS_CUR];
-            if (hs[SS_DONE] || Rc >= m || cc >= c1) break;
-            REQUIRE(queued < max_leaves);
-            batch = std::min(batch * 2, 32);
-        }
-        slab_leaves = std::max(1, std::min(hs[SS_ITER], 16));
-        // the slab's pivot columns in pivot order: committed ones, then the pending leaf's
-        PivList piv{};
-        for (int q = 0; q < hs[SS_PN]; ++q) piv.col[piv.n++] = hs[SS_PCOL + q];
-        if (hs[SS_PEND] && !hs[SS_DONE])
-            for (int q = 0; q < hs[SS_RLAST]; ++q) piv.col[piv.n++] = hs[SS_CCOL + q];
-        const int64_t R = piv.n;
-        REQUIRE(R <= m);
-        if (R > 0) {
-            PivList srt = piv;
-            std::sort(srt.col, srt.col + srt.n);
-            const int64_t len = c1 - c0;
-            int32_t* src = ws.ipool_scratch + ws.ipool_scratch_len / 2;
-            LAUNCH(PLDL_CLASS_OTHER, k_slab_colsrc, dim3(nblk(len)), dim3(256), 0, st, piv, srt, c0, len, src);
-            tcolperm(c0, len, src, a0, m);
-            idx_reorder(pC, c0, len, src);
-        }
+        const int64_t nch = (c1 - c0 + PS_CHUNK - 1) / PS_CHUNK;
+        REQUIRE(m >= 1 && m <= 64 && nch >= 1 && nch <= PS_MAXCH);
+        PsArgs g{};
+        g.T = T; g.ld = ldT; g.a0 = a0; g.m = (int)m; g.nch = (int)nch; g.c0 = c0; g.c1 = c1;
+        g.F = F; g.itab = itab; g.pR = pR; g.pC = pC; g.sh = ws.ps;
+        g.gen = ++ws.ps_gen;
+        g.hout = ws.hinfo_dev + HW_SLAB;   // (the base case uses words 0 .. 128)
+        ws.hinfo[HW_SLAB + 1] = 0;
+        LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_slab, dim3((unsigned)nch), dim3(PS_THREADS), 0, st, g);
+        const int32_t* h = read_host();
+        if (h[HW_SLAB + 1]) throw Err(PLDL_EINTERNAL, "PLDUQ slab: a chunk waited too long for its predecessor (launch aborted)");
+        const int64_t R = h[HW_SLAB];
+        REQUIRE(R >= 0 && R <= m);
         return R;
     }
 

@@ -23,6 +23,43 @@ constexpr int NZB_MAX = 2048;
 constexpr int SS_R = 0, SS_CUR = 1, SS_DONE = 2, SS_PEND = 3, SS_RLAST = 4, SS_CE = 5, SS_NH = 6, SS_PN = 7,
               SS_ITER = 8, SS_PCOL = 16, SS_CCOL = 80, SS_WORDS = 144;
 
+// PLDUQ slab in one launch (plduq.hip): chunk of PS_CHUNK columns per
+// workgroup of PS_THREADS threads (lane = slab row, each wave PS_CPW columns),
+// at most PS_MAXCH chunks; a wait gives up after PS_SPIN polls.
+constexpr int PS_CPW = 16, PS_THREADS = 1024, PS_CHUNK = PS_CPW * (PS_THREADS / 64), PS_MAXCH = 256;
+constexpr int PS_SPIN = 1 << 20;
+// Device words one slab launch shares between its workgroups.  flag[b] equals
+// the launch's generation once chunk b has published base[b] (slab pivots of
+// the chunks before it), cnt[b] and its pivot records: slab row, column (T row),
+// scaled pivot value and scaled pivot column (64 entries, 0 for rows it does
+// not eliminate).  abort_gen equals the generation of an aborted launch.
+struct PsShared {
+    int32_t flag[PS_MAXCH];
+    int32_t base[PS_MAXCH];
+    int32_t cnt[PS_MAXCH];
+    int32_t abort_gen;
+    int32_t prow[64];
+    int32_t pcol[64];
+    double px[64];
+    double pf[64 * 64];
+};
+struct PsArgs {
+    double* T;
+    int64_t ld;
+    int64_t a0;           // first slab row (T column)
+    int m;                // slab rows, 1 .. 64
+    int nch;              // chunks: ceil((c1 - c0) / PS_CHUNK) <= PS_MAXCH
+    int64_t c0, c1;       // slab columns (T rows)
+    Field F;
+    const uint32_t* itab;
+    int32_t* pR;          // original index of each slab row position (T column), updated
+    int32_t* pC;          // original index of each column position (T row), updated
+    PsShared* sh;
+    int32_t gen;          // this launch's generation (> every earlier one on sh)
+    int32_t* hout;        // mapped host words: [0] = slab rank, [1] = 1 if the launch aborted
+};
+__global__ void k_plduq_slab(PsArgs g);
+
 // Pivot columns of a PLDUQ slab (T row indices); a slab has at most 64 pivots.
 struct PivList {
     int32_t col[64];

@@ -1,0 +1,281 @@
+// plduq.hip -- the leaf of the rank-profile-revealing PLDUQ (Sections 4.2 and 5
+// pivoting): one row slab of Y (at most 64 rows, any width) in one launch.
+//
+// Y is held as its compact transpose T (Y[i][j] = T[j][i], leading dimension
+// ld), so Y column j is T row j and the slab's rows a0 .. a0+m-1 are m
+// contiguous doubles of every T row.
+//
+// Pivoting.  Columns are cut into chunks of PS_CHUNK; chunk b belongs to
+// workgroup b.  The pivots are taken chunk by chunk from left to right, and
+// inside a chunk in increasing row order: a row's pivot is the first nonzero of
+// its reduced row among the chunk's columns that are not yet pivot columns.
+// A pivot eliminates the rows that have no pivot yet; rows with a pivot keep
+// their values (their U part).  This is a lexicographic search: a row takes
+// a pivot in chunk b only when it is zero on every earlier chunk, so
+// elimination by pivots of later chunks never changes what an earlier chunk
+// saw, and the pivot set is the rank profile matrix of the slab.
+//
+// Elimination is fraction free: pivot (i, c) with value x turns an active row t
+// into x y_t - y_t[c] y_i.  Every active row is then scaled by the same factor
+// (the product S_s of the pivots taken before pivot s), which changes no zero
+// pattern, and no inverse is needed while searching.  At the end, with
+// x_s the scaled pivot values: multiplier of row t for pivot s = y_t[c_s] / x_s,
+// U entry of pivot row s = y / x_s, D_s = x_s / S_s.
+//
+// Chain.  Workgroup b loads its chunk into registers (lane = slab row, each
+// wave PS_CPW columns), applies the pivots of chunks 0 .. b-1 in order as they
+// are published (no barrier: wave shuffles only), searches its own chunk (two
+// workgroup barriers per pivot), then publishes its pivots (slab row, column,
+// x, and the scaled pivot column of multipliers) and raises its flag.  Once
+// the last chunk has published, every workgroup writes its chunk to its final
+// place: pivot rows first in pivot order, then the other rows in their previous
+// order; pivot columns first (T rows c0 .. c0+R) in pivot order, then the other
+// columns in increasing order.  Every workgroup has read its chunk before it
+// publishes, so no write lands on data still to be read.  pR / pC (original
+// row / column indices) follow the same orders.
+//
+// The chain needs every workgroup of the grid resident at once (at most
+// PS_MAXCH workgroups, one per compute unit suffices).  Each wait is bounded:
+// after PS_SPIN polls a wave marks the launch aborted, every waiting wave
+// leaves, and the host reports the error instead of hanging.
+#include "kernels.h"
+
+namespace pldl {
+
+namespace {
+
+__device__ __forceinline__ double rdlane(double v, int l) {
+    const long long w = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(w & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(w >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Waits for *flag == gen.  false: the launch was aborted (or this wait timed
+// out and aborted it).  Relaxed polls; one acquire fence once the flag is seen.
+__device__ bool ps_wait(const int32_t* flag, int32_t gen, int32_t* abort_word, int32_t* herr) {
+    for (int it = 0;; ++it) {
+        const int32_t v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v == gen) {
+            __atomic_thread_fence(__ATOMIC_ACQUIRE);
+            return true;
+        }
+        if ((it & 31) == 31 &&
+            __hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen)
+            return false;
+        if (it >= PS_SPIN) {
+            __hip_atomic_store(abort_word, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (herr) __hip_atomic_store(herr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(PS_THREADS) void k_plduq_slab(PsArgs g) {
+    constexpr int CPW = PS_CPW, NW = PS_THREADS / 64;
+    static_assert(NW * CPW == PS_CHUNK && CPW <= 32, "chunk geometry");
+    __shared__ unsigned long long wmask[NW];
+    __shared__ int wfirst[NW][64];
+    __shared__ double pf_l[64];
+    __shared__ double px_l;
+    __shared__ int colpiv[PS_CHUNK];     // chunk column -> slab pivot index (-1: none)
+    __shared__ int rowpiv[64];           // slab row -> slab pivot index (-1: none)
+    __shared__ double xinv_l[64], dval_l[64];
+    __shared__ int newpos[64];
+    __shared__ unsigned long long cmask[PS_CHUNK / 64];
+    __shared__ int okw;
+
+    const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const Field F = g.F;
+    PsShared* sh = g.sh;
+    const int m = g.m;
+    const int64_t cb = g.c0 + (int64_t)b * PS_CHUNK;           // first T row of the chunk
+    const int64_t wc = cb + (int64_t)wave * CPW;               // first T row of this wave
+    const int nw = (int)max((int64_t)0, min((int64_t)CPW, g.c1 - wc));
+    const int lr = min(lane, max(m - 1, 0));
+
+    // ---- the chunk into registers (row = lane), the old index vectors
+    double y[CPW];
+    if (nw > 0) {
+        const double* src = g.T + wc * g.ld + g.a0 + lr;
+#pragma unroll
+        for (int k = 0; k < CPW; ++k) {
+            const double v = src[(int64_t)min(k, nw - 1) * g.ld];
+            y[k] = (k < nw && lane < m) ? fcen(v, F) : 0.0;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < CPW; ++k) y[k] = 0.0;
+    }
+    const int pc_old = (lane < nw) ? g.pC[wc + lane] : 0;
+    const int pr_old = (b == 0 && lane < m) ? g.pR[g.a0 + lane] : 0;
+    for (int e = tid; e < PS_CHUNK; e += PS_THREADS) colpiv[e] = -1;
+    bool active = lane < m;
+    uint32_t live = nw >= 32 ? 0xffffffffu : ((1u << nw) - 1u);
+
+    // eliminate the active rows other than i with pivot (i, x) and scaled column f (this lane's row)
+    auto apply = [&](int i, double x, double f) {
+        const bool upd = active && lane != i;
+#pragma unroll
+        for (int k = 0; k < CPW; ++k) {
+            if ((live >> k) & 1u) {
+                const double u = rdlane(y[k], i);
+                const double t = fredc(fma(x, y[k], -f * u), F);
+                y[k] = upd ? t : y[k];
+            }
+        }
+        if (lane == i) active = false;
+    };
+
+    // ---- pivots of the chunks to the left, in order, as they are published
+    bool ok = true;
+    int base = 0;
+    for (int bp = 0; bp < b && ok; ++bp) {
+        ok = ps_wait(&sh->flag[bp], g.gen, &sh->abort_gen, g.hout + 1);
+        if (!ok) break;
+        const int bb = __builtin_amdgcn_readfirstlane(sh->base[bp]);
+        const int bc = __builtin_amdgcn_readfirstlane(sh->cnt[bp]);
+        for (int s = bb; s < bb + bc; ++s) {
+            const int i = __builtin_amdgcn_readfirstlane(sh->prow[s]);
+            apply(i, sh->px[s], sh->pf[s * 64 + lane]);
+        }
+        base = bb + bc;
+    }
+    if (__syncthreads_or(!ok)) return;
+
+    // ---- own search: the first active row with a nonzero on a live column, its first such column
+    int r = 0;
+    for (;;) {
+        uint32_t nzb = 0;
+#pragma unroll
+        for (int k = 0; k < CPW; ++k) nzb |= (((live >> k) & 1u) && y[k] != 0.0) ? (1u << k) : 0u;
+        if (!active) nzb = 0;
+        const unsigned long long bal = __ballot(nzb != 0);
+        if (lane == 0) wmask[wave] = bal;
+        wfirst[wave][lane] = nzb ? wave * CPW + __ffs(nzb) - 1 : 0x7fffffff;
+        __syncthreads();
+        unsigned long long M = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) M |= wmask[w];
+        if (M == 0) break;
+        const int i = __ffsll((long long)M) - 1;
+        int c = 0x7fffffff;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) c = min(c, wfirst[w][i]);
+        const int wo = c / CPW, ko = c - wo * CPW;
+        const int s = base + r;
+        if (wave == wo) {
+            double v = 0.0;
+#pragma unroll
+            for (int k = 0; k < CPW; ++k) v = (k == ko) ? y[k] : v;
+            const double x = rdlane(v, i);
+            const double f = (active && lane != i) ? v : 0.0;
+            pf_l[lane] = f;
+            sh->pf[s * 64 + lane] = f;
+            if (lane == 0) {
+                px_l = x;
+                sh->px[s] = x;
+                sh->prow[s] = i;
+                sh->pcol[s] = (int32_t)(cb + c);
+                colpiv[c] = s;
+            }
+            live &= ~(1u << ko);   // the column keeps D (row i), multipliers (active rows), U (pivot rows)
+        }
+        __syncthreads();
+        apply(i, px_l, pf_l[lane]);
+        ++r;
+    }
+
+    // ---- publish: records first, then the flag
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        sh->base[b] = base;
+        sh->cnt[b] = r;
+        __threadfence();
+        __hip_atomic_store(&sh->flag[b], g.gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+
+    // ---- every chunk published: final values, final places
+    if (tid < 64) {
+        ok = ps_wait(&sh->flag[g.nch - 1], g.gen, &sh->abort_gen, g.hout + 1);
+        if (tid == 0) okw = ok;
+    }
+    __syncthreads();
+    if (!okw) return;
+    const int R = __builtin_amdgcn_readfirstlane(sh->base[g.nch - 1] + sh->cnt[g.nch - 1]);
+    if (wave == 0) {
+        // 1/x_s, the exclusive prefix products of 1/x (1/S_s) and D_s = x_s / S_s
+        rowpiv[lane] = -1;
+        const double x = lane < R ? fcan(sh->px[lane], F) : 1.0;
+        const double xi = lane < R ? (g.itab ? (double)g.itab[(int)x] : finv(x, F)) : 1.0;
+        double pre = xi;   // inclusive scan of the inverses
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double o = __shfl_up(pre, off);
+            if (lane >= off) pre = fmulm(pre, o, F);
+        }
+        double sinv = __shfl_up(pre, 1);
+        if (lane == 0) sinv = 1.0;
+        xinv_l[lane] = xi;
+        dval_l[lane] = fmulm(x, sinv, F);
+    }
+    // this chunk's pivot columns as a bit mask (PS_CHUNK bits)
+    if (tid < PS_CHUNK) {
+        const unsigned long long cm = __ballot(colpiv[tid] >= 0);
+        if (lane == 0) cmask[tid >> 6] = cm;
+    }
+    __syncthreads();
+    if (wave == 0 && lane < R) rowpiv[sh->prow[lane]] = lane;
+    __syncthreads();
+    if (wave == 0) {
+        const bool isp = lane < m && rowpiv[lane] >= 0;
+        const unsigned long long pm = __ballot(isp);
+        const int before = lane - __popcll(pm & ((1ull << lane) - 1ull));   // non-pivot rows before this one
+        newpos[lane] = isp ? rowpiv[lane] : R + before;
+        if (b == 0 && lane < m) g.pR[g.a0 + newpos[lane]] = pr_old;
+    }
+    __syncthreads();
+    if (nw > 0) {
+        const int rp = lane < m ? rowpiv[lane] : -1;
+        const double xr = rp >= 0 ? xinv_l[rp] : 0.0;   // U scale of this row
+        const int np = newpos[lr];
+        // pivot columns of this chunk before the wave's first column
+        const int c00 = wave * CPW;
+        int pbefore = 0;
+#pragma unroll
+        for (int q = 0; q < PS_CHUNK / 64; ++q) {
+            const int lo = q * 64;
+            if (lo + 64 <= c00) pbefore += __popcll(cmask[q]);
+            else if (lo < c00) pbefore += __popcll(cmask[q] & ((1ull << (c00 - lo)) - 1ull));
+        }
+#pragma unroll
+        for (int k = 0; k < CPW; ++k) {
+            if (k < nw) {
+                const int c = wave * CPW + k;
+                const int s = colpiv[c];
+                int64_t dest;
+                double v;
+                if (s >= 0) {
+                    dest = g.c0 + s;
+                    if (rp == s) v = dval_l[s];
+                    else if (rp >= 0 && rp < s) v = fmulm(y[k], xr, F);
+                    else v = fmulm(y[k], xinv_l[s], F);
+                } else {
+                    dest = g.c0 + R + (cb - g.c0 + c) - base - pbefore;
+                    v = rp >= 0 ? fmulm(y[k], xr, F) : 0.0;
+                }
+                if (lane < m) g.T[dest * g.ld + g.a0 + np] = v;
+                const int pco = __shfl(pc_old, k);
+                if (lane == 0) g.pC[dest] = pco;
+                pbefore += s >= 0;
+            }
+        }
+    }
+    if (b == g.nch - 1 && tid == 0) g.hout[0] = R;
+}
+
+}  // namespace pldl
