@@ -63,6 +63,8 @@ struct Err : std::runtime_error {
 static inline unsigned nblk(int64_t x, int b = 256) { return (unsigned)((x + b - 1) / b); }
 // mapped host words written by the PLDUQ slab launch: rank, abort flag
 constexpr int HW_SLAB = 256;
+// "no column left of the range is read later" (see Engine::recall)
+constexpr int64_t AL_NONE = INT64_MAX;
 
 // ---------------------------------------------------------------------------
 // Profiling: HIP events around each launch, harvested at host synchronisations.
@@ -200,6 +202,9 @@ struct Workspace {
     int64_t ipool_len = 0;             // ints of the stack part
     int32_t* ipool_scratch = nullptr;  // two halves: inverse map, reorder source
     int64_t ipool_scratch_len = 0;
+    int32_t* colblk = nullptr;     // per column: block id once it stops moving with its rows, else -1
+    int32_t* dinv = nullptr;       // per block: position of each original index when it stopped (n each)
+    int64_t dinv_blocks = 0;       // capacity of dinv in blocks
     PsShared* ps = nullptr;        // words shared by the workgroups of a PLDUQ slab launch
     int32_t ps_gen = 0;            // generation of the last slab launch (flags compare equal to it)
     int32_t* hinfo = nullptr;      // pinned host words (rank, error flag, sigma, pivot columns)
@@ -208,7 +213,7 @@ struct Workspace {
         double* ds[] = {W, tmp1, tmp2, dd, de, xinv, yy, dvec, tinv};
         for (double* p : ds) if (p) (void)hipFree(p);
         if (kind) (void)hipFree(kind);
-        int32_t* is[] = {orig, sig, tmpo, info, pidx, ipool};
+        int32_t* is[] = {orig, sig, tmpo, info, pidx, ipool, colblk, dinv};
         for (int32_t* p : is) if (p) (void)hipFree(p);
         if (ps) (void)hipFree(ps);
         if (hinfo) (void)hipHostFree(hinfo);
@@ -237,13 +242,13 @@ struct Workspace {
         dalloc(&tinv, 64 * (size_t)(m + 64));
         tinv_rows = m + 64;
         if (hipMalloc((void**)&kind, m + 1) != hipSuccess) { release(); throw Err(PLDL_ENOMEM, "alloc"); }
-        int32_t** ips[] = {&orig, &sig, &tmpo, &pidx};
+        int32_t** ips[] = {&orig, &sig, &tmpo, &pidx, &colblk};
         for (int32_t** p : ips)
             if (hipMalloc((void**)p, (2 * m + 1024) * sizeof(int32_t)) != hipSuccess) {
                 release();
                 throw Err(PLDL_ENOMEM, "alloc");
             }
-        if (hipMalloc((void**)&info, (1024 + NZB_MAX) * sizeof(int32_t)) != hipSuccess) { release(); throw Err(PLDL_ENOMEM, "alloc"); }
+        if (hipMalloc((void**)&info, 1024 * sizeof(int32_t)) != hipSuccess) { release(); throw Err(PLDL_ENOMEM, "alloc"); }
         // snapshot stack: 3 segments of at most m entries per row-split level (<= 11 levels
         // for m <= 65535), then the scratch (inverse map and source, m + 64 each)
         ipool_len = 40 * (m + 64);
@@ -253,6 +258,12 @@ struct Workspace {
             throw Err(PLDL_ENOMEM, "alloc");
         }
         ipool_scratch = ipool + ipool_len;
+        dinv_blocks = 2 * ((m + 63) / 64) + 16;
+        if (hipMalloc((void**)&dinv, (size_t)dinv_blocks * (size_t)m * sizeof(int32_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            release();
+            throw Err(PLDL_ENOMEM, "alloc");
+        }
         if (hipMalloc((void**)&ps, sizeof(PsShared)) != hipSuccess || hipMemset(ps, 0, sizeof(PsShared)) != hipSuccess) {
             (void)hipGetLastError();
             release();
@@ -390,29 +401,62 @@ struct Engine {
         prof->n_f64++;
     }
 
+    // Columns left of every range still to be permuted that no later step reads
+    // before the output stop moving with their rows (see `al` below): columns
+    // [dead_upto, upto) are marked now, with where each original index sits,
+    // and the output reads them from there.
+    int64_t dead_upto = 0;
+    int32_t dead_blocks = 0;
+    bool track_dead = false;   // pldl_factor only: its output step gathers the stopped columns
+    void stop_columns(int64_t upto) {
+        if (!track_dead || upto <= dead_upto) return;
+        REQUIRE(dead_blocks < ws.dinv_blocks);
+        LAUNCH(PLDL_CLASS_PERM, k_dead_snapshot, dim3(nblk(n)), dim3(256), 0, st, ws.orig, dead_upto, upto, n,
+               dead_blocks, ws.colblk, ws.dinv + (int64_t)dead_blocks * n);
+        ++dead_blocks;
+        dead_upto = upto;
+    }
     // Symmetric permutation of [lo, hi): new lo+q <- old lo+sig[q].
-    // parts: 1 = rows x [0,lo), 2 = block, 4 = rows below x range, 8 = orig.
-    void perm_sym(int64_t lo, int64_t hi, const int32_t* sig, int parts) {
+    // parts: 1 = rows x [al, lo), 2 = block, 4 = rows below x range, 8 = orig.
+    // al: the first column left of the range that a later step still reads
+    // (AL_NONE: none of them; every column left of min(al, lo) stops moving).
+    void perm_sym(int64_t lo, int64_t hi, const int32_t* sig, int parts, int64_t al) {
         const int64_t s = hi - lo;
         if (s <= 1) return;
         REQUIRE(lo >= 0 && hi <= n && sig);
+        REQUIRE(lo >= dead_upto);   // no stopped column lies in a range that still moves
+        const int64_t c0 = (parts & 1) ? (track_dead ? std::min(std::max<int64_t>(al, 0), lo) : 0) : lo;
+        if (parts & 1) stop_columns(c0);
+        // rows below in one pass through LDS when a row segment fits
+        const bool below1 = (parts & 4) && n > hi && s <= PERM_BELOW_LDS;
         PermGeom g{};
-        g.n = n; g.lo = lo; g.hi = hi; g.s = s; g.parts = parts;
-        g.nb0 = nblk(std::max<int64_t>(lo, 1));
-        g.nb1 = nblk(s);
-        g.B0 = ((parts & 1) && lo > 0) ? s * g.nb0 : 0;
+        g.n = n; g.lo = lo; g.hi = hi; g.s = s; g.c0 = c0; g.parts = parts;
+        g.nb0 = nblk(std::max<int64_t>(lo - c0, 1), 256 * PERM_EPT);
+        g.nb1 = nblk(s, 256 * PERM_EPT);
+        g.B0 = ((parts & 1) && lo > c0) ? s * g.nb0 : 0;
         g.B1 = (parts & 2) ? s * g.nb1 : 0;
-        g.B2 = ((parts & 4) && n > hi) ? (n - hi) * g.nb1 : 0;
+        g.B2 = ((parts & 4) && n > hi && !below1) ? (n - hi) * g.nb1 : 0;
         g.B3 = (parts & 8) ? g.nb1 : 0;
         const int64_t blocks = g.B0 + g.B1 + g.B2 + g.B3;
-        if (blocks == 0) return;
         REQUIRE(blocks < ((int64_t)1 << 31));
-        double elems = (double)(g.B0 ? s * lo : 0) + (double)(g.B1 ? s * (s + 1) / 2 : 0) + (double)(g.B2 ? s * (n - hi) : 0);
+        double elems = (double)(g.B0 ? s * (lo - c0) : 0) + (double)(g.B1 ? s * (s + 1) / 2 : 0) +
+                       (double)(((parts & 4) && n > hi) ? s * (n - hi) : 0);
+        if (elems == 0.0 && blocks == 0) return;
         prof->begin(st, PLDL_CLASS_PERM, 0.0, 16.0 * elems);
-        hipLaunchKernelGGL(k_perm_sym, dim3((unsigned)blocks), dim3(256), 0, st, W, ld, g, sig, ws.tmp1, ws.orig, ws.tmpo, 0);
-        hipLaunchKernelGGL(k_perm_sym, dim3((unsigned)blocks), dim3(256), 0, st, W, ld, g, sig, ws.tmp1, ws.orig, ws.tmpo, 1);
+        if (blocks > 0) {
+            hipLaunchKernelGGL(k_perm_sym, dim3((unsigned)blocks), dim3(256), 0, st, W, ld, g, sig, ws.tmp1, ws.orig, ws.tmpo, 0);
+            hipLaunchKernelGGL(k_perm_sym, dim3((unsigned)blocks), dim3(256), 0, st, W, ld, g, sig, ws.tmp1, ws.orig, ws.tmpo, 1);
+            prof->n_launch += 2;
+        }
+        if (below1) {
+            const int rpw = (int)std::max<int64_t>(1, PERM_BELOW_ROWS_LDS / s);
+            const int64_t nwg = (n - hi + rpw - 1) / rpw;
+            REQUIRE(nwg < ((int64_t)1 << 31));
+            hipLaunchKernelGGL(k_perm_below, dim3((unsigned)nwg), dim3(256), (size_t)rpw * s * sizeof(double), st, W, ld,
+                               lo, s, hi, n, sig, rpw);
+            prof->n_launch += 1;
+        }
         prof->end(st);
-        prof->n_launch += 2;
     }
 
     // ---- TRSM (Section 3) ---------------------------------------------------
@@ -500,7 +544,7 @@ struct Engine {
     }
 
     // ---- base case (Section 5) ------------------------------------------------
-    int64_t bc(int64_t lo, int64_t hi) {
+    int64_t bc(int64_t lo, int64_t hi, int64_t al) {
         int s = (int)(hi - lo);
         REQUIRE(s >= 1 && s <= 128);
         LAUNCH(PLDL_CLASS_BASE_CASE, k_bc_leaf, dim3(1), dim3(BC_THREADS), 0, st, W, ld, lo, s, F, itab, ws.dd, ws.de, ws.sig,
@@ -509,18 +553,23 @@ struct Engine {
         int64_t r = h[0];
         bool ident = true;
         for (int q = 0; q < s; ++q) ident &= (h[1 + q] == q);
-        if (!ident) perm_sym(lo, hi, ws.sig, 1 | 4 | 8);
+        if (!ident) perm_sym(lo, hi, ws.sig, 1 | 4 | 8, al);
         return r;
     }
 
     // ---- Algorithm 2 -----------------------------------------------------------
-    int64_t recall(int64_t lo, int64_t hi) {
+    // al: the first column left of lo that a later step still reads: the start
+    // of the highest enclosing range whose first half contains this one (its
+    // TRSM and GEMM read that half's L block once the half is done); AL_NONE
+    // when there is none.  The first half of this range inherits min(al, lo);
+    // the second part inherits al (this range reads nothing after it).
+    int64_t recall(int64_t lo, int64_t hi, int64_t al) {
         int64_t N = hi - lo;
         if (N <= 0) return 0;
-        if (N <= t_leaf) return bc(lo, hi);
+        if (N <= t_leaf) return bc(lo, hi, al);
         int64_t m = N / 2;
         if (m >= 128) m = m / 64 * 64;
-        int64_t r1 = recall(lo, lo + m);
+        int64_t r1 = recall(lo, lo + m, std::min(al, lo));
         int64_t s = lo + m, n2 = hi - s;
         if (r1 > 0 && n2 > 0) {
             chk(s, lo, n2, m);
@@ -535,13 +584,13 @@ struct Engine {
             // SYRDK: Z = C - G D1 G^T = lower(C - G X)
             gemm(W + s * ld + s, n2, n2, GemmSeg{vrow(s, lo), MatV{ws.tmp2, 1, r1}, r1}, GemmSeg{MatV{nullptr, 0, 1}, MatV{nullptr, 0, 1}, 0}, true);
         }
-        return r1 + zlp(lo + r1, m - r1, hi);
+        return r1 + zlp(lo + r1, m - r1, hi, al);
     }
 
     // ---- Algorithm 3 -----------------------------------------------------------
-    int64_t zlp(int64_t lo, int64_t mz, int64_t hi) {
+    int64_t zlp(int64_t lo, int64_t mz, int64_t hi, int64_t al) {
         int64_t s0 = lo + mz, nc = hi - s0;
-        if (mz == 0) return recall(lo, hi);
+        if (mz == 0) return recall(lo, hi, al);
         if (nc == 0) return 0;
         // PLDUQ of Y on a compact copy of Y^T; then C' = Q C Q^T and the pack back into W
         REQUIRE(nc <= 65535 && mz <= 65535);
@@ -551,7 +600,7 @@ struct Engine {
         LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(nc)), dim3(256), 0, st, pC, nc);
         int64_t rY = plduq_t(0, mz, 0, nc);
         if (rY > 0) {
-            perm_sym(s0, hi, pC, 2);
+            perm_sym(s0, hi, pC, 2, al);
             LAUNCH(PLDL_CLASS_OTHER, k_copy2d, dim3(nblk(mz), (unsigned)nc), dim3(256), 0, st, W + s0 * ld + lo, ld, T, mz, nc, mz);
         }
         int64_t nz = nc - rY, nr = mz - rY, N = hi - lo;
@@ -609,15 +658,15 @@ struct Engine {
             LAUNCH(PLDL_CLASS_OTHER, k_zlp_sigma_total, dim3(nblk(N)), dim3(256), 0, st, ws.sig, mz, nc, rY, pR, pC);
         else
             LAUNCH(PLDL_CLASS_OTHER, k_zlp_sigma, dim3(nblk(N)), dim3(256), 0, st, ws.sig, mz, nc, rY);
-        perm_sym(lo, hi, ws.sig, 1 | 4 | 8);
+        perm_sym(lo, hi, ws.sig, 1 | 4 | 8, al);
         if (rY > 0)
             LAUNCH(PLDL_CLASS_OTHER, k_zlp_orig_d, dim3(nblk(N)), dim3(256), 0, st, ws.orig, ws.tmpo, lo, mz, hi, rY, W, ld, delta, ws.dd, ws.de, 2);
-        int64_t rz = recall(lo + 2 * rY, lo + 2 * rY + nz);
+        int64_t rz = recall(lo + 2 * rY, lo + 2 * rY + nz, al);
         // non-pivots of Z and of the zero block, merged by original index
         int64_t a = lo + 2 * rY + rz, n1 = nz - rz;
         if (n1 > 0 && nr > 0) {
             LAUNCH(PLDL_CLASS_OTHER, k_sigma_merge, dim3(nblk(n1 + nr)), dim3(256), 0, st, ws.orig, a, n1, nr, ws.sig);
-            perm_sym(a, hi, ws.sig, 1 | 4 | 8);
+            perm_sym(a, hi, ws.sig, 1 | 4 | 8, al);
         }
         return 2 * rY + rz;
     }
@@ -951,19 +1000,29 @@ int pldl_factor(pldl_ctx* ctx, uint32_t p, int64_t n, void* A, int64_t lda, int3
         LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(n)), dim3(256), 0, st, ws.orig, n);
         HIPCHK(hipMemsetAsync(ws.dd, 0, sizeof(double) * n, st));
         HIPCHK(hipMemsetAsync(ws.de, 0, sizeof(double) * n, st));
-        prof->n_launch += 2;
-        int64_t r = E.recall(0, n);
+        HIPCHK(hipMemsetAsync(ws.colblk, 0xFF, sizeof(int32_t) * n, st));
+        prof->n_launch += 3;
+        E.track_dead = true;
+        int64_t r = E.recall(0, n, AL_NONE);
+        const bool gathered = E.dead_blocks > 0;
         LAUNCH(PLDL_CLASS_OTHER, k_rpm, dim3(nblk(n)), dim3(256), 0, st, ws.orig, ws.de, n, r, rpm);
         if (o.standard_form && p == 2) {
             dim3 g2(nblk(n), (unsigned)n);
+            if (gathered) {   // the transform works on W in the final row order
+                LAUNCH(PLDL_CLASS_PERM, k_dead_gather, g2, dim3(256), 0, st, ws.W, E.ld, n, ws.orig, ws.colblk, ws.dinv, ws.tmp1);
+                LAUNCH(PLDL_CLASS_PERM, k_copy2d, g2, dim3(256), 0, st, ws.W, E.ld, ws.tmp1, E.ld, n, n);
+                E.dead_blocks = 0;
+            }
             LAUNCH(PLDL_CLASS_OTHER, k_char2_std, g2, dim3(256), 0, st, ws.W, E.ld, n, ws.dd, ws.de, ws.orig, ws.tmp1, 0);
             LAUNCH(PLDL_CLASS_OTHER, k_char2_std, g2, dim3(256), 0, st, ws.W, E.ld, n, ws.dd, ws.de, ws.orig, ws.tmp1, 1);
             LAUNCH(PLDL_CLASS_OTHER, k_char2_std, dim3(nblk(n)), dim3(256), 0, st, ws.W, E.ld, n, ws.dd, ws.de, ws.orig, ws.tmp1, 2);
         }
         if (dtype == PLDL_U32)
-            LAUNCH(PLDL_CLASS_OTHER, k_store_output<uint32_t>, g, dim3(256), 0, st, (uint32_t*)A, lda, ws.W, E.ld, n, ws.dd, ws.de, (uint32_t*)e, ws.orig, perm);
+            LAUNCH(PLDL_CLASS_OTHER, k_store_output<uint32_t>, g, dim3(256), 0, st, (uint32_t*)A, lda, ws.W, E.ld, n, ws.dd, ws.de, (uint32_t*)e, ws.orig, perm,
+                   E.dead_blocks > 0 ? ws.colblk : nullptr, ws.dinv);
         else
-            LAUNCH(PLDL_CLASS_OTHER, k_store_output<double>, g, dim3(256), 0, st, (double*)A, lda, ws.W, E.ld, n, ws.dd, ws.de, (double*)e, ws.orig, perm);
+            LAUNCH(PLDL_CLASS_OTHER, k_store_output<double>, g, dim3(256), 0, st, (double*)A, lda, ws.W, E.ld, n, ws.dd, ws.de, (double*)e, ws.orig, perm,
+                   E.dead_blocks > 0 ? ws.colblk : nullptr, ws.dinv);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
         prof->n_wait++;
@@ -1210,9 +1269,11 @@ int pldl_char2_to_standard(pldl_ctx* ctx, int64_t n, void* A, int64_t lda, int32
         LAUNCH(PLDL_CLASS_OTHER, k_char2_std, g, dim3(256), 0, st, ws.W, ld, n, ws.dd, ws.de, ws.orig, ws.tmp1, 1);
         LAUNCH(PLDL_CLASS_OTHER, k_char2_std, dim3(nblk(n)), dim3(256), 0, st, ws.W, ld, n, ws.dd, ws.de, ws.orig, ws.tmp1, 2);
         if (dtype == PLDL_U32)
-            LAUNCH(PLDL_CLASS_OTHER, k_store_output<uint32_t>, g, dim3(256), 0, st, (uint32_t*)A, lda, ws.W, ld, n, ws.dd, ws.de, (uint32_t*)e, ws.orig, perm);
+            LAUNCH(PLDL_CLASS_OTHER, k_store_output<uint32_t>, g, dim3(256), 0, st, (uint32_t*)A, lda, ws.W, ld, n, ws.dd, ws.de, (uint32_t*)e, ws.orig, perm,
+                   nullptr, nullptr);
         else
-            LAUNCH(PLDL_CLASS_OTHER, k_store_output<double>, g, dim3(256), 0, st, (double*)A, lda, ws.W, ld, n, ws.dd, ws.de, (double*)e, ws.orig, perm);
+            LAUNCH(PLDL_CLASS_OTHER, k_store_output<double>, g, dim3(256), 0, st, (double*)A, lda, ws.W, ld, n, ws.dd, ws.de, (double*)e, ws.orig, perm,
+                   nullptr, nullptr);
         HIPCHK(hipGetLastError());
         int32_t bad = 0;
         HIPCHK(hipMemcpyAsync(&bad, ws.info + 2, sizeof(int32_t), hipMemcpyDeviceToHost, st));

@@ -10,33 +10,20 @@ namespace pldl {
 constexpr int32_t NZ_NONE = 0x7F7F7F7F;
 // Threads of the base-case leaf (128 x 128 block, 4 rows x 4096/BC_THREADS columns each).
 constexpr int BC_THREADS = 1024;
-// Column chunk a PLDUQ leaf eliminates and the leaf's workgroup size (each
-// thread holds PLDUQ_CHUNK / (PLDUQ_THREADS / 64) entries in registers).
-constexpr int PLDUQ_CHUNK = 256;
-constexpr int PLDUQ_THREADS = 1024;
-// Most workgroups of a PLDUQ right-part update (one first-nonzero candidate each).
-constexpr int NZB_MAX = 2048;
-
-// Device state of a PLDUQ slab (int32 words; see k_plduq_leaf): rows with a
-// pivot so far, next column, done flag, pending leaf (its rank, chunk end and
-// pivot columns), scan-hint count for the next leaf, committed pivot columns.
-constexpr int SS_R = 0, SS_CUR = 1, SS_DONE = 2, SS_PEND = 3, SS_RLAST = 4, SS_CE = 5, SS_NH = 6, SS_PN = 7,
-              SS_ITER = 8, SS_PCOL = 16, SS_CCOL = 80, SS_WORDS = 144;
-
 // PLDUQ slab in one launch (plduq.hip): chunk of PS_CHUNK columns per
 // workgroup of PS_THREADS threads (lane = slab row, each wave PS_CPW columns),
 // at most PS_MAXCH chunks; a wait gives up after PS_SPIN polls.
 constexpr int PS_CPW = 16, PS_THREADS = 1024, PS_CHUNK = PS_CPW * (PS_THREADS / 64), PS_MAXCH = 256;
 constexpr int PS_SPIN = 1 << 20;
-// Device words one slab launch shares between its workgroups.  flag[b] equals
-// the launch's generation once chunk b has published base[b] (slab pivots of
-// the chunks before it), cnt[b] and its pivot records: slab row, column (T row),
-// scaled pivot value and scaled pivot column (64 entries, 0 for rows it does
-// not eliminate).  abort_gen equals the generation of an aborted launch.
+// Device words one slab launch shares between its workgroups.  Once chunk b has
+// published its pivot records (slab row, column (T row), scaled pivot value and
+// scaled pivot column: 64 entries, 0 for rows it does not eliminate) it sets
+// flag[b] = gen << 32 | base << 8 | cnt, with gen the launch's generation, base
+// the slab pivots of the chunks before it and cnt its own: one read gives a
+// waiting chunk everything it needs to fetch the records.  abort_gen equals the
+// generation of an aborted launch.
 struct PsShared {
-    int32_t flag[PS_MAXCH];
-    int32_t base[PS_MAXCH];
-    int32_t cnt[PS_MAXCH];
+    uint64_t flag[PS_MAXCH];
     int32_t abort_gen;
     int32_t prow[64];
     int32_t pcol[64];
@@ -60,24 +47,10 @@ struct PsArgs {
 };
 __global__ void k_plduq_slab(PsArgs g);
 
-// Pivot columns of a PLDUQ slab (T row indices); a slab has at most 64 pivots.
-struct PivList {
-    int32_t col[64];
-    int32_t n;
-};
-
-
 __global__ void k_bc_leaf(double* W, int64_t ld, int64_t lo, int s, Field F, const uint32_t* itab, double* dd,
                           double* de, int32_t* sig_out, int32_t* rank_out, int32_t* hsig);
-__global__ void k_plduq_leaf(double* T, int64_t ld, int64_t a0s, int ms, int64_t cinit, int64_t c1, Field F,
-                             const uint32_t* itab,
-                             const int32_t* hint0, int nhint0, const int32_t* nzb, int32_t* rsig, int32_t* ss,
-                             int32_t* pR);
-__global__ void k_plduq_rupdate(double* T, int64_t ld, int64_t a0s, int ms, int64_t c1, Field F, const uint32_t* itab,
-                                int32_t* nzblk, const int32_t* rsig, int32_t* ss, int32_t* hstate);
 constexpr int TS_THREADS = 256, TS_COLS = 2;   // small TRSM: workgroup size, right-hand sides per wave
 __global__ void k_trsm_small(double* B, int64_t ldb, int64_t nrhs, int r, MatV T, int right, Field F);
-__global__ void k_slab_colsrc(PivList ord, PivList srt, int64_t c0, int64_t len, int32_t* src);
 __global__ void k_inv_scatter(const int32_t* snap, int64_t len, int32_t* inv);
 __global__ void k_src_gather(const int32_t* cur, int64_t len, const int32_t* inv, int32_t* src);
 __global__ void k_rot_src(int64_t len, int64_t rot1, int32_t* src);
@@ -95,7 +68,7 @@ __global__ void k_zlp_sigma_total(int32_t* sig, int64_t mz, int64_t nc, int64_t 
                                   const int32_t* pC);
 __global__ void k_trinv_blocks(MatV T, int64_t r, int lower, double* N, Field F);
 __global__ void k_trss_leaf(double* W, int64_t ld, int64_t s0, int64_t u0, int r, Field F);
-struct PermGeom { int64_t n, lo, hi, s, nb0, nb1, B0, B1, B2, B3; int parts; };
+struct PermGeom { int64_t n, lo, hi, s, c0, nb0, nb1, B0, B1, B2, B3; int parts; };
 __global__ void k_perm_sym(double* W, int64_t ld, PermGeom g, const int32_t* sig, double* tmp,
                            int32_t* orig, int32_t* tmpo, int dir);
 __global__ void k_scale_pack(double* X, int64_t ld, int64_t rows, int64_t cols, const double* P, int64_t ldp,
@@ -124,7 +97,18 @@ template <typename T>
 __global__ void k_load_input(const T* A, int64_t lda, double* W, int64_t ld, int64_t n, Field F, int32_t* err);
 template <typename T>
 __global__ void k_store_output(T* A, int64_t lda, const double* W, int64_t ld, int64_t n, const double* dd,
-                               const double* de, T* e, const int32_t* orig, int32_t* perm);
+                               const double* de, T* e, const int32_t* orig, int32_t* perm, const int32_t* colblk,
+                               const int32_t* dinv);
+__global__ void k_perm_below(double* W, int64_t ld, int64_t lo, int64_t s, int64_t hi, int64_t n, const int32_t* sig,
+                             int rpw);
+__global__ void k_dead_snapshot(const int32_t* orig, int64_t d0, int64_t d1, int64_t n, int32_t blk, int32_t* colblk,
+                                int32_t* inv);
+__global__ void k_dead_gather(const double* W, int64_t ld, int64_t n, const int32_t* orig, const int32_t* colblk,
+                              const int32_t* dinv, double* tmp);
+// LDS a k_perm_below workgroup may stage (doubles); rows it takes target
+// PERM_BELOW_ROWS_LDS doubles; elements per thread of k_perm_sym
+constexpr int64_t PERM_BELOW_LDS = 8192, PERM_BELOW_ROWS_LDS = 4096;
+constexpr int PERM_EPT = 4;
 __global__ void k_rpm(const int32_t* orig, const double* de, int64_t n, int64_t r, int32_t* rpm);
 __global__ void k_char2_std(double* W, int64_t ld, int64_t n, double* dd, double* de, int32_t* orig, double* tmp,
                             int phase);

@@ -253,339 +253,6 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_leaf(double* W, int64_t ld, i
     }
 }
 
-// ===========================================================================
-// Rank-profile-revealing PLDUQ leaf (Sections 4.2 and 5 pivoting) on the
-// compact transposed copy T of Y (Y[i][j] = T[j][i], leading dimension ld):
-// rows [a0, a0+m) of Y (m <= 64), columns [c0, c1).  The kernel scans
-// PLDUQ_CHUNK-wide column chunks (from max(c0, *hint) when a hint is given: the first column a
-// preceding update found nonzero on these rows) until one holds a nonzero in
-// one of the rows, then eliminates that chunk in row order: a row's pivot is
-// the first nonzero of its reduced row among the chunk's non-pivot columns.
-// Elimination only adds multiples of pivot rows to a row in proportion to its
-// own entries on the pivot columns, so a row that is zero on the live columns
-// stays zero: the loop visits only the rows of an exact nonzero-row mask,
-// i.e. one iteration per pivot.  Right-looking, the chunk in registers, kept
-// reduced (centered) after every update so that the zero tests are exact:
-// thread t owns row t%64 and columns t/64 + g k (g = PLDUQ_THREADS / 64 column
-// groups, k < PLDUQ_CHUNK / g).  Every wave runs the
-// pivot search itself (no serial thread); row, multiplier and mask vectors
-// are double buffered: three barriers per pivot.
-// Output, in place: the LU pack of the chunk with its rows in the new order
-// (pivot rows first, in pivot order, then the others in their previous order;
-// the same reordering applied to pR[a0 .. a0+m)) and its columns in place,
-// rsig (new row -> old row, for the rest of these rows), and in the slab
-// state ss its rank, the end of its chunk and the T rows of its r pivot
-// columns (pending: the next leaf commits them, after the update has used
-// them).  The leaf takes its rows (a0s + R, ms - R rows), first column and scan
-// hint from the state, and returns at once when the slab is done (all rows
-// pivots, columns exhausted, or the active rows zero on what is left), so the
-// host can queue several leaves and updates ahead without reading anything.
-// ===========================================================================
-__global__ __launch_bounds__(PLDUQ_THREADS) void k_plduq_leaf(double* T, int64_t ld, int64_t a0s, int ms,
-                                                     int64_t cinit, int64_t c1, Field F, const uint32_t* itab,
-                                                     const int32_t* hint0, int nhint0, const int32_t* nzb,
-                                                     int32_t* rsig, int32_t* ss, int32_t* pR) {
-    constexpr int NT = PLDUQ_THREADS, NG = NT / 64;          // threads, column groups (one per wave)
-    constexpr int CW = PLDUQ_CHUNK, KC = CW / NG;            // chunk width, columns per thread
-    static_assert(KC <= 64 && CW % 64 == 0 && CW <= 1024, "live mask and search sizes");
-    __shared__ double rowI[2][CW];    // centered reduced row (0 on pivot columns)
-    __shared__ double fvec[2][64];    // centered multipliers of the rows below
-    __shared__ int ispc[CW], cpiv[CW];
-    __shared__ int rpiv[64];
-    __shared__ double pinvx[64];
-    __shared__ int rord[64], cord[64], rposs[64], prl[64];
-    __shared__ unsigned long long wmask[2][NG];
-    __shared__ int sw[SS_WORDS];
-    const int tid = threadIdx.x, row = tid & 63, cg = tid >> 6, lane = tid & 63;
-    // ---- slab state: one parallel read into LDS (or a fresh state from column
-    // cinit for the slab's first leaf), then every thread takes the same
-    // decisions: commit the previous leaf (its update has run), stop when done
-    if (tid < SS_WORDS) sw[tid] = cinit >= 0 ? (tid == SS_CUR ? (int32_t)cinit : 0) : ss[tid];
-    if (cinit >= 0 && tid == 0) {
-        ss[SS_R] = 0; ss[SS_PN] = 0; ss[SS_DONE] = 0; ss[SS_PEND] = 0; ss[SS_NH] = 0; ss[SS_ITER] = 0;
-        ss[SS_CUR] = (int32_t)cinit;
-    }
-    __syncthreads();
-    const int done0 = sw[SS_DONE], rl = sw[SS_RLAST], pn = sw[SS_PN];
-    const bool commit = !done0 && sw[SS_PEND];
-    const int R = sw[SS_R] + (commit ? rl : 0);
-    const int64_t c0 = commit ? sw[SS_CE] : sw[SS_CUR];
-    const bool done = done0 || R >= ms || c0 >= c1;
-    if (commit && tid < rl) ss[SS_PCOL + pn + tid] = sw[SS_CCOL + tid];
-    if (tid == 0) {
-        if (commit) { ss[SS_PN] = pn + rl; ss[SS_R] = R; ss[SS_CUR] = (int32_t)c0; ss[SS_PEND] = 0; }
-        if (done && !done0) ss[SS_DONE] = 1;
-    }
-    if (done) return;
-    const int iter = sw[SS_ITER];
-    const int64_t a0 = a0s + R;
-    const int m = ms - R;
-    const int32_t* hint = iter == 0 ? hint0 : (sw[SS_NH] > 0 ? nzb : nullptr);
-    const int nhint = iter == 0 ? nhint0 : sw[SS_NH];
-    // this leaf's rows' original indices, read now and reordered at the end
-    const int pr_pre = (tid < m) ? pR[a0 + tid] : 0;
-    double y[KC];
-    int64_t cs = c0;
-    if (hint) {   // the minimum of the nhint candidates left by the preceding update
-        __shared__ int hred[NG];
-        int v = NZ_NONE;
-        for (int k = tid; k < nhint; k += NT) v = min(v, hint[k]);
-        for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
-        if (lane == 0) hred[cg] = v;
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < NG; ++q) v = min(v, hred[q]);
-        cs = max(c0, (int64_t)v);
-    }
-    int w = 0;
-    // ---- scan for the first chunk with a nonzero on these rows
-    for (;;) {
-        w = (int)min((int64_t)CW, c1 - cs);
-        if (w <= 0) break;
-        int nzf = 0;
-        // unconditional loads (coordinates clamped into the chunk, masked after) in
-        // groups of 16, so that a group is in flight together
-        const double* in_p = T + (cs + min(cg, w - 1)) * ld + a0 + min(row, m - 1);
-#pragma unroll
-        for (int k = 0; k < KC; ++k) {
-            const int col = cg + NG * k;
-            const double v = (col < w) ? in_p[(int64_t)NG * k * ld] : T[(cs + w - 1) * ld + a0 + min(row, m - 1)];
-            y[k] = (row < m && col < w) ? fcen(v, F) : 0.0;
-            nzf |= (row < m && col < w && v != 0.0);
-            if ((k & 15) == 15) __builtin_amdgcn_sched_barrier(0);
-        }
-        if (__syncthreads_or(nzf)) break;
-        cs += CW;
-    }
-    if (w <= 0) {  // all rows are zero on [c0, c1): the slab is done
-        if (tid == 0) { ss[SS_DONE] = 1; ss[SS_ITER] = iter + 1; }
-        return;
-    }
-    for (int e = tid; e < CW; e += NT) { ispc[e] = 0; cpiv[e] = -1; }
-    if (tid < 64) rpiv[tid] = -1;
-    // live (not yet pivot) columns among this lane's KC, as a register bit mask
-    uint64_t live = 0;
-#pragma unroll
-    for (int k = 0; k < KC; ++k)
-        if (cg + NG * k < w) live |= 1ull << k;
-    // rows (bits) holding a nonzero on the live columns: per-wave ballots, OR-ed
-    auto row_nz = [&]() {
-        bool nz = false;
-#pragma unroll
-        for (int k = 0; k < KC; ++k) nz |= ((live >> k) & 1ull) && y[k] != 0.0;
-        return nz;
-    };
-    {
-        const unsigned long long bal = __ballot(row_nz());
-        if (lane == 0) wmask[0][cg] = bal;
-    }
-    __syncthreads();
-    int r = 0, i = -1, mb = 0;
-    for (;;) {
-        unsigned long long rows_nz = 0;
-#pragma unroll
-        for (int q = 0; q < NG; ++q) rows_nz |= wmask[mb][q];
-        rows_nz &= (i >= 63) ? 0ull : (~0ull << (i + 1));
-        if (rows_nz == 0) break;
-        i = __ffsll((long long)rows_nz) - 1;
-        const int b = r & 1;
-        if (row == i) {
-#pragma unroll
-            for (int k = 0; k < KC; ++k) rowI[b][cg + NG * k] = ((live >> k) & 1ull) ? y[k] : 0.0;
-        }
-        __syncthreads();
-        // every wave finds the first nonzero of the row (lowest column index); the
-        // mask guarantees there is one
-        int c = -1;
-        for (int q = 0; q < CW / 64 && c < 0; ++q) {
-            unsigned long long bal = __ballot(rowI[b][q * 64 + lane] != 0.0);
-            if (bal) c = q * 64 + __ffsll((long long)bal) - 1;
-        }
-        const double x = fcan(rowI[b][c], F);
-        const double xi = itab ? (double)itab[(int)x] : finv(x, F);
-        // this lane's columns: the pivot column leaves the live set
-#pragma unroll
-        for (int k = 0; k < KC; ++k)
-            if (cg + NG * k == c) live &= ~(1ull << k);
-        if (tid == 0) { rpiv[i] = r; cpiv[c] = r; pinvx[r] = xi; ispc[c] = 1; }
-        // multipliers of the rows below: f = Y[i'][c] / x  (owners of column c)
-        if (cg == (c % NG)) {
-            double v = 0.0;
-#pragma unroll
-            for (int k = 0; k < KC; ++k) v = (k == c / NG) ? y[k] : v;
-            fvec[b][row] = (row > i && row < m) ? fredc(v * xi, F) : 0.0;
-        }
-        __syncthreads();
-        const double f = fvec[b][row];
-        // in groups of 8 columns (the barrier keeps the compiler from hoisting every
-        // LDS read of the row ahead of the arithmetic: registers stay at y plus a group)
-#pragma unroll
-        for (int k0 = 0; k0 < KC; k0 += 8) {
-#pragma unroll
-            for (int k = k0; k < k0 + 8; ++k) y[k] = fredc(fma(-f, rowI[b][cg + NG * k], y[k]), F);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        // the pivot column now stores the multipliers (L) of the rows below
-        if (cg == (c % NG) && row > i && row < m) {
-#pragma unroll
-            for (int k = 0; k < KC; ++k)
-                if (k == c / NG) y[k] = f;
-        }
-        ++r;
-        mb ^= 1;
-        const unsigned long long bal = __ballot(row_nz());
-        if (lane == 0) wmask[mb][cg] = bal;
-        __syncthreads();
-    }
-    // ---- orders: pivots first (pivot order), then the rest increasing (ballot prefix counts)
-    if (tid < 64) {
-        bool np = (tid < m) && rpiv[tid] < 0;
-        unsigned long long bal = __ballot(np);
-        int before = __popcll(bal & ((1ull << tid) - 1ull));
-        if (tid < m) {
-            int pos = np ? r + before : rpiv[tid];
-            rord[pos] = tid;
-            rposs[tid] = pos;
-        }
-    }
-    // the pivot columns in pivot order (the other columns stay where they are)
-    for (int e = tid; e < w; e += NT)
-        if (cpiv[e] >= 0) cord[cpiv[e]] = e;
-    if (tid < 64) prl[tid] = pr_pre;
-    __syncthreads();
-    if (tid == 0) { ss[SS_RLAST] = r; ss[SS_CE] = (int32_t)(cs + w); ss[SS_PEND] = 1; ss[SS_ITER] = iter + 1; }
-    if (tid < r) ss[SS_CCOL + tid] = (int32_t)(cs + cord[tid]);   // T row of pivot tid's column
-    if (tid < m) rsig[tid] = rord[tid];
-    // pR follows the new row order (the old entries were read at the start)
-    const int pr_old = (tid < m) ? prl[rord[tid]] : 0;
-    // the tile, already in registers, is written with its rows in the new order
-    // (columns stay in place: the slab moves its pivot columns once, at its end)
-    if (row < m) {
-        const int a = rposs[row];
-        double* out_p = T + (cs + cg) * ld + a0 + a;   // column cg + NG k is NG k ld further
-        const int64_t step = (int64_t)NG * ld;
-#pragma unroll
-        for (int k = 0; k < KC; ++k) {
-            const int col = cg + NG * k;
-            if (col < w) {
-                const int bpos = cpiv[col] >= 0 ? cpiv[col] : (1 << 20);   // pivot index of the column
-                const double v = fred(y[k], F);
-                double out;
-                if (a == bpos && a < r) out = v;                           // D
-                else if (bpos < a && bpos < r) out = v;                    // L / M (stored multipliers)
-                else if (a < bpos && a < r) out = fmulm(v, pinvx[a], F);   // U / V
-                else out = 0.0;
-                out_p[k * step] = out;
-            }
-            if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-        }
-    }
-    if (tid < m) pR[a0 + tid] = pr_old;
-}
-
-// ===========================================================================
-// Right-part update of a PLDUQ tile (the step after a leaf, Sections 4.2 and 3:
-// TRSM with the tile's unit lower L, GEMM with its multipliers M, scaling by
-// D^{-1}), fused into one pass over the columns to the right of the tile.  In
-// the compact transposed copy T, Y column j is T row j and the slab's rows
-// a0 .. a0+m-1 are m contiguous entries of it, so one wave takes one column
-// with lane t on slab row t.  The leaf reordered the rows of its tile (rsig:
-// new row -> old row); each column is gathered through rsig on load, so the
-// reordering and the update share one pass.  The tile's pivot columns sit at T
-// rows ccol[0 .. r) of the slab state (pivot rows first): entry (s, t > s) is the multiplier of
-// row t for pivot s, entry (s, s) is D_s.  For each column: u_s = y_s -
-// sum_{s' < s} L[s][s'] u_s' (column elimination, one wave shuffle per pivot),
-// the other rows y_t -= M[t][s] u_s, then u_s <- u_s / D_s.  At most 64
-// products accumulate before the final reduction (below 2^53 for p < 2^23).
-// The pivot columns of the slab's earlier tiles (pcol of the state) hold these rows'
-// multipliers: they are only reordered.  With nzblk, workgroup b writes to
-// nzblk[b] the first of its columns left nonzero on rows r .. m-1 (NZ_NONE if
-// none): the next leaf's scan starts at the minimum.
-// ===========================================================================
-__global__ __launch_bounds__(256) void k_plduq_rupdate(double* T, int64_t ld, int64_t a0s, int ms, int64_t c1,
-                                                       Field F, const uint32_t* itab, int32_t* nzblk,
-                                                       const int32_t* rsig, int32_t* ss, int32_t* hstate) {
-    __shared__ double Lc[64][64];   // Lc[s][t]: multiplier of row t > s for pivot s, 0 for t <= s
-    __shared__ double dinv[64];
-    __shared__ int wfirst[4];
-    __shared__ int pcol[64], ccol[64];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // the last update of a queued batch hands the state (as the leaf left it) to
-    // the host, through host memory mapped into the device address space
-    if (hstate && blockIdx.x == 0 && tid < SS_WORDS) hstate[tid] = ss[tid];
-    // the leaf's results, not yet committed to the slab state (the next leaf does that)
-    if (ss[SS_DONE] || !ss[SS_PEND]) return;
-    const int R = ss[SS_R], r = ss[SS_RLAST], pn = ss[SS_PN];
-    const int64_t a0 = a0s + R, ce = ss[SS_CE], nr = c1 - ce;
-    const int m = ms - R;
-    const bool more = m > r && nr > 0;   // rows stay active: the next leaf wants a hint
-    if (!more) nzblk = nullptr;
-    if (blockIdx.x == 0 && tid == 0) ss[SS_NH] = more ? (int)gridDim.x : 0;
-    const int64_t stride = (int64_t)gridDim.x * 4, items = nr + pn;
-    if ((int64_t)blockIdx.x * 4 >= items) {   // the grid is sized for the slab's first leaf
-        if (nzblk && tid == 0) nzblk[blockIdx.x] = NZ_NONE;
-        return;
-    }
-    if (tid < r) ccol[tid] = ss[SS_CCOL + tid];
-    if (tid < pn) pcol[tid] = ss[SS_PCOL + tid];
-    __syncthreads();
-    for (int e = tid; e < r * 64; e += 256) {
-        const int sp = e >> 6, t = e & 63;
-        Lc[sp][t] = (t > sp && t < m) ? fcen(T[(int64_t)ccol[sp] * ld + a0 + t], F) : 0.0;
-    }
-    if (tid < r) {
-        const double d = T[(int64_t)ccol[tid] * ld + a0 + tid];
-        dinv[tid] = itab ? (double)itab[(int)d] : finv(d, F);
-    }
-    __syncthreads();
-    const int src = (lane < m) ? rsig[lane] : 0;
-    int first = NZ_NONE;
-    for (int64_t jj = (int64_t)blockIdx.x * 4 + wave; jj < items; jj += stride) {
-        if (jj >= nr) {   // an earlier pivot column: reorder only
-            double* col = T + (int64_t)pcol[jj - nr] * ld + a0;
-            const double v = (lane < m) ? col[src] : 0.0;
-            if (lane < m) col[lane] = v;
-            continue;
-        }
-        double* col = T + (ce + jj) * ld + a0;
-        double y = (lane < m) ? fcen(col[src], F) : 0.0;
-        for (int sp = 0; sp < r; ++sp) {
-            const double us = fredc(__shfl(y, sp), F);
-            y = (lane == sp) ? us : fma(-Lc[sp][lane], us, y);
-        }
-        double out;
-        if (lane < r) out = fmulm(y, dinv[lane], F);
-        else out = fred(y, F);
-        if (lane < m) col[lane] = out;
-        if (first == NZ_NONE && __ballot(lane >= r && lane < m && out != 0.0)) first = (int)(ce + jj);
-    }
-    if (nzblk) {
-        if (lane == 0) wfirst[wave] = first;
-        __syncthreads();
-        if (tid == 0) nzblk[blockIdx.x] = min(min(wfirst[0], wfirst[1]), min(wfirst[2], wfirst[3]));
-    }
-}
-
-// The column order of a finished PLDUQ slab on [c0, c0+len): its pivot columns
-// (T rows ord.col[], in pivot order) first, then the other positions in
-// increasing order (srt: the same columns sorted).  src[q] = old position
-// relative to c0.
-__global__ void k_slab_colsrc(PivList ord, PivList srt, int64_t c0, int64_t len, int32_t* src) {
-    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (q >= len) return;
-    int64_t pos;
-    if (q < ord.n) {
-        pos = ord.col[q] - c0;
-    } else {
-        pos = q - ord.n;   // the pos-th position that is not a pivot column
-        for (int s = 0; s < srt.n; ++s) {
-            if (srt.col[s] - c0 <= pos) ++pos;
-            else break;
-        }
-    }
-    src[q] = (int32_t)pos;
-}
-
 // inv[snap[q]] = q (snap: a segment of an index array before a reordering)
 __global__ void k_inv_scatter(const int32_t* snap, int64_t len, int32_t* inv) {
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -937,45 +604,156 @@ __device__ __forceinline__ int64_t sigma_at(const int32_t* sig, int64_t q, int64
 }
 
 // Symmetric permutation of the position range [lo, hi) of W, through tmp:
-// part 0 rows [lo,hi) x cols [0,lo); part 1 the lower block; part 2 rows
-// [hi,n) x cols [lo,hi); part 3 orig.  One flat grid: block b is decoded into
-// (part, row, column block); `dir` 0 gathers into tmp, 1 scatters back.
+// part 0 rows [lo,hi) x cols [c0,lo) (the columns left of the range that are
+// still read later); part 1 the lower block; part 2 rows [hi,n) x cols [lo,hi)
+// (when it is not done in one pass by k_perm_below); part 3 orig.  One flat
+// grid: block b is decoded into (part, row, column block); `dir` 0 gathers into
+// tmp, 1 scatters back.
 __global__ __launch_bounds__(256) void k_perm_sym(double* W, int64_t ld, PermGeom g, const int32_t* sig,
                                                  double* tmp, int32_t* orig, int32_t* tmpo, int dir) {
+    constexpr int EPT = PERM_EPT, CH = 256 * EPT;   // elements per thread, per block
     int64_t b = blockIdx.x;
     const int64_t s = g.s, lo = g.lo, hi = g.hi;
+    const int tid = threadIdx.x;
     int part;
     if (b < g.B0) part = 0;
     else if ((b -= g.B0) < g.B1) part = 1;
     else if ((b -= g.B1) < g.B2) part = 2;
     else { b -= g.B2; part = 3; }
+    const int64_t wl = lo - g.c0;   // width of part 0
+    double v[EPT];
     if (part == 0) {
-        int64_t row = b / g.nb0, c = (b - row * g.nb0) * 256 + threadIdx.x;
-        if (c >= lo) return;
-        if (dir == 0) tmp[row * lo + c] = W[(lo + sigma_at(sig, row, s)) * ld + c];
-        else W[(lo + row) * ld + c] = tmp[row * lo + c];
+        const int64_t row = b / g.nb0, cb = (b - row * g.nb0) * CH + tid;
+        const double* src = dir == 0 ? W + (lo + sigma_at(sig, row, s)) * ld + g.c0 : tmp + row * wl;
+        double* dst = dir == 0 ? tmp + row * wl : W + (lo + row) * ld + g.c0;
+#pragma unroll
+        for (int q = 0; q < EPT; ++q)
+            if (cb + q * 256 < wl) v[q] = src[cb + q * 256];
+#pragma unroll
+        for (int q = 0; q < EPT; ++q)
+            if (cb + q * 256 < wl) dst[cb + q * 256] = v[q];
     } else if (part == 1) {
-        int64_t row = b / g.nb1, c = (b - row * g.nb1) * 256 + threadIdx.x;
-        if (c > row) return;
+        const int64_t row = b / g.nb1, cb = (b - row * g.nb1) * CH + tid;
+        double* t = tmp + s * wl + row * s;
         if (dir == 0) {
-            int64_t x = lo + sigma_at(sig, row, s), y = lo + sigma_at(sig, c, s);
-            tmp[s * lo + row * s + c] = (x >= y) ? W[x * ld + y] : W[y * ld + x];
+            const int64_t x = lo + sigma_at(sig, row, s);
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) {
+                const int64_t c = cb + q * 256;
+                if (c <= row) {
+                    const int64_t y = lo + sigma_at(sig, c, s);
+                    v[q] = (x >= y) ? W[x * ld + y] : W[y * ld + x];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < EPT; ++q)
+                if (cb + q * 256 <= row) t[cb + q * 256] = v[q];
         } else {
-            W[(lo + row) * ld + lo + c] = tmp[s * lo + row * s + c];
+#pragma unroll
+            for (int q = 0; q < EPT; ++q)
+                if (cb + q * 256 <= row) v[q] = t[cb + q * 256];
+#pragma unroll
+            for (int q = 0; q < EPT; ++q)
+                if (cb + q * 256 <= row) W[(lo + row) * ld + lo + cb + q * 256] = v[q];
         }
     } else if (part == 2) {
-        int64_t row = b / g.nb1, c = (b - row * g.nb1) * 256 + threadIdx.x;
-        if (c >= s) return;
-        if (dir == 0) tmp[s * lo + s * s + row * s + c] = W[(hi + row) * ld + lo + sigma_at(sig, c, s)];
-        else W[(hi + row) * ld + lo + c] = tmp[s * lo + s * s + row * s + c];
+        const int64_t row = b / g.nb1, cb = (b - row * g.nb1) * CH + tid;
+        double* t = tmp + s * wl + s * s + row * s;
+        double* w = W + (hi + row) * ld + lo;
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int64_t c = cb + q * 256;
+            if (c < s) v[q] = dir == 0 ? w[sigma_at(sig, c, s)] : t[c];
+        }
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int64_t c = cb + q * 256;
+            if (c < s) {
+                if (dir == 0) t[c] = v[q];
+                else w[c] = v[q];
+            }
+        }
     } else {
-        int64_t c = b * 256 + threadIdx.x;
-        if (c >= s) return;
-        if (dir == 0) tmpo[c] = orig[lo + sigma_at(sig, c, s)];
-        else orig[lo + c] = tmpo[c];
+        const int64_t cb = b * CH + tid;
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int64_t c = cb + q * 256;
+            if (c < s) {
+                if (dir == 0) tmpo[c] = orig[lo + sigma_at(sig, c, s)];
+                else orig[lo + c] = tmpo[c];
+            }
+        }
     }
 }
 
+
+// Part 2 of a symmetric permutation in one pass: rows [hi, n) x columns
+// [lo, lo+s), each row segment staged in LDS (rpw rows of s doubles per
+// workgroup) and written back as new[q] = old[sig[q]].  Eight loads in
+// flight per thread.
+__global__ __launch_bounds__(256) void k_perm_below(double* W, int64_t ld, int64_t lo, int64_t s, int64_t hi,
+                                                    int64_t n, const int32_t* sig, int rpw) {
+    extern __shared__ double seg[];
+    const int64_t r0 = hi + (int64_t)blockIdx.x * rpw;
+    const int nr = (int)min((int64_t)rpw, n - r0);
+    const int si = (int)s, tot = nr * si, tid = threadIdx.x;
+    double v[8];
+    for (int base = 0; base < tot; base += 256 * 8) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = base + q * 256 + tid;
+            if (e < tot) {
+                const int rr = e / si, c = e - rr * si;
+                v[q] = W[(r0 + rr) * ld + lo + c];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = base + q * 256 + tid;
+            if (e < tot) seg[e] = v[q];
+        }
+    }
+    __syncthreads();
+    for (int base = 0; base < tot; base += 256 * 8) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = base + q * 256 + tid;
+            if (e < tot) {
+                const int rr = e / si, c = e - rr * si;
+                v[q] = seg[rr * si + (int)sigma_at(sig, c, s)];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = base + q * 256 + tid;
+            if (e < tot) {
+                const int rr = e / si, c = e - rr * si;
+                W[(r0 + rr) * ld + lo + c] = v[q];
+            }
+        }
+    }
+}
+
+// Columns [d0, d1) stop being moved by later row permutations (no step reads
+// them before the output): record where each original index sits now, for the
+// rows that hold entries in them (positions d0 .. n-1), and mark the columns.
+__global__ void k_dead_snapshot(const int32_t* orig, int64_t d0, int64_t d1, int64_t n, int32_t blk, int32_t* colblk,
+                                int32_t* inv) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= d0 && q < n) inv[orig[q]] = (int32_t)q;
+    if (q >= d0 && q < d1) colblk[q] = blk;
+}
+
+// tmp[i][j] = entry (i, j) of the finished factorization for j < i: W[i][j], or
+// for a column that stopped moving, the row where original index orig[i] sat then.
+__global__ void k_dead_gather(const double* W, int64_t ld, int64_t n, const int32_t* orig, const int32_t* colblk,
+                              const int32_t* dinv, double* tmp) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
+    if (i >= n || j > i) return;
+    const int32_t blk = j < i ? colblk[j] : -1;
+    const int64_t src = blk >= 0 ? dinv[(int64_t)blk * n + orig[i]] : i;
+    tmp[i * ld + j] = W[src * ld + j];
+}
 
 // Merge two runs of positions [a, a+n1) and [a+n1, a+n1+n2), each sorted by
 // original index, into one sorted run: sig[rank] = local index.
@@ -1231,13 +1009,21 @@ __global__ void k_load_input(const T* A, int64_t lda, double* W, int64_t ld, int
     W[i * ld + j] = v;
 }
 
+// colblk / dinv (may be NULL): columns that stopped moving (see k_dead_snapshot)
+// are read from the row where original index orig[i] sat when they stopped.
 template <typename T>
 __global__ void k_store_output(T* A, int64_t lda, const double* W, int64_t ld, int64_t n, const double* dd,
-                               const double* de, T* e, const int32_t* orig, int32_t* perm) {
+                               const double* de, T* e, const int32_t* orig, int32_t* perm, const int32_t* colblk,
+                               const int32_t* dinv) {
     int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     int64_t i = blockIdx.y;
     if (i >= n || j > i) return;
-    A[i * lda + j] = (T)(j == i ? dd[i] : W[i * ld + j]);
+    if (j == i) A[i * lda + j] = (T)dd[i];
+    else {
+        const int32_t blk = colblk ? colblk[j] : -1;
+        const int64_t src = blk >= 0 ? dinv[(int64_t)blk * n + orig[i]] : i;
+        A[i * lda + j] = (T)W[src * ld + j];
+    }
     if (j == 0) { e[i] = (T)de[i]; perm[i] = orig[i]; }
 }
 
@@ -1406,8 +1192,10 @@ template __global__ void k_load_factors<double>(const double*, int64_t, int64_t,
 template __global__ void k_load_input<uint32_t>(const uint32_t*, int64_t, double*, int64_t, int64_t, Field, int32_t*);
 template __global__ void k_load_input<double>(const double*, int64_t, double*, int64_t, int64_t, Field, int32_t*);
 template __global__ void k_store_output<uint32_t>(uint32_t*, int64_t, const double*, int64_t, int64_t, const double*,
-                                                  const double*, uint32_t*, const int32_t*, int32_t*);
+                                                  const double*, uint32_t*, const int32_t*, int32_t*, const int32_t*,
+                                                  const int32_t*);
 template __global__ void k_store_output<double>(double*, int64_t, const double*, int64_t, int64_t, const double*,
-                                                const double*, double*, const int32_t*, int32_t*);
+                                                const double*, double*, const int32_t*, int32_t*, const int32_t*,
+                                                const int32_t*);
 
 }  // namespace pldl

@@ -51,26 +51,29 @@ __device__ __forceinline__ double rdlane(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Waits for *flag == gen.  false: the launch was aborted (or this wait timed
-// out and aborted it).  Relaxed polls; one acquire fence once the flag is seen.
-__device__ bool ps_wait(const int32_t* flag, int32_t gen, int32_t* abort_word, int32_t* herr) {
+// Waits for chunk flag *flag to carry generation gen and returns it (base and
+// count in its low word).  0: the launch was aborted (or this wait timed out and
+// aborted it).  Relaxed polls; one agent-scope acquire fence once it is seen.
+__device__ uint64_t ps_wait(const uint64_t* flag, int32_t gen, int32_t* abort_word, int32_t* herr) {
     for (int it = 0;; ++it) {
-        const int32_t v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (v == gen) {
-            __atomic_thread_fence(__ATOMIC_ACQUIRE);
-            return true;
+        const uint64_t v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((int32_t)(v >> 32) == gen) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            return v;
         }
         if ((it & 31) == 31 &&
             __hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen)
-            return false;
+            return 0;
         if (it >= PS_SPIN) {
             __hip_atomic_store(abort_word, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (herr) __hip_atomic_store(herr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            return false;
+            return 0;
         }
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(1);
     }
 }
+__device__ __forceinline__ int flag_base(uint64_t v) { return (int)((v >> 8) & 0xff); }
+__device__ __forceinline__ int flag_cnt(uint64_t v) { return (int)(v & 0xff); }
 
 }  // namespace
 
@@ -86,7 +89,7 @@ __global__ __launch_bounds__(PS_THREADS) void k_plduq_slab(PsArgs g) {
     __shared__ double xinv_l[64], dval_l[64];
     __shared__ int newpos[64];
     __shared__ unsigned long long cmask[PS_CHUNK / 64];
-    __shared__ int okw;
+    __shared__ int okw, rtot;
 
     const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const Field F = g.F;
@@ -134,13 +137,25 @@ __global__ __launch_bounds__(PS_THREADS) void k_plduq_slab(PsArgs g) {
     bool ok = true;
     int base = 0;
     for (int bp = 0; bp < b && ok; ++bp) {
-        ok = ps_wait(&sh->flag[bp], g.gen, &sh->abort_gen, g.hout + 1);
+        const uint64_t fv = ps_wait(&sh->flag[bp], g.gen, &sh->abort_gen, g.hout + 1);
+        ok = fv != 0;
         if (!ok) break;
-        const int bb = __builtin_amdgcn_readfirstlane(sh->base[bp]);
-        const int bc = __builtin_amdgcn_readfirstlane(sh->cnt[bp]);
-        for (int s = bb; s < bb + bc; ++s) {
-            const int i = __builtin_amdgcn_readfirstlane(sh->prow[s]);
-            apply(i, sh->px[s], sh->pf[s * 64 + lane]);
+        const int bb = __builtin_amdgcn_readfirstlane(flag_base(fv));
+        const int bc = __builtin_amdgcn_readfirstlane(flag_cnt(fv));
+        // the records of up to four pivots in flight at once
+        for (int s0 = bb; s0 < bb + bc; s0 += 4) {
+            int ri[4];
+            double rx[4], rf[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int s = min(s0 + q, bb + bc - 1);
+                ri[q] = sh->prow[s];
+                rx[q] = sh->px[s];
+                rf[q] = sh->pf[s * 64 + lane];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (s0 + q < bb + bc) apply(__builtin_amdgcn_readfirstlane(ri[q]), rx[q], rf[q]);
         }
         base = bb + bc;
     }
@@ -189,24 +204,22 @@ __global__ __launch_bounds__(PS_THREADS) void k_plduq_slab(PsArgs g) {
         ++r;
     }
 
-    // ---- publish: records first, then the flag
-    __threadfence();
+    // ---- publish: records first (every wave's stores released), then the flag
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (tid == 0) {
-        sh->base[b] = base;
-        sh->cnt[b] = r;
-        __threadfence();
-        __hip_atomic_store(&sh->flag[b], g.gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t fv = ((uint64_t)(uint32_t)g.gen << 32) | ((uint64_t)base << 8) | (uint64_t)r;
+        __hip_atomic_store(&sh->flag[b], fv, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 
     // ---- every chunk published: final values, final places
     if (tid < 64) {
-        ok = ps_wait(&sh->flag[g.nch - 1], g.gen, &sh->abort_gen, g.hout + 1);
-        if (tid == 0) okw = ok;
+        const uint64_t fv = ps_wait(&sh->flag[g.nch - 1], g.gen, &sh->abort_gen, g.hout + 1);
+        if (tid == 0) { okw = fv != 0; rtot = flag_base(fv) + flag_cnt(fv); }
     }
     __syncthreads();
     if (!okw) return;
-    const int R = __builtin_amdgcn_readfirstlane(sh->base[g.nch - 1] + sh->cnt[g.nch - 1]);
+    const int R = rtot;
     if (wave == 0) {
         // 1/x_s, the exclusive prefix products of 1/x (1/S_s) and D_s = x_s / S_s
         rowpiv[lane] = -1;
