@@ -34,6 +34,7 @@ extern "C" {
 #define PLDL_EHIP 3            /* HIP runtime error (text in pldl_last_error)    */
 #define PLDL_ENOMEM 4          /* workspace allocation failed                    */
 #define PLDL_EINTERNAL 5       /* internal consistency check failed              */
+#define PLDL_ETOOBIG 6         /* larger than the fixed scratch of an allocation-free call */
 
 #define PLDL_U32 0             /* uint32 residues */
 #define PLDL_F64 1             /* FP64 residues   */
@@ -235,6 +236,23 @@ int pldl_trss(pldl_ctx *ctx, uint32_t p, int64_t n, const double *U, int64_t ldu
  */
 int pldl_plduq(pldl_ctx *ctx, uint32_t p, int64_t m, int64_t n, double *Y, int64_t ldy,
                int32_t *rows, int32_t *cols, int64_t *rank, void *stream);
+
+/*
+ * pldl_syrdk_noalloc -- pldl_syrdk (same arguments, same result) for callers
+ * that cannot allocate device memory: code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc.  The call allocates nothing: A D (and
+ * B D) are staged in a fixed device array of PLDL_NOALLOC_SCRATCH_DOUBLES
+ * doubles per GPU (16 MiB, held from the context's creation to the end of the
+ * process), and the products run on the FP64 matrix cores whatever the
+ * context's path.  Limit: n * k (2 n k with B) <= PLDL_NOALLOC_SCRATCH_DOUBLES,
+ * else PLDL_ETOOBIG.  Asynchronous: nothing is waited for (read C after
+ * synchronising `stream`).  Calls that overlap on one GPU share the array and
+ * race: serialise them.
+ */
+#define PLDL_NOALLOC_SCRATCH_DOUBLES (1 << 21)
+int pldl_syrdk_noalloc(pldl_ctx *ctx, uint32_t p, int64_t n, int64_t k, const double *A, int64_t lda,
+                       const double *B, int64_t ldb, const double *dd, const double *de,
+                       double *C, int64_t ldc, void *stream);
 
 /*
  * Matrix cores used by the products (GEMM, TRMM, SYRDK, SYRD2K of Section 3)

@@ -131,6 +131,10 @@ void launch_factor_batched(hipStream_t s, const Field& F, const uint32_t* itab, 
 // Longest K (summed over the segments of one product) the INT8 split accumulates
 // exactly in INT32: a shift class gains at most 2^15 per k, 65535 * 2^15 < 2^31.
 constexpr int64_t I8_MAX_KTOT = 65535;
+// The allocation-free entry point's device array (noalloc.hip): resolved per
+// device by noalloc_init (the device current), read back by noalloc_scratch.
+bool noalloc_init(int device);
+double* noalloc_scratch(int device);
 // Products below this many flops stay on FP64 inside a factorization.
 constexpr double I8_MIN_FLOPS = 134217728.0;   // 2^27: below it the limb split costs more than it saves
 

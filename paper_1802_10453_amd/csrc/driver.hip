@@ -922,6 +922,12 @@ int pldl_create(pldl_ctx** ctx, int device) {
     if (!ctx) return -1;
     int cnt = 0;
     if (hipGetDeviceCount(&cnt) != hipSuccess || device < 0 || device >= cnt) return -2;
+    // the allocation-free entry point's array, resolved on this device
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess) return PLDL_EHIP;
+    const bool na = noalloc_init(device);
+    (void)hipSetDevice(prev);
+    if (!na) return PLDL_EHIP;
     pldl_ctx* c = new (std::nothrow) pldl_ctx();
     if (!c) return PLDL_ENOMEM;
     c->device = device;
@@ -1116,6 +1122,43 @@ int pldl_syrdk(pldl_ctx* ctx, uint32_t p, int64_t n, int64_t k, const double* A,
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
     });
+}
+
+int pldl_syrdk_noalloc(pldl_ctx* ctx, uint32_t p, int64_t n, int64_t k, const double* A, int64_t lda, const double* B,
+                       int64_t ldb, const double* dd, const double* de, double* C, int64_t ldc, void* stream) {
+    if (!ctx) return -1;
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (n < 0) return fail(ctx, -3, "n < 0");
+    if (k < 0) return fail(ctx, -4, "k < 0");
+    if (n > 0 && k > 0 && !A) return fail(ctx, -5, "A is NULL");
+    if (lda < std::max<int64_t>(1, k)) return fail(ctx, -6, "lda too small");
+    if (B && ldb < std::max<int64_t>(1, k)) return fail(ctx, -8, "ldb too small");
+    if (k > 0 && (!dd || !de)) return fail(ctx, -9, "dd/de is NULL");
+    if (n > 0 && !C) return fail(ctx, -11, "C is NULL");
+    if (ldc < std::max<int64_t>(1, n)) return fail(ctx, -12, "ldc too small");
+    if (n > 0 && k > 0 && (double)n * (double)k * (B ? 2.0 : 1.0) > (double)PLDL_NOALLOC_SCRATCH_DOUBLES)
+        return fail(ctx, PLDL_ETOOBIG, "n * k (2 n k with B) exceeds the allocation-free scratch of " +
+                                           std::to_string(PLDL_NOALLOC_SCRATCH_DOUBLES) + " doubles");
+    if (n == 0 || k == 0) return PLDL_OK;
+    double* sp = noalloc_scratch(ctx->device);
+    if (!sp) return fail(ctx, PLDL_EINTERNAL, "the allocation-free scratch was not resolved on this device");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, PLDL_EHIP, "hipSetDevice failed");
+    hipStream_t st = as_stream(stream);
+    const Field F = make_field(p);
+    double* AD = sp;
+    double* BD = sp + n * k;
+    hipLaunchKernelGGL(k_apply_d, dim3(nblk(k), (unsigned)n), dim3(256), 0, st, A, lda, n, k, dd, de, AD, F);
+    GemmSeg segs[2] = {GemmSeg{MatV{AD, k, 1}, B ? MatV{(double*)B, 1, ldb} : MatV{(double*)A, 1, lda}, k},
+                       GemmSeg{MatV{nullptr, 0, 1}, MatV{nullptr, 0, 1}, 0}};
+    if (B) {
+        hipLaunchKernelGGL(k_apply_d, dim3(nblk(k), (unsigned)n), dim3(256), 0, st, B, ldb, n, k, dd, de, BD, F);
+        segs[1] = GemmSeg{MatV{BD, k, 1}, MatV{(double*)A, 1, lda}, k};
+    }
+    launch_gemm(st, F, n, n, C, ldc, segs, 2, true, false);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ctx, PLDL_EHIP, std::string("launch failed: ") + hipGetErrorString(e));
+    ctx->err.clear();
+    return PLDL_OK;
 }
 
 int pldl_trss(pldl_ctx* ctx, uint32_t p, int64_t n, const double* U, int64_t ldu, const double* C, int64_t ldc,

@@ -24,7 +24,9 @@ _vp, _i64, _i32, _u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.
 
 PLDL_U32, PLDL_F64 = 0, 1
 PLDL_PATH_AUTO, PLDL_PATH_F64, PLDL_PATH_I8 = 0, 1, 2
-ERRORS = {1: "PLDL_ERANGE", 2: "PLDL_EUNSUPPORTED_P", 3: "PLDL_EHIP", 4: "PLDL_ENOMEM", 5: "PLDL_EINTERNAL"}
+ERRORS = {1: "PLDL_ERANGE", 2: "PLDL_EUNSUPPORTED_P", 3: "PLDL_EHIP", 4: "PLDL_ENOMEM", 5: "PLDL_EINTERNAL",
+          6: "PLDL_ETOOBIG"}
+NOALLOC_SCRATCH_DOUBLES = 1 << 21
 ERRORS_BY_NAME = {v: k for k, v in ERRORS.items()}
 
 
@@ -61,6 +63,7 @@ _lib.pldl_factor.argtypes = [_vp, _u32, _i64, _vp, _i64, _i32, _vp, _vp, _vp, ct
 _lib.pldl_gemm.argtypes = [_vp, _u32, _i64, _i64, _i64, _vp, _i64, _i32, _vp, _i64, _i32, _vp, _i64, _i32, _vp]
 _lib.pldl_trsm.argtypes = [_vp, _u32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp]
 _lib.pldl_syrdk.argtypes = [_vp, _u32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _i64, _vp]
+_lib.pldl_syrdk_noalloc.argtypes = [_vp, _u32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _i64, _vp]
 _lib.pldl_trss.argtypes = [_vp, _u32, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]
 _lib.pldl_plduq.argtypes = [_vp, _u32, _i64, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(_i64), _vp]
 _lib.pldl_profile.argtypes = [_vp, _i32, ctypes.POINTER(pldl_stats)]
@@ -69,13 +72,14 @@ _lib.pldl_char2_to_standard.argtypes = [_vp, _i64, _vp, _i64, _i32, _vp, _vp, _v
 _lib.pldl_autotune.argtypes = [_vp, _u32, ctypes.POINTER(_i64), _i64, ctypes.c_char_p, _vp]
 _lib.pldl_factor_batched.argtypes = [_vp, _u32, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
                                      ctypes.POINTER(pldl_opts), _vp]
-for _f in ("pldl_create", "pldl_destroy", "pldl_factor", "pldl_gemm", "pldl_trsm", "pldl_syrdk", "pldl_trss",
+for _f in ("pldl_create", "pldl_destroy", "pldl_factor", "pldl_gemm", "pldl_trsm", "pldl_syrdk", "pldl_syrdk_noalloc",
+           "pldl_trss",
            "pldl_plduq", "pldl_profile", "pldl_set_path", "pldl_factor_batched", "pldl_char2_to_standard",
            "pldl_autotune"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("pldl_create", "pldl_destroy", "pldl_last_error", "pldl_factor", "pldl_gemm", "pldl_trsm",
-            "pldl_syrdk", "pldl_trss", "pldl_plduq", "pldl_profile", "pldl_set_path", "pldl_factor_batched",
+            "pldl_syrdk", "pldl_syrdk_noalloc", "pldl_trss", "pldl_plduq", "pldl_profile", "pldl_set_path", "pldl_factor_batched",
             "pldl_char2_to_standard", "pldl_autotune")
 
 
@@ -236,6 +240,14 @@ class Context:
         n, k = A.shape
         rc = _lib.pldl_syrdk(self._h, p, n, k, _ptr(A), _ld(A), _ptr(B), _ld(B) if B is not None else 1,
                              _ptr(dd), _ptr(de), _ptr(C), _ld(C), _stream())
+        self._check(rc)
+        return C
+
+    def syrdk_noalloc(self, p, C, A, dd, de, B=None):
+        """pldl_syrdk_noalloc: the same product with no device allocation (asynchronous)."""
+        n, k = A.shape
+        rc = _lib.pldl_syrdk_noalloc(self._h, p, n, k, _ptr(A), _ld(A), _ptr(B), _ld(B) if B is not None else 1,
+                                     _ptr(dd), _ptr(de), _ptr(C), _ld(C), _stream())
         self._check(rc)
         return C
 
