@@ -104,6 +104,29 @@ def cpu_baseline_batched(mats, params, p, sample=2048):
                        f"{ops / dt / 1e9:.3f} effective GOPS)")
 
 
+def pluq_comparison(ctx, torch, A0, p, ldlt_ms, ldlt_rank, steps=2):
+    """The same input factored as an unsymmetric matrix by the rank-profile-revealing
+    PLUQ (pldl_plduq, the elimination the symmetric one is compared with in Section 6):
+    one warm-up, then `steps` timed calls on fresh FP64 copies."""
+    log("[bench] unsymmetric PLUQ of the same input ...")
+    copies = [A0.double() for _ in range(steps + 1)]
+    out = ctx.plduq(p, copies[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        out = ctx.plduq(p, copies[1 + k])
+    torch.cuda.synchronize()
+    pms = (time.perf_counter() - t0) * 1e3 / steps
+    del copies
+    if out["rank"] != ldlt_rank:
+        log(f"[bench] PLUQ rank {out['rank']} differs from the factorization's {ldlt_rank}")
+        sys.exit(1)
+    log(f"[bench] PLUQ {pms:.3f} ms per call, {pms / ldlt_ms:.2f}x the symmetric factorization")
+    return dict(pluq_ms_per_step=round(pms, 3), ldlt_ms_per_step=round(ldlt_ms, 3),
+                pluq_over_ldlt=round(pms / ldlt_ms, 3), rank=out["rank"], steps=steps,
+                entry="pldl_plduq on the same n x n input (FP64 residues)")
+
+
 def bench_batched(args, torch, inputs, pldl):
     """Batched workload: every step is one replay of a captured graph holding the whole
     persistent batched launch, on its own copy of the input batch."""
@@ -207,6 +230,8 @@ def main():
                          "split into signed bytes")
     ap.add_argument("--no-profile", action="store_true", help="time without per-launch events (no roofline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pluq", action="store_true",
+                    help="skip the comparison with the unsymmetric RPM-revealing PLUQ (pldl_plduq) of the same input")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="before the timed steps, run one plain device copy of BYTES bytes (an elementwise "
                          "kernel reading and writing BYTES each): the reference for the HBM counters")
@@ -313,6 +338,9 @@ def main():
                 + (f"  {v['ops8'] / v['ms'] / 1e9:8.2f} INT8 TOP/s" if v["ops8"] and v["ms"] else "")
                 + (f"  {v['bytes'] / v['ms'] / 1e6:8.1f} GB/s" if v["bytes"] and v["ms"] else ""))
         log(f"    sum of kernel time {tot_ms:.3f} ms; timed steps {ms:.3f} ms/step")
+    pluq = None
+    if not args.no_pluq:
+        pluq = pluq_comparison(ctx, torch, A0, p, ms, r)
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
@@ -327,6 +355,8 @@ def main():
                    "input": "uint32 residues in HBM", "schedule": sched},
         "roofline": roofline, "cpu_baseline": cpu,
     }
+    if pluq is not None:
+        line["pluq_comparison"] = pluq
     print(json.dumps(line), flush=True)
     ctx.close()
 

@@ -428,7 +428,7 @@ struct Engine {
         const int64_t c0 = (parts & 1) ? (track_dead ? std::min(std::max<int64_t>(al, 0), lo) : 0) : lo;
         if (parts & 1) stop_columns(c0);
         // rows below in one pass through LDS when a row segment fits
-        const bool below1 = (parts & 4) && n > hi && s <= PERM_BELOW_LDS;
+        const bool below1 = (parts & 4) && n > hi && s <= SEG_PERM_LDS;
         PermGeom g{};
         g.n = n; g.lo = lo; g.hi = hi; g.s = s; g.c0 = c0; g.parts = parts;
         g.nb0 = nblk(std::max<int64_t>(lo - c0, 1), 256 * PERM_EPT);
@@ -449,10 +449,10 @@ struct Engine {
             prof->n_launch += 2;
         }
         if (below1) {
-            const int rpw = (int)std::max<int64_t>(1, PERM_BELOW_ROWS_LDS / s);
+            const int rpw = (int)std::max<int64_t>(1, SEG_PERM_ROWS_LDS / s);
             const int64_t nwg = (n - hi + rpw - 1) / rpw;
             REQUIRE(nwg < ((int64_t)1 << 31));
-            hipLaunchKernelGGL(k_perm_below, dim3((unsigned)nwg), dim3(256), (size_t)rpw * s * sizeof(double), st, W, ld,
+            hipLaunchKernelGGL(k_seg_perm, dim3((unsigned)nwg), dim3(256), (size_t)rpw * s * sizeof(double), st, W, ld,
                                lo, s, hi, n, sig, rpw);
             prof->n_launch += 1;
         }
@@ -714,7 +714,7 @@ struct Engine {
     void tcolperm(int64_t j0, int64_t len, const int32_t* src, int64_t i0, int64_t ni) {
         if (len <= 1 || ni <= 0) return;
         REQUIRE(len <= 65535 && len * ni <= ws.cap * ws.cap);
-        dim3 g(nblk(ni), (unsigned)len);
+        dim3 g(nblk(ni, 256 * PERM_EPT), (unsigned)len);
         prof->begin(st, PLDL_CLASS_PERM, 0.0, 16.0 * (double)len * (double)ni);
         hipLaunchKernelGGL(k_tcolperm, g, dim3(256), 0, st, T, ldT, j0, len, src, i0, ni, ws.tmp1, 0);
         hipLaunchKernelGGL(k_tcolperm, g, dim3(256), 0, st, T, ldT, j0, len, src, i0, ni, ws.tmp1, 1);
@@ -725,12 +725,20 @@ struct Engine {
     void trowperm(int64_t j0, int64_t nj, int64_t i0, int64_t len, const int32_t* src) {
         if (len <= 1 || nj <= 0) return;
         REQUIRE(nj <= 65535 && len * nj <= ws.cap * ws.cap);
-        dim3 g(nblk(len), (unsigned)nj);
         prof->begin(st, PLDL_CLASS_PERM, 0.0, 16.0 * (double)len * (double)nj);
-        hipLaunchKernelGGL(k_trowperm, g, dim3(256), 0, st, T, ldT, j0, nj, i0, len, src, ws.tmp1, 0);
-        hipLaunchKernelGGL(k_trowperm, g, dim3(256), 0, st, T, ldT, j0, nj, i0, len, src, ws.tmp1, 1);
+        if (len <= SEG_PERM_LDS) {   // one pass: each T row segment through LDS
+            const int rpw = (int)std::max<int64_t>(1, SEG_PERM_ROWS_LDS / len);
+            const int64_t nwg = (nj + rpw - 1) / rpw;
+            hipLaunchKernelGGL(k_seg_perm, dim3((unsigned)nwg), dim3(256), (size_t)rpw * len * sizeof(double), st, T,
+                               ldT, i0, len, j0, j0 + nj, src, rpw);
+            prof->n_launch += 1;
+        } else {
+            dim3 g(nblk(len), (unsigned)nj);
+            hipLaunchKernelGGL(k_trowperm, g, dim3(256), 0, st, T, ldT, j0, nj, i0, len, src, ws.tmp1, 0);
+            hipLaunchKernelGGL(k_trowperm, g, dim3(256), 0, st, T, ldT, j0, nj, i0, len, src, ws.tmp1, 1);
+            prof->n_launch += 2;
+        }
         prof->end(st);
-        prof->n_launch += 2;
     }
     // idx[a + q] <- idx[a + src[q]]
     void idx_reorder(int32_t* idx, int64_t a, int64_t len, const int32_t* src) {

@@ -22,8 +22,9 @@ constexpr int PS_SPIN = 1 << 20;
 // the slab pivots of the chunks before it and cnt its own: one read gives a
 // waiting chunk everything it needs to fetch the records.  abort_gen equals the
 // generation of an aborted launch.
+constexpr int PS_FLAG_STRIDE = 16;   // flags 128 bytes apart: one cache line each
 struct PsShared {
-    uint64_t flag[PS_MAXCH];
+    uint64_t flag[PS_MAXCH * PS_FLAG_STRIDE];
     int32_t abort_gen;
     int32_t prow[64];
     int32_t pcol[64];
@@ -99,15 +100,15 @@ template <typename T>
 __global__ void k_store_output(T* A, int64_t lda, const double* W, int64_t ld, int64_t n, const double* dd,
                                const double* de, T* e, const int32_t* orig, int32_t* perm, const int32_t* colblk,
                                const int32_t* dinv);
-__global__ void k_perm_below(double* W, int64_t ld, int64_t lo, int64_t s, int64_t hi, int64_t n, const int32_t* sig,
+__global__ void k_seg_perm(double* W, int64_t ld, int64_t lo, int64_t s, int64_t hi, int64_t n, const int32_t* sig,
                              int rpw);
 __global__ void k_dead_snapshot(const int32_t* orig, int64_t d0, int64_t d1, int64_t n, int32_t blk, int32_t* colblk,
                                 int32_t* inv);
 __global__ void k_dead_gather(const double* W, int64_t ld, int64_t n, const int32_t* orig, const int32_t* colblk,
                               const int32_t* dinv, double* tmp);
-// LDS a k_perm_below workgroup may stage (doubles); rows it takes target
-// PERM_BELOW_ROWS_LDS doubles; elements per thread of k_perm_sym
-constexpr int64_t PERM_BELOW_LDS = 8192, PERM_BELOW_ROWS_LDS = 4096;
+// LDS a k_seg_perm workgroup may stage (doubles); rows it takes target
+// SEG_PERM_ROWS_LDS doubles; elements per thread of k_perm_sym
+constexpr int64_t SEG_PERM_LDS = 8192, SEG_PERM_ROWS_LDS = 4096;
 constexpr int PERM_EPT = 4;
 __global__ void k_rpm(const int32_t* orig, const double* de, int64_t n, int64_t r, int32_t* rpm);
 __global__ void k_char2_std(double* W, int64_t ld, int64_t n, double* dd, double* de, int32_t* orig, double* tmp,

@@ -291,10 +291,17 @@ __global__ void k_rot_src(int64_t len, int64_t rot1, int32_t* src) {
 // [i0, i0+ni) (Y rows): phase 0 gathers into tmp, phase 1 copies back.
 __global__ void k_tcolperm(double* T, int64_t ld, int64_t j0, int64_t len, const int32_t* src, int64_t i0,
                            int64_t ni, double* tmp, int phase) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x, q = blockIdx.y;
-    if (i >= ni || q >= len) return;
-    if (phase == 0) tmp[q * ni + i] = T[(j0 + src[q]) * ld + i0 + i];
-    else T[(j0 + q) * ld + i0 + i] = tmp[q * ni + i];
+    const int64_t ib = (int64_t)blockIdx.x * (256 * PERM_EPT) + threadIdx.x, q = blockIdx.y;
+    if (q >= len) return;
+    const double* from = phase == 0 ? T + (j0 + src[q]) * ld + i0 : tmp + q * ni;
+    double* to = phase == 0 ? tmp + q * ni : T + (j0 + q) * ld + i0;
+    double v[PERM_EPT];
+#pragma unroll
+    for (int e = 0; e < PERM_EPT; ++e)
+        if (ib + e * 256 < ni) v[e] = from[ib + e * 256];
+#pragma unroll
+    for (int e = 0; e < PERM_EPT; ++e)
+        if (ib + e * 256 < ni) to[ib + e * 256] = v[e];
 }
 // Reorder T columns i0 .. i0+len (Y rows) by src, within T rows [j0, j0+nj).
 __global__ void k_trowperm(double* T, int64_t ld, int64_t j0, int64_t nj, int64_t i0, int64_t len,
@@ -606,7 +613,7 @@ __device__ __forceinline__ int64_t sigma_at(const int32_t* sig, int64_t q, int64
 // Symmetric permutation of the position range [lo, hi) of W, through tmp:
 // part 0 rows [lo,hi) x cols [c0,lo) (the columns left of the range that are
 // still read later); part 1 the lower block; part 2 rows [hi,n) x cols [lo,hi)
-// (when it is not done in one pass by k_perm_below); part 3 orig.  One flat
+// (when it is not done in one pass by k_seg_perm); part 3 orig.  One flat
 // grid: block b is decoded into (part, row, column block); `dir` 0 gathers into
 // tmp, 1 scatters back.
 __global__ __launch_bounds__(256) void k_perm_sym(double* W, int64_t ld, PermGeom g, const int32_t* sig,
@@ -687,11 +694,12 @@ __global__ __launch_bounds__(256) void k_perm_sym(double* W, int64_t ld, PermGeo
 }
 
 
-// Part 2 of a symmetric permutation in one pass: rows [hi, n) x columns
-// [lo, lo+s), each row segment staged in LDS (rpw rows of s doubles per
-// workgroup) and written back as new[q] = old[sig[q]].  Eight loads in
-// flight per thread.
-__global__ __launch_bounds__(256) void k_perm_below(double* W, int64_t ld, int64_t lo, int64_t s, int64_t hi,
+// The same permutation of one segment of every row, in one pass: rows
+// [hi, n) x columns [lo, lo+s), each row segment staged in LDS (rpw rows of s
+// doubles per workgroup) and written back as new[q] = old[sig[q]].  Part 2 of
+// a symmetric permutation, and PLDUQ's row reorders of its transposed copy.
+// Eight loads in flight per thread.
+__global__ __launch_bounds__(256) void k_seg_perm(double* W, int64_t ld, int64_t lo, int64_t s, int64_t hi,
                                                     int64_t n, const int32_t* sig, int rpw) {
     extern __shared__ double seg[];
     const int64_t r0 = hi + (int64_t)blockIdx.x * rpw;

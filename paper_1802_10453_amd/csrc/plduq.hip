@@ -90,6 +90,7 @@ __global__ __launch_bounds__(PS_THREADS) void k_plduq_slab(PsArgs g) {
     __shared__ int newpos[64];
     __shared__ unsigned long long cmask[PS_CHUNK / 64];
     __shared__ int okw, rtot;
+    __shared__ uint64_t flagw;
 
     const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const Field F = g.F;
@@ -133,11 +134,17 @@ __global__ __launch_bounds__(PS_THREADS) void k_plduq_slab(PsArgs g) {
         if (lane == i) active = false;
     };
 
-    // ---- pivots of the chunks to the left, in order, as they are published
+    // ---- pivots of the chunks to the left, in order, as they are published:
+    // wave 0 polls the flag (one poller per workgroup), the others wait at a barrier
     bool ok = true;
     int base = 0;
     for (int bp = 0; bp < b && ok; ++bp) {
-        const uint64_t fv = ps_wait(&sh->flag[bp], g.gen, &sh->abort_gen, g.hout + 1);
+        if (wave == 0) {
+            const uint64_t fv = ps_wait(&sh->flag[bp * PS_FLAG_STRIDE], g.gen, &sh->abort_gen, g.hout + 1);
+            if (lane == 0) flagw = fv;
+        }
+        __syncthreads();
+        const uint64_t fv = flagw;
         ok = fv != 0;
         if (!ok) break;
         const int bb = __builtin_amdgcn_readfirstlane(flag_base(fv));
@@ -158,8 +165,9 @@ __global__ __launch_bounds__(PS_THREADS) void k_plduq_slab(PsArgs g) {
                 if (s0 + q < bb + bc) apply(__builtin_amdgcn_readfirstlane(ri[q]), rx[q], rf[q]);
         }
         base = bb + bc;
+        __syncthreads();   // flagw is rewritten for the next chunk
     }
-    if (__syncthreads_or(!ok)) return;
+    if (!ok) return;   // (uniform: every wave read the same flag)
 
     // ---- own search: the first active row with a nonzero on a live column, its first such column
     int r = 0;
@@ -204,17 +212,17 @@ __global__ __launch_bounds__(PS_THREADS) void k_plduq_slab(PsArgs g) {
         ++r;
     }
 
-    // ---- publish: records first (every wave's stores released), then the flag
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // ---- publish: the barrier puts every wave's record stores in the (shared)
+    // L2, thread 0's agent-scope release writes them back with the flag
     __syncthreads();
     if (tid == 0) {
         const uint64_t fv = ((uint64_t)(uint32_t)g.gen << 32) | ((uint64_t)base << 8) | (uint64_t)r;
-        __hip_atomic_store(&sh->flag[b], fv, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&sh->flag[b * PS_FLAG_STRIDE], fv, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 
     // ---- every chunk published: final values, final places
     if (tid < 64) {
-        const uint64_t fv = ps_wait(&sh->flag[g.nch - 1], g.gen, &sh->abort_gen, g.hout + 1);
+        const uint64_t fv = ps_wait(&sh->flag[(g.nch - 1) * PS_FLAG_STRIDE], g.gen, &sh->abort_gen, g.hout + 1);
         if (tid == 0) { okw = fv != 0; rtot = flag_base(fv) + flag_cnt(fv); }
     }
     __syncthreads();
