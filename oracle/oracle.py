@@ -63,9 +63,11 @@ def lib():
         L.orc_plduq.argtypes = [_u32, _i64, _i64, _u32p, _i64, _i32p, _i32p, _u32p, _i64,
                                 ctypes.POINTER(_i64)]
         L.orc_delta.argtypes = [_u32, _i64, _u32p, _i64, _u32p, _i64, _u32p]
+        L.orc_det.argtypes = [_u32, _i64, _u32p, _i64, _u32p]
+        L.orc_solve.argtypes = [_u32, _i64, _u32p, _i64, _u32p, _i64, _i64, _u32p, _i64, _i32p]
         for f in ("orc_leading_ranks", "orc_rpm_bruteforce", "orc_search", "orc_replay",
                   "orc_reconstruct", "orc_char2_standard", "orc_gemm", "orc_trsm_left", "orc_syrdk",
-                  "orc_syrd2k", "orc_trss", "orc_plduq", "orc_delta"):
+                  "orc_syrd2k", "orc_trss", "orc_plduq", "orc_delta", "orc_det", "orc_solve"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -214,6 +216,29 @@ def delta(p: int, U, C) -> np.ndarray:
     d = np.zeros(r, dtype=np.uint32)
     assert lib().orc_delta(p, r, U, max(r, 1), C, max(r, 1), d) == 0
     return d
+
+
+def det(A, p: int) -> int:
+    """det(A) mod p by plain elimination (Section 1's uses: invariants of the form)."""
+    A = _sq(A)
+    out = np.zeros(1, dtype=np.uint32)
+    assert lib().orc_det(p, A.shape[0], A, max(A.shape[0], 1), out) == 0
+    return int(out[0])
+
+
+def solve(A, p: int, B):
+    """A X = B by Gauss-Jordan elimination (Section 1's uses: symmetric systems).
+    Returns (X, cons): cons[k] = 1 when column k has a solution."""
+    A = _sq(A)
+    n = A.shape[0]
+    B = _u(B)
+    if B.ndim == 1:
+        B = B.reshape(n, 1)
+    nrhs = B.shape[1]
+    X = np.zeros((n, nrhs), dtype=np.uint32)
+    cons = np.zeros(nrhs, dtype=np.int32)
+    assert lib().orc_solve(p, n, A, max(n, 1), B, max(nrhs, 1), nrhs, X, max(nrhs, 1), cons) == 0
+    return X, cons
 
 
 def effective_ops(n: int, r: int) -> float:

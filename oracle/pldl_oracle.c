@@ -521,3 +521,81 @@ int orc_delta(u32 p, int64_t r, const u32 *U, int64_t ldu, const u32 *C, int64_t
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Determinant: reduce to upper triangular form with row exchanges (each one */
+/* flips the sign); det = sign * product of the pivots.                      */
+int orc_det(u32 p, int64_t n, const u32 *A, int64_t lda, u32 *det) {
+    u32 *W = (u32 *)malloc(sizeof(u32) * (size_t)(n * n > 0 ? n * n : 1));
+    if (!W) return -1;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) W[i * n + j] = A[i * lda + j] % p;
+    u32 d = 1 % p;
+    for (int64_t c = 0; c < n; ++c) {
+        int64_t piv = -1;
+        for (int64_t i = c; i < n; ++i)
+            if (W[i * n + c]) { piv = i; break; }
+        if (piv < 0) { d = 0; break; }
+        if (piv != c) {
+            for (int64_t j = 0; j < n; ++j) { u32 t = W[c * n + j]; W[c * n + j] = W[piv * n + j]; W[piv * n + j] = t; }
+            d = m_sub(0, d, p);
+        }
+        d = m_mul(d, W[c * n + c], p);
+        u32 inv = orc_inv(W[c * n + c], p);
+        #pragma omp parallel for schedule(static)
+        for (int64_t i = c + 1; i < n; ++i) {
+            u32 f = m_mul(W[i * n + c], inv, p);
+            if (!f) continue;
+            for (int64_t j = c; j < n; ++j) W[i * n + j] = m_sub(W[i * n + j], m_mul(f, W[c * n + j], p), p);
+        }
+    }
+    free(W);
+    *det = d;
+    return 0;
+}
+
+/* Solve A X = B: Gauss-Jordan elimination of [A | B] to reduced row echelon */
+/* form (pivot columns found left to right, the first nonzero row below the   */
+/* current one as pivot row), then read each column's solution off it.        */
+int orc_solve(u32 p, int64_t n, const u32 *A, int64_t lda, const u32 *B, int64_t ldb, int64_t nrhs, u32 *X,
+              int64_t ldx, int32_t *cons) {
+    const int64_t w = n + nrhs;
+    u32 *W = (u32 *)malloc(sizeof(u32) * (size_t)(n * w > 0 ? n * w : 1));
+    int64_t *pc = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!W || !pc) { free(W); free(pc); return -1; }
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < n; ++j) W[i * w + j] = A[i * lda + j] % p;
+        for (int64_t k = 0; k < nrhs; ++k) W[i * w + n + k] = B[i * ldb + k] % p;
+    }
+    int64_t r = 0;
+    for (int64_t c = 0; c < n && r < n; ++c) {
+        int64_t piv = -1;
+        for (int64_t i = r; i < n; ++i)
+            if (W[i * w + c]) { piv = i; break; }
+        if (piv < 0) continue;
+        if (piv != r)
+            for (int64_t j = 0; j < w; ++j) { u32 t = W[r * w + j]; W[r * w + j] = W[piv * w + j]; W[piv * w + j] = t; }
+        u32 inv = orc_inv(W[r * w + c], p);
+        for (int64_t j = c; j < w; ++j) W[r * w + j] = m_mul(W[r * w + j], inv, p);
+        #pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            if (i == r) continue;
+            u32 f = W[i * w + c];
+            if (!f) continue;
+            for (int64_t j = c; j < w; ++j) W[i * w + j] = m_sub(W[i * w + j], m_mul(f, W[r * w + j], p), p);
+        }
+        pc[r] = c;
+        ++r;
+    }
+    for (int64_t k = 0; k < nrhs; ++k) {
+        int32_t ok = 1;
+        for (int64_t i = r; i < n; ++i)
+            if (W[i * w + n + k]) { ok = 0; break; }
+        cons[k] = ok;
+        for (int64_t j = 0; j < n; ++j) X[j * ldx + k] = 0;
+        if (ok)
+            for (int64_t i = 0; i < r; ++i) X[pc[i] * ldx + k] = W[i * w + n + k];
+    }
+    free(W); free(pc);
+    return 0;
+}

@@ -139,6 +139,18 @@ int orc_plduq(uint32_t p, int64_t m, int64_t n, const uint32_t *Y, int64_t ldy,
 int orc_delta(uint32_t p, int64_t r, const uint32_t *U, int64_t ldu,
               const uint32_t *C, int64_t ldc, uint32_t *delta);
 
+/* Uses of the factorization named in Section 1 (solving symmetric systems,
+ * invariants of symmetric forms), computed here without it, by plain Gaussian
+ * elimination with row exchanges on the matrix itself.
+ * orc_det: det(A) mod p of the n x n A.
+ * orc_solve: for each of the nrhs columns of B (n x nrhs), cons[k] = 1 when
+ * A x = B[:, k] has a solution (then X[:, k] is the one whose free variables
+ * of the reduced row echelon form of A are 0), else cons[k] = 0 and X[:, k]
+ * = 0.  Returns 0. */
+int orc_det(uint32_t p, int64_t n, const uint32_t *A, int64_t lda, uint32_t *det);
+int orc_solve(uint32_t p, int64_t n, const uint32_t *A, int64_t lda, const uint32_t *B, int64_t ldb,
+              int64_t nrhs, uint32_t *X, int64_t ldx, int32_t *cons);
+
 #ifdef __cplusplus
 }
 #endif

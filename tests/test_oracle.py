@@ -557,3 +557,69 @@ def test_reconstruct_of_search_on_generator_inputs():
                 A, _ = inputs.rank_profile_matrix_input(40, p, 12, 6, 90 + seed)
             f = orc.search(A, p)
             assert (orc.reconstruct(p, f["perm"], f["L"], f["dd"], f["de"]) == A).all()
+
+
+# ---------------------------------------------------------------- uses of the factorization (Section 1)
+@pytest.mark.parametrize("p", [2, 3, 65521, 8388593])
+def test_det_against_independent_elimination(p):
+    g = inputs.rng(77 + p)
+    for t in range(8):
+        n = int(g.integers(1, 14))
+        A = g.integers(0, p, size=(n, n)).astype(np.uint32)
+        if t % 3 == 2 and n > 1:
+            A[n - 1] = A[0]                         # singular
+        assert orc.det(A, p) == det_indep(A, p)
+
+
+def test_det_of_symmetric_generator_inputs_is_det_of_D():
+    """For a full-rank L R L^T, det A = det R (L unit lower): a closed form."""
+    p = 65521
+    for seed in range(3):
+        A, rpm = inputs.rank_profile_matrix_input(24, p, 10, 7, 300 + seed)
+        assert orc.det(A, p) == det_indep(A, p)
+
+
+@pytest.mark.parametrize("p", [3, 65521, 8388593])
+def test_solve_nonsingular_cramer(p):
+    """x_i = det(A with column i replaced by b) / det(A) (Cramer), Python integers."""
+    g = inputs.rng(91 + p)
+    done = 0
+    while done < 5:
+        n = int(g.integers(1, 7))
+        A = g.integers(0, p, size=(n, n)).astype(np.uint32)
+        d = det_indep(A, p)
+        if d == 0:
+            continue
+        b = g.integers(0, p, size=n).astype(np.uint32)
+        X, cons = orc.solve(A, p, b)
+        assert cons[0] == 1
+        dinv = pow(d, p - 2, p)
+        for i in range(n):
+            Ai = A.copy()
+            Ai[:, i] = b
+            assert int(X[i, 0]) == det_indep(Ai, p) * dinv % p
+        done += 1
+
+
+@pytest.mark.parametrize("p", [2, 65521])
+def test_solve_singular_consistency(p):
+    g = inputs.rng(5 + p)
+    for seed in range(4):
+        A, _ = inputs.rank_profile_matrix_input(20, p, 6, 4, 400 + seed)   # rank 14
+        y = g.integers(0, p, size=(20, 3)).astype(np.uint32)
+        B = (A.astype(object) @ y.astype(object)) % p                       # in the range
+        X, cons = orc.solve(A, p, B.astype(np.uint32))
+        assert (cons == 1).all()
+        assert ((A.astype(object) @ X.astype(object)) % p == B).all()
+        # b + e_j leaves the range for some j (A has rank 14 < 20): the rank of [A | b] grows
+        found = False
+        for j in range(20):
+            cand = B[:, 0].astype(np.int64)
+            cand[j] = (cand[j] + 1) % p
+            cand = cand.astype(np.uint32)
+            if orc.rank(np.concatenate([A, cand.reshape(20, 1)], axis=1), p) > 14:
+                Xb, cb = orc.solve(A, p, cand)
+                assert cb[0] == 0
+                found = True
+                break
+        assert found
