@@ -181,6 +181,48 @@ int pldl_char2_to_standard(pldl_ctx *ctx, int64_t n, void *A, int64_t lda, int32
 int pldl_autotune(pldl_ctx *ctx, uint32_t p, const int64_t *n_list, int64_t count, const char *table_path,
                   void *stream);
 
+/* ---------------- uses of a factorization (Section 1) ---------------- */
+
+/*
+ * pldl_solve -- X with A X = B for the symmetric A whose factorization
+ * pldl_factor returned (the introduction names solving symmetric systems as
+ * the first use of the factorization): A = P L D L^T P^T gives
+ * X = P L^{-T} D^+ L^{-1} P^T B, with D^+ inverting D's 1x1 blocks and its 2x2
+ * blocks [[0,c],[c,d]] on the r pivot positions.  For a singular A a column b
+ * has a solution when L^{-1} P^T b vanishes on the n - r non-pivot positions;
+ * the solution returned is the one with L^T P^T x zero there.
+ *  F (lda, dtype), e, perm, rank: pldl_factor's outputs, unchanged (not in the
+ *            characteristic-2 standard form: the relaxed blocks are expected).
+ *  B         device, n x nrhs FP64 residues, leading dimension ldb >= nrhs; in:
+ *            the right-hand sides, out: the solutions (a column without a
+ *            solution is left undefined).
+ *  consistent device int32[nrhs] (may be NULL): 1 if the column has a solution, else 0.
+ * Errors: -1 ctx; -3 n; -4 F; -5 lda; -6 dtype; -7 e; -8 perm; -9 rank outside
+ * [0, n]; -10 B; -11 ldb; -12 nrhs < 0; PLDL_ERANGE for an entry of F >= p.
+ * Synchronises `stream`.
+ */
+int pldl_solve(pldl_ctx *ctx, uint32_t p, int64_t n, const void *F, int64_t lda, int32_t dtype,
+               const void *e, const int32_t *perm, int64_t rank, double *B, int64_t ldb, int64_t nrhs,
+               int32_t *consistent, void *stream);
+
+/*
+ * pldl_invariants -- invariants of the symmetric bilinear form x^T A y read
+ * off its factorization (the introduction's second use: invariants of
+ * symmetric forms, such as the signature).  Over F_p the form is classified by
+ * its rank and, for odd p, by the discriminant of its nondegenerate part
+ * modulo squares (two nondegenerate forms of the same rank are equivalent iff
+ * these agree); in characteristic 2 by its rank and whether it is alternating.
+ *  out (host int64[5]): [0] rank r; [1] det(A) mod p (0 when r < n);
+ *   [2] the product of the determinants of D's blocks (1x1: x; 2x2: -c^2), a
+ *       discriminant of the nondegenerate part; [3] its quadratic character,
+ *       1 (a square) or -1 (p odd; 1 for p = 2); [4] p = 2: 1 if the form is
+ *       alternating (diag(D) = 0, i.e. diag(A) = 0), else 0 (odd p: 0).
+ * Errors: -1 ctx; -3 n; -4 F; -5 lda; -6 dtype; -7 e; -8 rank; -9 out.
+ * Synchronises `stream`.
+ */
+int pldl_invariants(pldl_ctx *ctx, uint32_t p, int64_t n, const void *F, int64_t lda, int32_t dtype,
+                    const void *e, int64_t rank, int64_t *out, void *stream);
+
 /* ---------------- building blocks (Section 3), FP64 residues ---------------- */
 
 /*

@@ -1169,6 +1169,86 @@ int pldl_syrdk_noalloc(pldl_ctx* ctx, uint32_t p, int64_t n, int64_t k, const do
     return PLDL_OK;
 }
 
+int pldl_solve(pldl_ctx* ctx, uint32_t p, int64_t n, const void* F, int64_t lda, int32_t dtype, const void* e,
+               const int32_t* perm, int64_t rank, double* B, int64_t ldb, int64_t nrhs, int32_t* consistent,
+               void* stream) {
+    if (!ctx) return -1;
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (n < 0 || n > 65535) return fail(ctx, -3, "n out of range [0, 65535]");
+    if (n > 0 && !F) return fail(ctx, -4, "F is NULL");
+    if (lda < std::max<int64_t>(1, n)) return fail(ctx, -5, "lda < max(1, n)");
+    if (dtype != PLDL_U32 && dtype != PLDL_F64) return fail(ctx, -6, "unknown dtype");
+    if (n > 0 && !e) return fail(ctx, -7, "e is NULL");
+    if (n > 0 && !perm) return fail(ctx, -8, "perm is NULL");
+    if (rank < 0 || rank > n) return fail(ctx, -9, "rank outside [0, n]");
+    if (nrhs < 0) return fail(ctx, -12, "nrhs < 0");
+    if (n > 0 && nrhs > 0 && !B) return fail(ctx, -10, "B is NULL");
+    if (ldb < std::max<int64_t>(1, nrhs)) return fail(ctx, -11, "ldb < max(1, nrhs)");
+    if (n == 0 || nrhs == 0) return PLDL_OK;
+    hipStream_t st = as_stream(stream);
+    return guarded(ctx, [&]() {
+        ctx->ws.ensure(n);
+        Workspace& ws = ctx->ws;
+        Engine E(ws, st, p, n, 128, &ctx->prof);
+        ctx->setup(E, ctx->path, 0.0);
+        E.itab = ctx->inv_table(p, st);
+        Prof* prof = &ctx->prof;
+        const Field Fl = E.F;
+        dim3 g(nblk(n), (unsigned)n);
+        // L (strict lower part of F) into W, and M^T = (J L J)^T into tmp1 for the L^T solve
+        HIPCHK(hipMemsetAsync(ws.info, 0, sizeof(int32_t) * 4, st));
+        prof->n_launch++;
+        if (dtype == PLDL_U32)
+            LAUNCH(PLDL_CLASS_OTHER, k_load_input<uint32_t>, g, dim3(256), 0, st, (const uint32_t*)F, lda, ws.W, E.ld, n, Fl, ws.info + 2);
+        else
+            LAUNCH(PLDL_CLASS_OTHER, k_load_input<double>, g, dim3(256), 0, st, (const double*)F, lda, ws.W, E.ld, n, Fl, ws.info + 2);
+        LAUNCH(PLDL_CLASS_OTHER, k_solve_revlt, g, dim3(256), 0, st, F, lda, dtype, n, ws.tmp1, E.ld);
+        if (consistent) {
+            LAUNCH(PLDL_CLASS_OTHER, k_fill_i32, dim3(nblk(nrhs)), dim3(256), 0, st, consistent, nrhs, 1);
+        }
+        // column blocks of at most n right-hand sides (two n x nb buffers in tmp2)
+        for (int64_t k0 = 0; k0 < nrhs; k0 += n) {
+            const int64_t nb = std::min(n, nrhs - k0);
+            double* Y = ws.tmp2;
+            double* U = ws.tmp2 + n * nb;
+            dim3 gb(nblk(nb), (unsigned)n);
+            LAUNCH(PLDL_CLASS_OTHER, k_solve_gather, gb, dim3(256), 0, st, B + k0, ldb, perm, n, nb, Y);
+            E.trsm_ll(MatV{Y, nb, 1}, n, nb, MatV{ws.W, E.ld, 1});                  // L^{-1} P^T b
+            LAUNCH(PLDL_CLASS_OTHER, k_solve_dblock, gb, dim3(256), 0, st, Y, n, nb, rank, F, lda, dtype, e, E.itab, Fl,
+                   consistent ? consistent + k0 : nullptr, U);                        // D^+, reversed
+            E.trsm_ll(MatV{U, nb, 1}, n, nb, MatV{ws.tmp1, E.ld, 1});                // (M^T)^{-1} J u = J L^{-T} u
+            LAUNCH(PLDL_CLASS_OTHER, k_solve_scatter, gb, dim3(256), 0, st, U, n, nb, perm, B + k0, ldb);   // x = P w
+        }
+        HIPCHK(hipGetLastError());
+        int32_t* h = E.read_info(3);
+        if (h[2]) throw Err(PLDL_ERANGE, "an entry of the factorization is not in [0, p)");
+    });
+}
+
+int pldl_invariants(pldl_ctx* ctx, uint32_t p, int64_t n, const void* F, int64_t lda, int32_t dtype, const void* e,
+                    int64_t rank, int64_t* out, void* stream) {
+    if (!ctx) return -1;
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (n < 0 || n > 65535) return fail(ctx, -3, "n out of range [0, 65535]");
+    if (n > 0 && !F) return fail(ctx, -4, "F is NULL");
+    if (lda < std::max<int64_t>(1, n)) return fail(ctx, -5, "lda < max(1, n)");
+    if (dtype != PLDL_U32 && dtype != PLDL_F64) return fail(ctx, -6, "unknown dtype");
+    if (n > 0 && !e) return fail(ctx, -7, "e is NULL");
+    if (rank < 0 || rank > n) return fail(ctx, -8, "rank outside [0, n]");
+    if (!out) return fail(ctx, -9, "out is NULL");
+    hipStream_t st = as_stream(stream);
+    return guarded(ctx, [&]() {
+        ctx->ws.ensure(std::max<int64_t>(n, 1));
+        Prof* prof = &ctx->prof;
+        int64_t* dout = reinterpret_cast<int64_t*>(ctx->ws.info + 16);   // 8-byte aligned words of info
+        LAUNCH(PLDL_CLASS_OTHER, k_invariants, dim3(1), dim3(1024), 0, st, F, lda, dtype, e, n, rank, make_field(p), dout);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(out + 1, dout, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        out[0] = rank;
+    });
+}
+
 int pldl_trss(pldl_ctx* ctx, uint32_t p, int64_t n, const double* U, int64_t ldu, const double* C, int64_t ldc,
               double* X, int64_t ldx, void* stream) {
     if (!ctx) return -1;

@@ -126,6 +126,16 @@ __global__ void k_trss_unpack(const double* W, int64_t ldw, int64_t n, double* X
 template <typename T>
 __global__ void k_load_factors(const double* W, int64_t ld, int64_t n, const T* e, const int32_t* perm, double* dd,
                                double* de, int32_t* orig);
+// consumers.hip: solving with and reading invariants off a finished factorization
+__global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v);
+__global__ void k_solve_gather(const double* B, int64_t ldb, const int32_t* perm, int64_t n, int64_t nrhs, double* Y);
+__global__ void k_solve_dblock(const double* Y, int64_t n, int64_t nrhs, int64_t r, const void* Fd, int64_t lda,
+                               int32_t dtype, const void* e, const uint32_t* itab, Field F, int32_t* cons, double* U);
+__global__ void k_solve_revlt(const void* Fd, int64_t lda, int32_t dtype, int64_t n, double* Mt, int64_t ldm);
+__global__ void k_solve_scatter(const double* Wt, int64_t n, int64_t nrhs, const int32_t* perm, double* B,
+                                int64_t ldb);
+__global__ void k_invariants(const void* Fd, int64_t lda, int32_t dtype, const void* e, int64_t n, int64_t r, Field F,
+                             int64_t* out);
 __global__ void k_fill_uniform_sym(double* A, int64_t n, uint32_t p, uint64_t seed);
 __global__ void k_fill_unit_lower(double* L, int64_t n, uint32_t p, uint64_t seed);
 __global__ void k_fill_neg_rlt(double* B, const double* L, int64_t n, const int32_t* rpm, const double* scale, Field F);

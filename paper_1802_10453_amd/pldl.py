@@ -63,6 +63,8 @@ _lib.pldl_factor.argtypes = [_vp, _u32, _i64, _vp, _i64, _i32, _vp, _vp, _vp, ct
 _lib.pldl_gemm.argtypes = [_vp, _u32, _i64, _i64, _i64, _vp, _i64, _i32, _vp, _i64, _i32, _vp, _i64, _i32, _vp]
 _lib.pldl_trsm.argtypes = [_vp, _u32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp]
 _lib.pldl_syrdk.argtypes = [_vp, _u32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _i64, _vp]
+_lib.pldl_solve.argtypes = [_vp, _u32, _i64, _vp, _i64, _i32, _vp, _vp, _i64, _vp, _i64, _i64, _vp, _vp]
+_lib.pldl_invariants.argtypes = [_vp, _u32, _i64, _vp, _i64, _i32, _vp, _i64, ctypes.POINTER(_i64), _vp]
 _lib.pldl_syrdk_noalloc.argtypes = [_vp, _u32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _i64, _vp]
 _lib.pldl_trss.argtypes = [_vp, _u32, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]
 _lib.pldl_plduq.argtypes = [_vp, _u32, _i64, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(_i64), _vp]
@@ -72,13 +74,15 @@ _lib.pldl_char2_to_standard.argtypes = [_vp, _i64, _vp, _i64, _i32, _vp, _vp, _v
 _lib.pldl_autotune.argtypes = [_vp, _u32, ctypes.POINTER(_i64), _i64, ctypes.c_char_p, _vp]
 _lib.pldl_factor_batched.argtypes = [_vp, _u32, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
                                      ctypes.POINTER(pldl_opts), _vp]
-for _f in ("pldl_create", "pldl_destroy", "pldl_factor", "pldl_gemm", "pldl_trsm", "pldl_syrdk", "pldl_syrdk_noalloc",
+for _f in ("pldl_create", "pldl_destroy", "pldl_factor", "pldl_solve", "pldl_invariants", "pldl_gemm", "pldl_trsm",
+           "pldl_syrdk", "pldl_syrdk_noalloc",
            "pldl_trss",
            "pldl_plduq", "pldl_profile", "pldl_set_path", "pldl_factor_batched", "pldl_char2_to_standard",
            "pldl_autotune"):
     getattr(_lib, _f).restype = ctypes.c_int
 
-EXPORTED = ("pldl_create", "pldl_destroy", "pldl_last_error", "pldl_factor", "pldl_gemm", "pldl_trsm",
+EXPORTED = ("pldl_create", "pldl_destroy", "pldl_last_error", "pldl_factor", "pldl_solve", "pldl_invariants",
+            "pldl_gemm", "pldl_trsm",
             "pldl_syrdk", "pldl_syrdk_noalloc", "pldl_trss", "pldl_plduq", "pldl_profile", "pldl_set_path", "pldl_factor_batched",
             "pldl_char2_to_standard", "pldl_autotune")
 
@@ -158,6 +162,26 @@ class Context:
                               ctypes.byref(rank), ctypes.byref(o), ctypes.byref(sc), _stream())
         self._check(rc)
         return dict(perm=perm[:n], rpm=rpm[:n], e=e[:n], rank=int(rank.value), schedule=sc.as_dict())
+
+    def solve(self, p: int, F: torch.Tensor, e: torch.Tensor, perm: torch.Tensor, rank: int, B: torch.Tensor):
+        """pldl_solve on pldl_factor's outputs: B (n x nrhs float64) overwritten by X.
+        Returns the per-column consistency flags (int32 tensor)."""
+        n = F.shape[0]
+        dt = PLDL_U32 if F.dtype == torch.int32 else PLDL_F64
+        assert B.dtype == torch.float64 and B.dim() == 2 and B.shape[0] == n
+        cons = torch.zeros(max(B.shape[1], 1), dtype=torch.int32, device=B.device)
+        self._check(_lib.pldl_solve(self._h, int(p), n, _ptr(F), _ld(F) if n else 1, dt, _ptr(e), _ptr(perm),
+                                    int(rank), _ptr(B), _ld(B), B.shape[1], _ptr(cons), _stream()))
+        return cons[:B.shape[1]]
+
+    def invariants(self, p: int, F: torch.Tensor, e: torch.Tensor, rank: int) -> dict:
+        """pldl_invariants: rank, det, discriminant, its quadratic character, alternating flag."""
+        n = F.shape[0]
+        dt = PLDL_U32 if F.dtype == torch.int32 else PLDL_F64
+        out = (_i64 * 5)()
+        self._check(_lib.pldl_invariants(self._h, int(p), n, _ptr(F), _ld(F) if n else 1, dt, _ptr(e), int(rank),
+                                         out, _stream()))
+        return dict(rank=out[0], det=out[1], disc=out[2], character=out[3], alternating=out[4])
 
     def char2_to_standard(self, A: torch.Tensor, e: torch.Tensor, perm: torch.Tensor):
         """pldl_char2_to_standard on pldl_factor's outputs (p = 2), in place."""
