@@ -24,8 +24,8 @@
 //
 // Chain.  Workgroup b loads its chunk into registers (lane = slab row, each
 // wave PS_CPW columns), applies the pivots of chunks 0 .. b-1 in order as they
-// are published (no barrier: wave shuffles only), searches its own chunk (two
-// workgroup barriers per pivot), then publishes its pivots (slab row, column,
+// are published (no barrier: wave shuffles only), searches its own chunk (one
+// workgroup barrier per pivot), then publishes its pivots (slab row, column,
 // x, and the scaled pivot column of multipliers) and raises its flag.  Once
 // the last chunk has published, every workgroup writes its chunk to its final
 // place: pivot rows first in pivot order, then the other rows in their previous
@@ -38,6 +38,8 @@
 // PS_MAXCH workgroups, one per compute unit suffices).  Each wait is bounded:
 // after PS_SPIN polls a wave marks the launch aborted, every waiting wave
 // leaves, and the host reports the error instead of hanging.
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace pldl {
@@ -80,10 +82,8 @@ __device__ __forceinline__ int flag_cnt(uint64_t v) { return (int)(v & 0xff); }
 __global__ __launch_bounds__(PS_THREADS) void k_plduq_slab(PsArgs g) {
     constexpr int CPW = PS_CPW, NW = PS_THREADS / 64;
     static_assert(NW * CPW == PS_CHUNK && CPW <= 32, "chunk geometry");
-    __shared__ unsigned long long wmask[NW];
-    __shared__ int wfirst[NW][64];
-    __shared__ double pf_l[64];
-    __shared__ double px_l;
+    __shared__ int offer[2][NW];
+    __shared__ double offer_col[2][NW][64];
     __shared__ int colpiv[PS_CHUNK];     // chunk column -> slab pivot index (-1: none)
     __shared__ int rowpiv[64];           // slab row -> slab pivot index (-1: none)
     __shared__ double xinv_l[64], dval_l[64];
@@ -120,19 +120,28 @@ __global__ __launch_bounds__(PS_THREADS) void k_plduq_slab(PsArgs g) {
     bool active = lane < m;
     uint32_t live = nw >= 32 ? 0xffffffffu : ((1u << nw) - 1u);
 
-    // eliminate the active rows other than i with pivot (i, x) and scaled column f (this lane's row)
-    auto apply = [&](int i, double x, double f) {
+    // eliminate the active rows other than i with pivot (i, x) and scaled column f (this lane's row).
+    // A row left as it is takes x = 1, f = 0: 1 * y - 0 * u = y, which the reduction keeps
+    // (y is a reduced centered residue).  The live-column mask is the same in every lane
+    // of the wave, so the column tests are scalar branches.
+    // all_live: no column of the chunk is a pivot column yet (the pivots of the chunks to
+    // the left), so every column is updated (the padding columns past the edge hold 0
+    // in every row and stay 0).
+    auto apply = [&](int i, double x, double f, auto all_live) {
         const bool upd = active && lane != i;
+        const double xl = upd ? x : 1.0, fl = upd ? f : 0.0;
+        const uint32_t lv = __builtin_amdgcn_readfirstlane(live);
 #pragma unroll
         for (int k = 0; k < CPW; ++k) {
-            if ((live >> k) & 1u) {
+            if (decltype(all_live)::value || __builtin_expect((lv >> k) & 1u, 1u)) {
                 const double u = rdlane(y[k], i);
-                const double t = fredc(fma(x, y[k], -f * u), F);
-                y[k] = upd ? t : y[k];
+                y[k] = fredc(fma(xl, y[k], -fl * u), F);
             }
         }
         if (lane == i) active = false;
     };
+    using AllLive = std::true_type;
+    using SomeDead = std::false_type;
 
     // ---- pivots of the chunks to the left, in order, as they are published:
     // wave 0 polls the flag (one poller per workgroup), the others wait at a barrier
@@ -162,54 +171,60 @@ __global__ __launch_bounds__(PS_THREADS) void k_plduq_slab(PsArgs g) {
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                if (s0 + q < bb + bc) apply(__builtin_amdgcn_readfirstlane(ri[q]), rx[q], rf[q]);
+                if (s0 + q < bb + bc) apply(__builtin_amdgcn_readfirstlane(ri[q]), rx[q], rf[q], AllLive{});
         }
         base = bb + bc;
         __syncthreads();   // flagw is rewritten for the next chunk
     }
     if (!ok) return;   // (uniform: every wave read the same flag)
 
-    // ---- own search: the first active row with a nonzero on a live column, its first such column
+    // ---- own search: the first active row with a nonzero on a live column, its first such
+    // column.  Each wave offers a candidate (its first such row, that row's first such
+    // column among the wave's columns, packed row << 16 | column, and the column's values
+    // in every row); the smallest packed value wins, so one barrier per pivot suffices.
+    // The offers are double-buffered: a wave that runs ahead writes the other buffer.
     int r = 0;
-    for (;;) {
+    for (;; ++r) {
+        const int ob = r & 1;
+        const uint32_t lv = __builtin_amdgcn_readfirstlane(live);
         uint32_t nzb = 0;
 #pragma unroll
-        for (int k = 0; k < CPW; ++k) nzb |= (((live >> k) & 1u) && y[k] != 0.0) ? (1u << k) : 0u;
+        for (int k = 0; k < CPW; ++k) nzb |= (((lv >> k) & 1u) && y[k] != 0.0) ? (1u << k) : 0u;
         if (!active) nzb = 0;
         const unsigned long long bal = __ballot(nzb != 0);
-        if (lane == 0) wmask[wave] = bal;
-        wfirst[wave][lane] = nzb ? wave * CPW + __ffs(nzb) - 1 : 0x7fffffff;
-        __syncthreads();
-        unsigned long long M = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) M |= wmask[w];
-        if (M == 0) break;
-        const int i = __ffsll((long long)M) - 1;
-        int c = 0x7fffffff;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) c = min(c, wfirst[w][i]);
-        const int wo = c / CPW, ko = c - wo * CPW;
-        const int s = base + r;
-        if (wave == wo) {
+        int cw = 0x7fffffff;
+        if (bal) {
+            const int iw = __ffsll((long long)bal) - 1;
+            const int kw = __ffs(__builtin_amdgcn_readlane((int)nzb, iw)) - 1;
+            cw = (iw << 16) | (wave * CPW + kw);
             double v = 0.0;
 #pragma unroll
-            for (int k = 0; k < CPW; ++k) v = (k == ko) ? y[k] : v;
-            const double x = rdlane(v, i);
-            const double f = (active && lane != i) ? v : 0.0;
-            pf_l[lane] = f;
-            sh->pf[s * 64 + lane] = f;
+            for (int k = 0; k < CPW; ++k) v = (k == kw) ? y[k] : v;
+            offer_col[ob][wave][lane] = v;
+        }
+        if (lane == 0) offer[ob][wave] = cw;
+        __syncthreads();
+        int best = 0x7fffffff;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) best = min(best, offer[ob][w]);
+        if (best == 0x7fffffff) break;
+        const int i = best >> 16, c = best & 0xffff;
+        const int wo = c / CPW, ko = c - wo * CPW;
+        const double x = offer_col[ob][wo][i];
+        const double fv = offer_col[ob][wo][lane];
+        const double f = (active && lane != i) ? fv : 0.0;
+        const int sp = base + r;
+        if (wave == wo) {
+            sh->pf[sp * 64 + lane] = f;
             if (lane == 0) {
-                px_l = x;
-                sh->px[s] = x;
-                sh->prow[s] = i;
-                sh->pcol[s] = (int32_t)(cb + c);
-                colpiv[c] = s;
+                sh->px[sp] = x;
+                sh->prow[sp] = i;
+                sh->pcol[sp] = (int32_t)(cb + c);
+                colpiv[c] = sp;
             }
             live &= ~(1u << ko);   // the column keeps D (row i), multipliers (active rows), U (pivot rows)
         }
-        __syncthreads();
-        apply(i, px_l, pf_l[lane]);
-        ++r;
+        apply(i, x, f, SomeDead{});
     }
 
     // ---- publish: the barrier puts every wave's record stores in the (shared)
