@@ -94,10 +94,8 @@ struct GemmSeg {
 };
 // C (row-major, ldc) <- C - sum_seg A_seg B_seg   (mod p)
 //   lower_c: only entries j <= i of C (m == n);  b_upper: B[t][j] taken as 0 for t > j (segment 0)
-//   nzrow (optional): atomicMin(nzrow, nzoff + index of the first row of C holding a nonzero result)
 void launch_gemm(hipStream_t s, const Field& F, int64_t m, int64_t n, double* C, int64_t ldc,
-                 const GemmSeg* segs, int nseg, bool lower_c, bool b_upper, int32_t* nzrow = nullptr,
-                 int32_t nzoff = 0, Stamp stamp = Stamp{});
+                 const GemmSeg* segs, int nseg, bool lower_c, bool b_upper, Stamp stamp = Stamp{});
 
 // The same product on the INT8 matrix cores with residues split into signed
 // bytes (gemm_i8.hip), in two launches: i8_prepare writes the operands' limb

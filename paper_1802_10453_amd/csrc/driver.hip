@@ -250,8 +250,10 @@ struct Workspace {
             }
         if (hipMalloc((void**)&info, 1024 * sizeof(int32_t)) != hipSuccess) { release(); throw Err(PLDL_ENOMEM, "alloc"); }
         // snapshot stack: 3 segments of at most m entries per row-split level (<= 11 levels
-        // for m <= 65535), then the scratch (inverse map and source, m + 64 each)
-        ipool_len = 40 * (m + 64);
+        // for m <= 65535), the orig snapshots of the ranges that move the rows under them
+        // at their end (at most 2m along one recursion path), then the scratch (inverse
+        // map and source, m + 64 each)
+        ipool_len = 44 * (m + 64);
         ipool_scratch_len = 2 * (m + 64);
         if (hipMalloc((void**)&ipool, (ipool_len + ipool_scratch_len) * sizeof(int32_t)) != hipSuccess) {
             release();
@@ -360,14 +362,14 @@ struct Engine {
             const double tri = nc <= k0 ? nc * (nc + 1) / 2.0 : k0 * (k0 + 1) / 2.0 + (nc - k0) * k0;
             flops -= 2.0 * (double)m * (nc * k0 - tri);
         }
-        mm(C, ld, m, nn, segs, 2, lower, b_upper, nullptr, 0, flops);
+        mm(C, ld, m, nn, segs, 2, lower, b_upper, flops);
     }
-    // one product on the selected matrix cores (INT8 split needs no first-nonzero detection)
+    // one product on the selected matrix cores
     // (the limb split is timed as class OTHER, the INT8 product as class GEMM).  flops: the
     // useful work recorded by the profile (structural zeros of a triangular operand left
     // out); the path is chosen on the work the matrix cores do (every product of the tiles).
     void mm(double* C, int64_t ldc, int64_t m, int64_t nn, const GemmSeg* segs, int nseg, bool lower, bool b_upper,
-            int32_t* nzrow, int32_t nzoff, double flops) {
+            double flops) {
         double opnd = 0.0;   // operand elements, each read once
         double ksum = 0.0;
         for (int q = 0; q < nseg; ++q)
@@ -376,7 +378,7 @@ struct Engine {
                 ksum += (double)segs[q].k;
             }
         const double outs = lower ? (double)m * (double)(m + 1) / 2.0 : (double)m * (double)nn;
-        if (path == PLDL_PATH_I8 && !nzrow && 2.0 * outs * ksum >= i8_min_flops) {
+        if (path == PLDL_PATH_I8 && 2.0 * outs * ksum >= i8_min_flops) {
             if (i8->ensure(i8_workspace_bytes((uint32_t)F.ip, m, nn, segs, nseg), st)) prof->n_wait++;
             I8Product pr;
             prof->begin(st, PLDL_CLASS_OTHER);
@@ -395,7 +397,7 @@ struct Engine {
             }
         }
         const Stamp sp = prof->begin(st, PLDL_CLASS_GEMM, flops, 8.0 * opnd + 16.0 * outs);
-        launch_gemm(st, F, m, nn, C, ldc, segs, nseg, lower, b_upper, nzrow, nzoff, sp);
+        launch_gemm(st, F, m, nn, C, ldc, segs, nseg, lower, b_upper, sp);
         prof->end(st);
         prof->n_launch++;
         prof->n_f64++;
@@ -417,30 +419,36 @@ struct Engine {
         dead_upto = upto;
     }
     // Symmetric permutation of [lo, hi): new lo+q <- old lo+sig[q].
-    // parts: 1 = rows x [al, lo), 2 = block, 4 = rows below x range, 8 = orig.
+    // parts: 1 = rows x [al, lo), 2 = block, 4 = rows [hi, below) x range, 8 = orig.
     // al: the first column left of the range that a later step still reads
     // (AL_NONE: none of them; every column left of min(al, lo) stops moving).
-    void perm_sym(int64_t lo, int64_t hi, const int32_t* sig, int parts, int64_t al) {
+    // below: the rows under the range that take the new column order now; the
+    // rows past it take it later, composed with the enclosing range's own order
+    // (see recall).
+    int64_t n_perms = 0;   // symmetric permutations applied so far
+    void perm_sym(int64_t lo, int64_t hi, const int32_t* sig, int parts, int64_t al, int64_t below) {
         const int64_t s = hi - lo;
         if (s <= 1) return;
+        REQUIRE(below >= hi && below <= n);
+        ++n_perms;
         REQUIRE(lo >= 0 && hi <= n && sig);
         REQUIRE(lo >= dead_upto);   // no stopped column lies in a range that still moves
         const int64_t c0 = (parts & 1) ? (track_dead ? std::min(std::max<int64_t>(al, 0), lo) : 0) : lo;
         if (parts & 1) stop_columns(c0);
         // rows below in one pass through LDS when a row segment fits
-        const bool below1 = (parts & 4) && n > hi && s <= SEG_PERM_LDS;
+        const bool below1 = (parts & 4) && below > hi && s <= SEG_PERM_LDS;
         PermGeom g{};
         g.n = n; g.lo = lo; g.hi = hi; g.s = s; g.c0 = c0; g.parts = parts;
         g.nb0 = nblk(std::max<int64_t>(lo - c0, 1), 256 * PERM_EPT);
         g.nb1 = nblk(s, 256 * PERM_EPT);
         g.B0 = ((parts & 1) && lo > c0) ? s * g.nb0 : 0;
         g.B1 = (parts & 2) ? s * g.nb1 : 0;
-        g.B2 = ((parts & 4) && n > hi && !below1) ? (n - hi) * g.nb1 : 0;
+        g.B2 = ((parts & 4) && below > hi && !below1) ? (below - hi) * g.nb1 : 0;
         g.B3 = (parts & 8) ? g.nb1 : 0;
         const int64_t blocks = g.B0 + g.B1 + g.B2 + g.B3;
         REQUIRE(blocks < ((int64_t)1 << 31));
         double elems = (double)(g.B0 ? s * (lo - c0) : 0) + (double)(g.B1 ? s * (s + 1) / 2 : 0) +
-                       (double)(((parts & 4) && n > hi) ? s * (n - hi) : 0);
+                       (double)(((parts & 4) && below > hi) ? s * (below - hi) : 0);
         if (elems == 0.0 && blocks == 0) return;
         prof->begin(st, PLDL_CLASS_PERM, 0.0, 16.0 * elems);
         if (blocks > 0) {
@@ -450,10 +458,10 @@ struct Engine {
         }
         if (below1) {
             const int rpw = (int)std::max<int64_t>(1, SEG_PERM_ROWS_LDS / s);
-            const int64_t nwg = (n - hi + rpw - 1) / rpw;
+            const int64_t nwg = (below - hi + rpw - 1) / rpw;
             REQUIRE(nwg < ((int64_t)1 << 31));
             hipLaunchKernelGGL(k_seg_perm, dim3((unsigned)nwg), dim3(256), (size_t)rpw * s * sizeof(double), st, W, ld,
-                               lo, s, hi, n, sig, rpw);
+                               lo, s, hi, below, sig, rpw);
             prof->n_launch += 1;
         }
         prof->end(st);
@@ -486,7 +494,7 @@ struct Engine {
     }
     void trsm_ru_rec(MatV B, int64_t m, int64_t r, MatV T, double* Nb) {
         if (r <= 64) {   // B <- B - B N (N strictly upper: column j sums j products)
-            gemm_ld(B.p, B.rs, m, r, GemmSeg{MatV{B.p, B.rs, 1}, MatV{Nb, 64, 1}, r}, nullptr, 0,
+            gemm_ld(B.p, B.rs, m, r, GemmSeg{MatV{B.p, B.rs, 1}, MatV{Nb, 64, 1}, r},
                     (double)m * (double)r * (double)(r - 1));
             return;
         }
@@ -510,7 +518,7 @@ struct Engine {
     }
     void trsm_ll_rec(MatV B, int64_t r, int64_t ncols, MatV T, double* Nb) {
         if (r <= 64) {   // B <- B - N B (N strictly lower: row i sums i products)
-            gemm_ld(B.p, B.rs, r, ncols, GemmSeg{MatV{Nb, 64, 1}, MatV{B.p, B.rs, 1}, r}, nullptr, 0,
+            gemm_ld(B.p, B.rs, r, ncols, GemmSeg{MatV{Nb, 64, 1}, MatV{B.p, B.rs, 1}, r},
                     (double)ncols * (double)r * (double)(r - 1));
             return;
         }
@@ -536,15 +544,15 @@ struct Engine {
         ws.tinv_rows = rows;
     }
     // flops < 0: the dense count 2 m nn k (else the useful flops of a structured operand)
-    void gemm_ld(double* C, int64_t ldc, int64_t m, int64_t nn, GemmSeg s0, int32_t* nzrow = nullptr, int32_t nzoff = 0,
-                 double flops = -1.0) {
+    void gemm_ld(double* C, int64_t ldc, int64_t m, int64_t nn, GemmSeg s0, double flops = -1.0) {
         if (m <= 0 || nn <= 0 || s0.k <= 0) return;
-        mm(C, ldc, m, nn, &s0, 1, false, false, nzrow, nzoff,
+        mm(C, ldc, m, nn, &s0, 1, false, false,
            flops >= 0.0 ? flops : 2.0 * (double)m * (double)nn * (double)s0.k);
     }
 
     // ---- base case (Section 5) ------------------------------------------------
-    int64_t bc(int64_t lo, int64_t hi, int64_t al) {
+    // below: the rows under the range that take its column order now (see recall)
+    int64_t bc(int64_t lo, int64_t hi, int64_t al, int64_t below) {
         int s = (int)(hi - lo);
         REQUIRE(s >= 1 && s <= 128);
         LAUNCH(PLDL_CLASS_BASE_CASE, k_bc_leaf, dim3(1), dim3(BC_THREADS), 0, st, W, ld, lo, s, F, itab, ws.dd, ws.de, ws.sig,
@@ -553,7 +561,7 @@ struct Engine {
         int64_t r = h[0];
         bool ident = true;
         for (int q = 0; q < s; ++q) ident &= (h[1 + q] == q);
-        if (!ident) perm_sym(lo, hi, ws.sig, 1 | 4 | 8, al);
+        if (!ident) perm_sym(lo, hi, ws.sig, 1 | 4 | 8, al, below);
         return r;
     }
 
@@ -563,13 +571,29 @@ struct Engine {
     // TRSM and GEMM read that half's L block once the half is done); AL_NONE
     // when there is none.  The first half of this range inherits min(al, lo);
     // the second part inherits al (this range reads nothing after it).
-    int64_t recall(int64_t lo, int64_t hi, int64_t al) {
+    //
+    // below: the rows under the range that must hold its columns in their final
+    // order when it returns.  A range with al != AL_NONE moves the rows under it
+    // only once, at its end: its permutations update the rows inside it at once
+    // and leave the rows in [hi, below) alone, and its end applies the order of
+    // its columns relative to its start (from a snapshot of orig) to those rows.
+    // This is sound because no step inside the range reads rows below hi, and
+    // no column of the range stops moving meanwhile (every permutation inside
+    // keeps the columns from min(al, ...) <= al <= lo on moving).  A range with
+    // al == AL_NONE updates every row under its permutations at once (its own
+    // steps stop columns inside it).
+    int64_t recall(int64_t lo, int64_t hi, int64_t al, int64_t below) {
         int64_t N = hi - lo;
         if (N <= 0) return 0;
-        if (N <= t_leaf) return bc(lo, hi, al);
+        if (N <= t_leaf) return bc(lo, hi, al, below);
+        const bool defer = al != AL_NONE && below > hi;
+        const int64_t inner = al == AL_NONE ? n : hi;   // bound the parts of this range pass down
+        const int64_t ip_save = ip_top;
+        const int32_t* snap = defer ? snapshot(ws.orig + lo, N) : nullptr;
+        const int64_t perms0 = n_perms;
         int64_t m = N / 2;
         if (m >= 128) m = m / 64 * 64;
-        int64_t r1 = recall(lo, lo + m, std::min(al, lo));
+        int64_t r1 = recall(lo, lo + m, std::min(al, lo), inner);
         int64_t s = lo + m, n2 = hi - s;
         if (r1 > 0 && n2 > 0) {
             chk(s, lo, n2, m);
@@ -584,13 +608,17 @@ struct Engine {
             // SYRDK: Z = C - G D1 G^T = lower(C - G X)
             gemm(W + s * ld + s, n2, n2, GemmSeg{vrow(s, lo), MatV{ws.tmp2, 1, r1}, r1}, GemmSeg{MatV{nullptr, 0, 1}, MatV{nullptr, 0, 1}, 0}, true);
         }
-        return r1 + zlp(lo + r1, m - r1, hi, al);
+        const int64_t r = r1 + zlp(lo + r1, m - r1, hi, al, inner);
+        if (defer && n_perms != perms0) perm_sym(lo, hi, reorder_src(snap, ws.orig + lo, N), 4, al, below);
+        ip_top = ip_save;
+        return r;
     }
 
     // ---- Algorithm 3 -----------------------------------------------------------
-    int64_t zlp(int64_t lo, int64_t mz, int64_t hi, int64_t al) {
+    // below: as in recall, for the rows under hi (the enclosing recall's bound)
+    int64_t zlp(int64_t lo, int64_t mz, int64_t hi, int64_t al, int64_t below) {
         int64_t s0 = lo + mz, nc = hi - s0;
-        if (mz == 0) return recall(lo, hi, al);
+        if (mz == 0) return recall(lo, hi, al, below);
         if (nc == 0) return 0;
         // PLDUQ of Y on a compact copy of Y^T; then C' = Q C Q^T and the pack back into W
         REQUIRE(nc <= 65535 && mz <= 65535);
@@ -600,7 +628,7 @@ struct Engine {
         LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(nc)), dim3(256), 0, st, pC, nc);
         int64_t rY = plduq_t(0, mz, 0, nc);
         if (rY > 0) {
-            perm_sym(s0, hi, pC, 2, al);
+            perm_sym(s0, hi, pC, 2, al, hi);
             LAUNCH(PLDL_CLASS_OTHER, k_copy2d, dim3(nblk(mz), (unsigned)nc), dim3(256), 0, st, W + s0 * ld + lo, ld, T, mz, nc, mz);
         }
         int64_t nz = nc - rY, nr = mz - rY, N = hi - lo;
@@ -658,15 +686,15 @@ struct Engine {
             LAUNCH(PLDL_CLASS_OTHER, k_zlp_sigma_total, dim3(nblk(N)), dim3(256), 0, st, ws.sig, mz, nc, rY, pR, pC);
         else
             LAUNCH(PLDL_CLASS_OTHER, k_zlp_sigma, dim3(nblk(N)), dim3(256), 0, st, ws.sig, mz, nc, rY);
-        perm_sym(lo, hi, ws.sig, 1 | 4 | 8, al);
+        perm_sym(lo, hi, ws.sig, 1 | 4 | 8, al, below);
         if (rY > 0)
             LAUNCH(PLDL_CLASS_OTHER, k_zlp_orig_d, dim3(nblk(N)), dim3(256), 0, st, ws.orig, ws.tmpo, lo, mz, hi, rY, W, ld, delta, ws.dd, ws.de, 2);
-        int64_t rz = recall(lo + 2 * rY, lo + 2 * rY + nz, al);
+        int64_t rz = recall(lo + 2 * rY, lo + 2 * rY + nz, al, below);
         // non-pivots of Z and of the zero block, merged by original index
         int64_t a = lo + 2 * rY + rz, n1 = nz - rz;
         if (n1 > 0 && nr > 0) {
             LAUNCH(PLDL_CLASS_OTHER, k_sigma_merge, dim3(nblk(n1 + nr)), dim3(256), 0, st, ws.orig, a, n1, nr, ws.sig);
-            perm_sym(a, hi, ws.sig, 1 | 4 | 8, al);
+            perm_sym(a, hi, ws.sig, 1 | 4 | 8, al, below);
         }
         return 2 * rY + rz;
     }
@@ -1017,7 +1045,7 @@ int pldl_factor(pldl_ctx* ctx, uint32_t p, int64_t n, void* A, int64_t lda, int3
         HIPCHK(hipMemsetAsync(ws.colblk, 0xFF, sizeof(int32_t) * n, st));
         prof->n_launch += 3;
         E.track_dead = true;
-        int64_t r = E.recall(0, n, AL_NONE);
+        int64_t r = E.recall(0, n, AL_NONE, n);
         const bool gathered = E.dead_blocks > 0;
         LAUNCH(PLDL_CLASS_OTHER, k_rpm, dim3(nblk(n)), dim3(256), 0, st, ws.orig, ws.de, n, r, rpm);
         if (o.standard_form && p == 2) {
@@ -1067,7 +1095,7 @@ int pldl_gemm(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, int64_t k, const 
         Engine E(ctx->ws, st, p, 0, 128, &ctx->prof);
         ctx->setup(E, ctx->path, 0.0);
         double outs = lower_only ? (double)m * (double)(m + 1) / 2.0 : (double)m * (double)n;
-        if (m > 0 && n > 0 && k > 0) E.mm(C, ldc, m, n, &s, 1, lower_only != 0, false, nullptr, 0, 2.0 * outs * (double)k);
+        if (m > 0 && n > 0 && k > 0) E.mm(C, ldc, m, n, &s, 1, lower_only != 0, false, 2.0 * outs * (double)k);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
     });
@@ -1126,7 +1154,7 @@ int pldl_syrdk(pldl_ctx* ctx, uint32_t p, int64_t n, int64_t k, const double* A,
         GemmSeg segs[2] = {s0, s1};
         Engine E(ctx->ws, st, p, 0, 128, &ctx->prof);
         ctx->setup(E, ctx->path, 0.0);
-        E.mm(C, ldc, n, n, segs, 2, true, false, nullptr, 0, 2.0 * (double)n * (double)(n + 1) / 2.0 * (double)(B ? 2 * k : k));
+        E.mm(C, ldc, n, n, segs, 2, true, false, 2.0 * (double)n * (double)(n + 1) / 2.0 * (double)(B ? 2 * k : k));
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
     });

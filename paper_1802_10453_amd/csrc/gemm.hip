@@ -37,8 +37,6 @@ struct GemmKArgs {
     int64_t K[2];
     Field F;
     int tiles_n;
-    int32_t* nzrow;   // optional: atomicMin(nzrow, nzoff + first row of C with a nonzero result)
-    int32_t nzoff;
     Stamp stamp;
 };
 
@@ -198,7 +196,6 @@ __global__ __launch_bounds__(gemm_threads<BM>()) void k_gemm(GemmKArgs g) {
         }
     }
     // epilogue: v_mfma_f64_16x16x4f64 result layout: lane l, register r holds D[l/16 + 4r][l%16]
-    int first_nz = 1 << 30;
 #pragma unroll
     for (int x = 0; x < FM; ++x)
 #pragma unroll
@@ -212,22 +209,8 @@ __global__ __launch_bounds__(gemm_threads<BM>()) void k_gemm(GemmKArgs g) {
                     const double cv = PRE_C ? cpre[PRE_C ? x : 0][PRE_C ? y : 0][r] : *c;
                     double v = fred(cv - fred(acc[x][y][r], F), F);
                     *c = v;
-                    if (v != 0.0 && row < first_nz) first_nz = (int)row;
                 }
             }
-    if (g.nzrow) {
-        // block minimum, then one atomic per block
-        for (int off = 32; off > 0; off >>= 1) first_nz = min(first_nz, __shfl_xor(first_nz, off));
-        __syncthreads();
-        int* red = (int*)&As[0][0][0];
-        if (lane == 0) red[wave] = first_nz;
-        __syncthreads();
-        if (tid == 0) {
-            int v = red[0];
-            for (int q = 1; q < NW; ++q) v = min(v, red[q]);
-            if (v < (1 << 30)) atomicMin(g.nzrow, g.nzoff + v);
-        }
-    }
     stamp_end(g.stamp);
 }
 
@@ -255,12 +238,10 @@ void dispatch_layout(hipStream_t s, GemmKArgs& g, bool ar, bool br, bool lower_c
 }  // namespace
 
 void launch_gemm(hipStream_t s, const Field& F, int64_t m, int64_t n, double* C, int64_t ldc,
-                 const GemmSeg* segs, int nseg, bool lower_c, bool b_upper, int32_t* nzrow, int32_t nzoff,
-                 Stamp stamp) {
+                 const GemmSeg* segs, int nseg, bool lower_c, bool b_upper, Stamp stamp) {
     if (m <= 0 || n <= 0) return;
     GemmKArgs g{};
     g.m = m; g.n = n; g.C = C; g.ldc = ldc; g.F = F;
-    g.nzrow = nzrow; g.nzoff = nzoff;
     g.stamp = stamp;
     bool any = false;
     for (int i = 0; i < 2; ++i) {
