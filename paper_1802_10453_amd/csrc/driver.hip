@@ -16,6 +16,7 @@
 #include <cstring>
 #include <stdexcept>
 #include <chrono>
+#include <immintrin.h>
 #include <fstream>
 #include <random>
 #include <sstream>
@@ -63,6 +64,8 @@ struct Err : std::runtime_error {
 static inline unsigned nblk(int64_t x, int b = 256) { return (unsigned)((x + b - 1) / b); }
 // mapped host words written by the PLDUQ slab launch: rank, abort flag
 constexpr int HW_SLAB = 256;
+// mapped host word a leaf launch raises to its generation once its results are written
+constexpr int HW_FLAG = 512;
 // "no column left of the range is read later" (see Engine::recall)
 constexpr int64_t AL_NONE = INT64_MAX;
 
@@ -208,6 +211,7 @@ struct Workspace {
     PsShared* ps = nullptr;        // words shared by the workgroups of a PLDUQ slab launch
     int32_t ps_gen = 0;            // generation of the last slab launch (flags compare equal to it)
     int32_t* hinfo = nullptr;      // pinned host words (rank, error flag, sigma, pivot columns)
+    int32_t hgen = 0;              // last generation raised in hinfo[HW_FLAG]
     int32_t* hinfo_dev = nullptr;  // the same words as seen from the device: leaves write them directly
     void release() {
         double* ds[] = {W, tmp1, tmp2, dd, de, xinv, yy, dvec, tinv};
@@ -278,6 +282,8 @@ struct Workspace {
             release();
             throw Err(PLDL_ENOMEM, "pinned alloc");
         }
+        std::memset(hinfo, 0, 1024 * sizeof(int32_t));
+        hgen = 0;
         cap = n;
     }
 };
@@ -335,6 +341,30 @@ struct Engine {
         HIPCHK(hipMemcpyAsync(ws.hinfo, ws.info + off, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, st));
         prof->n_launch++;
         return read_host();
+    }
+    // A leaf launch writes its results straight into the pinned host words and then
+    // raises HW_FLAG to its generation (system-scope release): the host polls that
+    // word and queues the next launches while the leaf's last waves drain, instead
+    // of waiting for the launch to end.  A launch that ends without raising it (an
+    // aborted PLDUQ slab) is caught by the stream query.  With per-launch events on,
+    // the plain wait keeps their harvest as it was.
+    int32_t next_hgen() {
+        ws.hgen = ws.hgen == INT32_MAX ? 1 : ws.hgen + 1;
+        return ws.hgen;
+    }
+    int32_t* wait_leaf(int32_t gen) {
+        if (prof->on && !prof->light) return read_host();
+        for (uint32_t it = 1;; ++it) {
+            if (__atomic_load_n(ws.hinfo + HW_FLAG, __ATOMIC_ACQUIRE) == gen) break;
+            if ((it & 255u) == 0) {
+                const hipError_t e = hipStreamQuery(st);
+                if (e == hipSuccess) break;
+                if (e != hipErrorNotReady) HIPCHK(e);
+            }
+            _mm_pause();
+        }
+        prof->n_wait++;
+        return ws.hinfo;
     }
     // words the device wrote straight into the pinned host words: only a wait
     int32_t* read_host() {
@@ -555,9 +585,10 @@ struct Engine {
     int64_t bc(int64_t lo, int64_t hi, int64_t al, int64_t below) {
         int s = (int)(hi - lo);
         REQUIRE(s >= 1 && s <= 128);
+        const int32_t gen = next_hgen();
         LAUNCH(PLDL_CLASS_BASE_CASE, k_bc_leaf, dim3(1), dim3(BC_THREADS), 0, st, W, ld, lo, s, F, itab, ws.dd, ws.de, ws.sig,
-               ws.hinfo_dev, ws.hinfo_dev + 1);
-        int32_t* h = read_host();
+               ws.hinfo_dev, ws.hinfo_dev + 1, ws.hinfo_dev + HW_FLAG, gen);
+        int32_t* h = wait_leaf(gen);
         int64_t r = h[0];
         bool ident = true;
         for (int q = 0; q < s; ++q) ident &= (h[1 + q] == q);
@@ -839,9 +870,11 @@ struct Engine {
         g.F = F; g.itab = itab; g.pR = pR; g.pC = pC; g.sh = ws.ps;
         g.gen = ++ws.ps_gen;
         g.hout = ws.hinfo_dev + HW_SLAB;   // (the base case uses words 0 .. 128)
+        g.hflag = ws.hinfo_dev + HW_FLAG;
+        g.hgen = next_hgen();
         ws.hinfo[HW_SLAB + 1] = 0;
         LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_slab, dim3((unsigned)nch), dim3(PS_THREADS), 0, st, g);
-        const int32_t* h = read_host();
+        const int32_t* h = wait_leaf(g.hgen);
         if (h[HW_SLAB + 1]) throw Err(PLDL_EINTERNAL, "PLDUQ slab: a chunk waited too long for its predecessor (launch aborted)");
         const int64_t R = h[HW_SLAB];
         REQUIRE(R >= 0 && R <= m);

@@ -45,11 +45,13 @@ struct PsArgs {
     PsShared* sh;
     int32_t gen;          // this launch's generation (> every earlier one on sh)
     int32_t* hout;        // mapped host words: [0] = slab rank, [1] = 1 if the launch aborted
+    int32_t* hflag;       // mapped host word raised to hgen once hout[0] is written
+    int32_t hgen;
 };
 __global__ void k_plduq_slab(PsArgs g);
 
 __global__ void k_bc_leaf(double* W, int64_t ld, int64_t lo, int s, Field F, const uint32_t* itab, double* dd,
-                          double* de, int32_t* sig_out, int32_t* rank_out, int32_t* hsig);
+                          double* de, int32_t* sig_out, int32_t* rank_out, int32_t* hsig, int32_t* hflag, int32_t hgen);
 constexpr int TS_THREADS = 256, TS_COLS = 2;   // small TRSM: workgroup size, right-hand sides per wave
 __global__ void k_trsm_small(double* B, int64_t ldb, int64_t nrhs, int r, MatV T, int right, Field F);
 __global__ void k_inv_scatter(const int32_t* snap, int64_t len, int32_t* inv);

@@ -28,7 +28,8 @@ namespace pldl {
 // ===========================================================================
 __global__ __launch_bounds__(BC_THREADS) void k_bc_leaf(double* W, int64_t ld, int64_t lo, int s, Field F,
                                                   const uint32_t* itab, double* dd, double* de,
-                                                  int32_t* sig_out, int32_t* rank_out, int32_t* hsig) {
+                                                  int32_t* sig_out, int32_t* rank_out, int32_t* hsig,
+                                                  int32_t* hflag, int32_t hgen) {
     __shared__ double colI[2][128], colJ[2][128];  // centered reduced columns, 0 on eliminated rows
     __shared__ int order[128], zeros[128], sig[128];
     __shared__ double bx[128], by[128];
@@ -250,6 +251,13 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_leaf(double* W, int64_t ld, i
         W[(lo + tid) * ld + lo + tid] = dd[lo + tid];
         sig_out[tid] = sig[tid];
         hsig[tid] = sig[tid];
+        __threadfence_system();
+    }
+    // the host polls this word instead of waiting for the launch to end
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence_system();
+        __hip_atomic_store(hflag, hgen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 

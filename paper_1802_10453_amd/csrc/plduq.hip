@@ -311,7 +311,12 @@ __global__ __launch_bounds__(PS_THREADS) void k_plduq_slab(PsArgs g) {
             }
         }
     }
-    if (b == g.nch - 1 && tid == 0) g.hout[0] = R;
+    if (b == g.nch - 1 && tid == 0) {
+        g.hout[0] = R;
+        // the host polls this word instead of waiting for the launch to end
+        __threadfence_system();
+        __hip_atomic_store(g.hflag, g.hgen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 }  // namespace pldl
