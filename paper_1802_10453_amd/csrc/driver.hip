@@ -657,7 +657,7 @@ struct Engine {
         LAUNCH(PLDL_CLASS_OTHER, k_copy2d, dim3(nblk(mz), (unsigned)nc), dim3(256), 0, st, T, mz, W + s0 * ld + lo, ld, nc, mz);
         LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(mz)), dim3(256), 0, st, pR, mz);
         LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(nc)), dim3(256), 0, st, pC, nc);
-        int64_t rY = plduq_t(0, mz, 0, nc);
+        int64_t rY = plduq_all(mz, nc);
         if (rY > 0) {
             perm_sym(s0, hi, pC, 2, al, hi);
             LAUNCH(PLDL_CLASS_OTHER, k_copy2d, dim3(nblk(mz), (unsigned)nc), dim3(256), 0, st, W + s0 * ld + lo, ld, T, mz, nc, mz);
@@ -812,20 +812,28 @@ struct Engine {
 
     // rows [a0, a1) and columns [c0, c1) of Y.  Row slabs of <= 64 rows; the
     // bottom half of a row split is updated with the top half's pivots (TRSM,
-    // GEMM) and continues on the columns the top half left.
-    int64_t plduq_t(int64_t a0, int64_t a1, int64_t c0, int64_t c1) {
+    // GEMM) and continues on the columns the top half left.  On return row a0 + q
+    // holds the row that was at a0 + srcR[q], column c0 + q the column that was at
+    // c0 + srcC[q] (the caller carries these orders to the parts it holds).
+    int64_t plduq_t(int64_t a0, int64_t a1, int64_t c0, int64_t c1, int32_t* srcR, int32_t* srcC) {
         const int64_t m = a1 - a0;
-        if (m <= 0 || c1 <= c0) return 0;
+        if (m <= 0 || c1 <= c0) {   // nothing moves
+            if (m > 0) LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(m)), dim3(256), 0, st, srcR, m);
+            if (c1 > c0) LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(c1 - c0)), dim3(256), 0, st, srcC, c1 - c0);
+            return 0;
+        }
         REQUIRE(a1 <= TC && c1 <= TR);
-        if (m <= 64) return plduq_slab(a0, a1, c0, c1);
+        if (m <= 64) return plduq_slab(a0, a1, c0, c1, srcR, srcC);
         const int64_t ip_save = ip_top;
         const int64_t am = a0 + std::max<int64_t>(64, (m / 2) / 64 * 64);
-        int32_t* snapC = snapshot(pC + c0, c1 - c0);
-        const int64_t r1 = plduq_t(a0, am, c0, c1);
+        const int64_t h = am - a0, mb = a1 - am, len = c1 - c0;
+        int32_t* sRt = ipush(h);
+        int32_t* sCt = ipush(len);
+        const int64_t r1 = plduq_t(a0, am, c0, c1, sRt, sCt);
         if (r1 > 0) {
-            const int64_t mb = a1 - am, ncr = c1 - c0 - r1;
+            const int64_t ncr = len - r1;
             // the bottom rows take the top half's column order
-            tcolperm(c0, c1 - c0, reorder_src(snapC, pC + c0, c1 - c0), am, mb);
+            tcolperm(c0, len, sCt, am, mb);
             // Wb^T = U_t^{-T} Y_b1^T  (U_t^T unit lower at T[c0.., a0..])
             trsm_ll(MatV{T + c0 * ldT + am, ldT, 1}, r1, mb, MatV{T + c0 * ldT + a0, ldT, 1});
             // Y_b2^T -= V_t^T Wb^T
@@ -836,24 +844,36 @@ struct Engine {
             LAUNCH(PLDL_CLASS_OTHER, k_scale_pack, dim3(nblk(mb), (unsigned)r1), dim3(256), 0, st, T + c0 * ldT + am, ldT, r1, mb,
                    T + c0 * ldT + a0, ldT, 1, itab, F);
         }
-        int32_t* snapC2 = snapshot(pC + c0 + r1, c1 - c0 - r1);
-        int32_t* snapR2 = snapshot(pR + am, a1 - am);
-        const int64_t r2 = plduq_t(am, a1, c0 + r1, c1);
+        int32_t* sRb = ipush(mb);
+        int32_t* sCb = ipush(std::max<int64_t>(len - r1, 1));
+        const int64_t r2 = plduq_t(am, a1, c0 + r1, c1, sRb, sCb);
         if (r2 > 0) {
             // the top rows take the bottom half's column order, the bottom rows' multipliers its row order
-            tcolperm(c0 + r1, c1 - c0 - r1, reorder_src(snapC2, pC + c0 + r1, c1 - c0 - r1), a0, am - a0);
-            if (r1 > 0) trowperm(c0, r1, am, a1 - am, reorder_src(snapR2, pR + am, a1 - am));
+            tcolperm(c0 + r1, len - r1, sCb, a0, h);
+            if (r1 > 0) trowperm(c0, r1, am, mb, sRb);
             // pivot rows of both halves first: rotate the top non-pivots behind the bottom pivots
-            if (am - a0 > r1) {
-                const int64_t len = am + r2 - (a0 + r1);
+            if (h > r1) {
+                const int64_t rl = am + r2 - (a0 + r1);
                 int32_t* src = ws.ipool_scratch + ws.ipool_scratch_len / 2;
-                LAUNCH(PLDL_CLASS_OTHER, k_rot_src, dim3(nblk(len)), dim3(256), 0, st, len, am - a0 - r1, src);
-                trowperm(c0, c1 - c0, a0 + r1, len, src);
-                idx_reorder(pR, a0 + r1, len, src);
+                LAUNCH(PLDL_CLASS_OTHER, k_rot_src, dim3(nblk(rl)), dim3(256), 0, st, rl, h - r1, src);
+                trowperm(c0, len, a0 + r1, rl, src);
+                idx_reorder(pR, a0 + r1, rl, src);
             }
         }
+        // this call's orders, composed from its halves' (a bottom half without pivots moved nothing)
+        LAUNCH(PLDL_CLASS_OTHER, k_compose_cols, dim3(nblk(len)), dim3(256), 0, st, srcC, sCt, r1, sCb, len);
+        LAUNCH(PLDL_CLASS_OTHER, k_compose_rows, dim3(nblk(m)), dim3(256), 0, st, srcR, sRt, h, sRb, m, r1, r2);
         ip_top = ip_save;
         return r1 + r2;
+    }
+    // the whole of T: the orders go to scratch on the stack
+    int64_t plduq_all(int64_t rows, int64_t cols) {
+        const int64_t ip_save = ip_top;
+        int32_t* sR = ipush(rows);
+        int32_t* sC = ipush(cols);
+        const int64_t r = plduq_t(0, rows, 0, cols, sR, sC);
+        ip_top = ip_save;
+        return r;
     }
 
     // A slab (<= 64 rows) in one launch (k_plduq_slab): chunks of PS_CHUNK
@@ -861,13 +881,14 @@ struct Engine {
     // in row order inside a chunk; on return the slab's pivot rows and pivot
     // columns come first (pivot order), pR / pC updated.  The host reads the
     // slab's rank from mapped host words (one wait per slab).
-    int64_t plduq_slab(int64_t a0, int64_t a1, int64_t c0, int64_t c1) {
+    int64_t plduq_slab(int64_t a0, int64_t a1, int64_t c0, int64_t c1, int32_t* srcR, int32_t* srcC) {
         const int64_t m = a1 - a0;
         const int64_t nch = (c1 - c0 + PS_CHUNK - 1) / PS_CHUNK;
         REQUIRE(m >= 1 && m <= 64 && nch >= 1 && nch <= PS_MAXCH);
         PsArgs g{};
         g.T = T; g.ld = ldT; g.a0 = a0; g.m = (int)m; g.nch = (int)nch; g.c0 = c0; g.c1 = c1;
         g.F = F; g.itab = itab; g.pR = pR; g.pC = pC; g.sh = ws.ps;
+        g.srcR = srcR; g.srcC = srcC;
         g.gen = ++ws.ps_gen;
         g.hout = ws.hinfo_dev + HW_SLAB;   // (the base case uses words 0 .. 128)
         g.hflag = ws.hinfo_dev + HW_FLAG;
@@ -1377,7 +1398,7 @@ int pldl_plduq(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, double* Y, int64
         LAUNCH(PLDL_CLASS_OTHER, k_transpose, dim3(nblk(n), (unsigned)m), dim3(256), 0, st, E.T, m, Y, ldy, m, n);
         LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(m)), dim3(256), 0, st, E.pR, m);
         LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(n)), dim3(256), 0, st, E.pC, n);
-        int64_t r = E.plduq_t(0, m, 0, n);
+        int64_t r = E.plduq_all(m, n);
         LAUNCH(PLDL_CLASS_OTHER, k_transpose, dim3(nblk(m), (unsigned)n), dim3(256), 0, st, Y, ldy, E.T, m, n, m);
         HIPCHK(hipMemcpyAsync(rows, E.pR, m * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(cols, E.pC, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));

@@ -47,6 +47,8 @@ struct PsArgs {
     int32_t* hout;        // mapped host words: [0] = slab rank, [1] = 1 if the launch aborted
     int32_t* hflag;       // mapped host word raised to hgen once hout[0] is written
     int32_t hgen;
+    int32_t* srcC;        // out: column position c0 + q holds the column that was at c0 + srcC[q]
+    int32_t* srcR;        // out: slab row a0 + q holds the row that was at a0 + srcR[q]
 };
 __global__ void k_plduq_slab(PsArgs g);
 
@@ -57,6 +59,9 @@ __global__ void k_trsm_small(double* B, int64_t ldb, int64_t nrhs, int r, MatV T
 __global__ void k_inv_scatter(const int32_t* snap, int64_t len, int32_t* inv);
 __global__ void k_src_gather(const int32_t* cur, int64_t len, const int32_t* inv, int32_t* src);
 __global__ void k_rot_src(int64_t len, int64_t rot1, int32_t* src);
+__global__ void k_compose_cols(int32_t* src, const int32_t* top, int64_t r1, const int32_t* bot, int64_t len);
+__global__ void k_compose_rows(int32_t* src, const int32_t* top, int64_t h, const int32_t* bot, int64_t len,
+                               int64_t r1, int64_t r2);
 __global__ void k_reorder_src_1wg(const int32_t* snap, const int32_t* cur, int64_t len, int32_t* inv, int32_t* src);
 __global__ void k_idx_reorder_1wg(int32_t* idx, int64_t a, int64_t len, const int32_t* src);
 __global__ void k_tcolperm(double* T, int64_t ld, int64_t j0, int64_t len, const int32_t* src, int64_t i0,

@@ -272,7 +272,10 @@ __global__ __launch_bounds__(PS_THREADS) void k_plduq_slab(PsArgs g) {
         const unsigned long long pm = __ballot(isp);
         const int before = lane - __popcll(pm & ((1ull << lane) - 1ull));   // non-pivot rows before this one
         newpos[lane] = isp ? rowpiv[lane] : R + before;
-        if (b == 0 && lane < m) g.pR[g.a0 + newpos[lane]] = pr_old;
+        if (b == 0 && lane < m) {
+            g.pR[g.a0 + newpos[lane]] = pr_old;
+            g.srcR[newpos[lane]] = lane;
+        }
     }
     __syncthreads();
     if (nw > 0) {
@@ -306,7 +309,10 @@ __global__ __launch_bounds__(PS_THREADS) void k_plduq_slab(PsArgs g) {
                 }
                 if (lane < m) g.T[dest * g.ld + g.a0 + np] = v;
                 const int pco = __shfl(pc_old, k);
-                if (lane == 0) g.pC[dest] = pco;
+                if (lane == 0) {
+                    g.pC[dest] = pco;
+                    g.srcC[dest - g.c0] = (int32_t)(cb - g.c0 + c);
+                }
                 pbefore += s >= 0;
             }
         }
