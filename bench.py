@@ -230,6 +230,8 @@ def main():
                          "split into signed bytes")
     ap.add_argument("--no-profile", action="store_true", help="time without per-launch events (no roofline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--winograd", type=int, default=0, metavar="MIN_ORDER",
+                    help="dense products with m, n, k >= MIN_ORDER take Winograd levels (pldl_set_winograd; 0: off)")
     ap.add_argument("--no-pluq", action="store_true",
                     help="skip the comparison with the unsymmetric RPM-revealing PLUQ (pldl_plduq) of the same input")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -258,6 +260,7 @@ def main():
     copies = [A0.clone() for _ in range(nrun)]
     ctx = pldl.Context(0)
     ctx.set_path(pldl.PLDL_PATH_I8 if args.path == "i8" else pldl.PLDL_PATH_F64)
+    ctx.set_winograd(args.winograd)
     threshold_used = args.threshold or 128
     if args.autotune and not args.threshold:
         import tempfile
@@ -352,7 +355,7 @@ def main():
         "dtype": "f64" if args.path == "f64" else "i8", "data": "synthetic",
         "config": {"workload": cfg["name"], "n": n, "p": p, "rank": r, "threshold": sched["threshold_used"],
                    "path": "fp64-mfma" if args.path == "f64" else "int8-split-mfma",
-                   "input": "uint32 residues in HBM", "schedule": sched},
+                   "winograd_min_order": args.winograd, "input": "uint32 residues in HBM", "schedule": sched},
         "roofline": roofline, "cpu_baseline": cpu,
     }
     if pluq is not None:

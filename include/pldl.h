@@ -61,6 +61,7 @@ typedef struct {
     int64_t products_i8;      /* products run on the INT8 matrix cores                  */
     int64_t launches;         /* kernel launches and stream memory operations queued    */
     int64_t host_waits;       /* host synchronisations of the stream inside the call    */
+    int64_t products_winograd;/* products split by a Winograd level (pldl_set_winograd) */
 } pldl_schedule;
 
 typedef struct {
@@ -304,10 +305,27 @@ int pldl_syrdk_noalloc(pldl_ctx *ctx, uint32_t p, int64_t n, int64_t k, const do
  * planes (L = 1 for p < 2^8, 2 for p < 2^15, else 3) into a context buffer
  * grown on demand, and runs the L^2 byte products on v_mfma_i32_16x16x64_i8;
  * results are identical to the FP64 path (both are exact).  Inside
- * pldl_factor, products below 2^27 flops and those that detect the first
- * nonzero row of their result stay on FP64.  Returns -2 for another value.
+ * pldl_factor, products below 2^27 flops, and products whose two segments
+ * together exceed the INT32 bound (K0 + K1 > 65535), stay on FP64.  Returns
+ * -2 for another value.
  */
 int pldl_set_path(pldl_ctx *ctx, int32_t path);
+
+/*
+ * Sub-cubic products (the paper's introduction: fast matrix multiplication is
+ * exact over F_p, so the factorization inherits its exponent).  Every later
+ * dense product of this context (a GEMM of the recursion, of PLDUQ or of
+ * pldl_gemm; not the triangular-output SYRDK / SYRD2K nor the TRMM) whose m,
+ * n and k are all >= min_order takes one level of Winograd's variant of
+ * Strassen's algorithm: seven products of half size and fifteen additions,
+ * all mod p, on the leading part whose halves are multiples of 64; the rest
+ * of the product is plain.  The half-size products take another level while
+ * they are still large enough.  Temporaries come from a context buffer grown
+ * on demand (about 4/3 of (m k + k n + 2 m n) / 2 doubles).  Results are
+ * identical (exact arithmetic).  min_order: 0 (off, the default) or
+ * 256 .. 65535; returns -2 for another value.
+ */
+int pldl_set_winograd(pldl_ctx *ctx, int64_t min_order);
 
 /* ---------------- measurement ---------------- */
 

@@ -91,8 +91,8 @@ struct Prof {
     struct TRec { int cls; double flops, bytes, ops8; };
     std::vector<TRec> trecs;
     // counts of the current call (pldl_schedule): dispatches queued, host waits, products per path
-    int64_t n_launch = 0, n_wait = 0, n_f64 = 0, n_i8 = 0;
-    void reset_counts() { n_launch = n_wait = n_f64 = n_i8 = 0; }
+    int64_t n_launch = 0, n_wait = 0, n_f64 = 0, n_i8 = 0, n_wino = 0;
+    void reset_counts() { n_launch = n_wait = n_f64 = n_i8 = n_wino = 0; }
 
     hipEvent_t ev() {
         if (pool.empty()) {
@@ -290,7 +290,7 @@ struct Workspace {
 
 // ---------------------------------------------------------------------------
 // Limb planes of the INT8-split products (grown on demand; see gemm_i8.hip).
-struct I8Space {
+struct GrowBuf {
     int8_t* p = nullptr;
     size_t cap = 0;
     void release() {
@@ -324,8 +324,11 @@ struct Engine {
     Prof* prof;
     const uint32_t* itab = nullptr;  // x -> x^{-1} mod p table (device), or NULL
     int path = PLDL_PATH_F64;         // products on FP64 or INT8-split matrix cores
-    I8Space* i8 = nullptr;
+    GrowBuf* i8 = nullptr;
     double i8_min_flops = 0.0;        // smaller products stay on FP64 (split passes would dominate)
+    GrowBuf* wg = nullptr;            // temporaries of the Winograd products (a stack)
+    int64_t wino_min = 0;             // products with m, n, k all >= this take a Winograd level (0: off)
+    size_t wg_top = 0;                // doubles in use on the Winograd stack
     Engine(Workspace& w, hipStream_t s, uint32_t p, int64_t n_, int t, Prof* pr)
         : st(s), F(make_field(p)), n(n_), ld(std::max<int64_t>(n_, 1)), t_leaf(t), ws(w), W(w.W), prof(pr) {}
 
@@ -400,6 +403,11 @@ struct Engine {
     // out); the path is chosen on the work the matrix cores do (every product of the tiles).
     void mm(double* C, int64_t ldc, int64_t m, int64_t nn, const GemmSeg* segs, int nseg, bool lower, bool b_upper,
             double flops) {
+        if (wino_min > 0 && !lower && !b_upper && segs[0].k >= wino_min && (nseg < 2 || segs[1].k <= 0) &&
+            m >= wino_min && nn >= wino_min) {
+            winograd(C, ldc, m, nn, segs[0].A, segs[0].B, segs[0].k);
+            return;
+        }
         double opnd = 0.0;   // operand elements, each read once
         double ksum = 0.0;
         for (int q = 0; q < nseg; ++q)
@@ -431,6 +439,87 @@ struct Engine {
         prof->end(st);
         prof->n_launch++;
         prof->n_f64++;
+    }
+
+    // One level of Winograd's variant of Strassen's product (exact over F_p: the
+    // seven half-size products and the fifteen sums are all taken mod p) on the
+    // leading 2mh x 2nh x 2kh part of C -= A B, the halves rounded down to
+    // multiples of 64; the strips outside it are plain products.  With
+    // S1 = A21 + A22, S2 = S1 - A11, S3 = A11 - A21, S4 = A12 - S2,
+    // T1 = B12 - B11, T2 = B22 - T1, T3 = B22 - B12, T4 = T2 - B21 and
+    // P1 = A11 B11, P2 = A12 B21, P3 = S4 B22, P4 = A22 T4, P5 = S1 T1,
+    // P6 = S2 T2, P7 = S3 T3, U2 = P1 + P6, U3 = U2 + P7, U4 = U2 + P5:
+    // C11 -= P1 + P2, C12 -= U4 + P3, C21 -= U3 - P4, C22 -= U3 + P5.
+    // The product kernel subtracts, so the temporaries hold -P1, -U2, ...
+    // Sub-products go through mm again (another level when they are still large).
+    double* wpush(size_t cnt) {
+        REQUIRE(wg_top + cnt <= wg->cap / sizeof(double));
+        double* p = (double*)wg->p + wg_top;
+        wg_top += (cnt + 31) / 32 * 32;
+        return p;
+    }
+    void winograd(double* C, int64_t ldc, int64_t m, int64_t nn, MatV A, MatV B, int64_t k) {
+        const int64_t mh = (m / 2) / 64 * 64, nh = (nn / 2) / 64 * 64, kh = (k / 2) / 64 * 64;
+        REQUIRE(mh > 0 && nh > 0 && kh > 0);
+        const size_t need = (size_t)(2 * mh * kh + 2 * kh * nh + 4 * mh * nh);
+        if (wg_top == 0) {   // outermost level: room for every nested level (each a quarter of its parent's)
+            if (wg->ensure(2 * (need + 1024) * sizeof(double), st)) prof->n_wait++;
+        }
+        prof->n_wino++;
+        const size_t top0 = wg_top;
+        double* S = wpush(mh * kh);
+        double* S4 = wpush(mh * kh);
+        double* Tt = wpush(kh * nh);
+        double* T34 = wpush(kh * nh);
+        double* Qa = wpush(mh * nh);
+        double* Qb = wpush(mh * nh);
+        double* Qc = wpush(mh * nh);
+        double* Qd = wpush(mh * nh);
+        auto blk = [](MatV X, int64_t r0, int64_t c0) { return MatV{X.p + r0 * X.rs + c0 * X.cs, X.rs, X.cs}; };
+        const MatV Cv{C, ldc, 1}, none{nullptr, 0, 0};
+        const MatV A11 = blk(A, 0, 0), A12 = blk(A, 0, kh), A21 = blk(A, mh, 0), A22 = blk(A, mh, kh);
+        const MatV B11 = blk(B, 0, 0), B12 = blk(B, 0, nh), B21 = blk(B, kh, 0), B22 = blk(B, kh, nh);
+        const MatV C11 = blk(Cv, 0, 0), C12 = blk(Cv, 0, nh), C21 = blk(Cv, mh, 0), C22 = blk(Cv, mh, nh);
+        const MatV vS{S, kh, 1}, vS4{S4, kh, 1}, vT{Tt, nh, 1}, vT34{T34, nh, 1};
+        const MatV vQa{Qa, nh, 1}, vQb{Qb, nh, 1}, vQc{Qc, nh, 1}, vQd{Qd, nh, 1};
+        auto ew = [&](MatV D, int64_t rows, int64_t cols, MatV X, int sx, MatV Y, int sy, MatV Z, int sz) {
+            LAUNCH(PLDL_CLASS_OTHER, k_ew3, dim3(nblk(cols), (unsigned)rows), dim3(256), 0, st, D, X, Y, Z, rows, cols,
+                   sx, sy, sz, F);
+        };
+        auto prod = [&](MatV Cq, int64_t pm, int64_t pn, MatV X, MatV Y, int64_t pk) {   // Cq -= X Y
+            if (pm <= 0 || pn <= 0 || pk <= 0) return;
+            GemmSeg sg{X, Y, pk};
+            mm(Cq.p, Cq.rs, pm, pn, &sg, 1, false, false, 2.0 * (double)pm * (double)pn * (double)pk);
+        };
+        REQUIRE(mh <= 65535 && kh <= 65535);
+        ew(vQa, mh, nh, none, 0, none, 0, none, 0);        // Qa = 0
+        prod(vQa, mh, nh, A11, B11, kh);                   // Qa = -P1
+        prod(C11, mh, nh, A12, B21, kh);                   // C11 -= P2
+        ew(C11, mh, nh, C11, 1, vQa, 1, none, 0);          // C11 -= P1
+        ew(vS, mh, kh, A21, 1, A22, 1, none, 0);           // S1
+        ew(vT, kh, nh, B12, 1, B11, -1, none, 0);          // T1
+        ew(vQc, mh, nh, none, 0, none, 0, none, 0);
+        prod(vQc, mh, nh, vS, vT, kh);                     // Qc = -P5
+        ew(vS, mh, kh, vS, 1, A11, -1, none, 0);           // S2
+        ew(vT, kh, nh, B22, 1, vT, -1, none, 0);           // T2
+        prod(vQa, mh, nh, vS, vT, kh);                     // Qa = -U2
+        ew(vS4, mh, kh, A12, 1, vS, -1, none, 0);          // S4
+        ew(vQb, mh, nh, vQa, 1, none, 0, none, 0);         // Qb = -U2
+        ew(vS, mh, kh, A11, 1, A21, -1, none, 0);          // S3
+        ew(vT34, kh, nh, B22, 1, B12, -1, none, 0);        // T3
+        prod(vQb, mh, nh, vS, vT34, kh);                   // Qb = -U3
+        ew(C22, mh, nh, C22, 1, vQb, 1, vQc, 1);           // C22 -= U3 + P5
+        ew(vQa, mh, nh, vQa, 1, vQc, 1, none, 0);          // Qa = -U4
+        prod(vQa, mh, nh, vS4, B22, kh);                   // Qa = -(U4 + P3)
+        ew(C12, mh, nh, C12, 1, vQa, 1, none, 0);          // C12 -= U4 + P3
+        ew(vT34, kh, nh, vT, 1, B21, -1, none, 0);         // T4
+        ew(vQd, mh, nh, none, 0, none, 0, none, 0);
+        prod(vQd, mh, nh, A22, vT34, kh);                  // Qd = -P4
+        ew(C21, mh, nh, C21, 1, vQb, 1, vQd, -1);          // C21 -= U3 - P4
+        wg_top = top0;
+        prod(C11, 2 * mh, 2 * nh, blk(A, 0, 2 * kh), blk(B, 2 * kh, 0), k - 2 * kh);
+        prod(blk(Cv, 2 * mh, 0), m - 2 * mh, nn, blk(A, 2 * mh, 0), B, k);
+        prod(blk(Cv, 0, 2 * nh), 2 * mh, nn - 2 * nh, A, blk(B, 0, 2 * nh), k);
     }
 
     // Columns left of every range still to be permuted that no later step reads
@@ -499,12 +588,11 @@ struct Engine {
 
     // ---- TRSM (Section 3) ---------------------------------------------------
     // A triangle of order <= 64 is one substitution launch (k_trsm_small).
-    // Larger ones: recursive halving (on multiples of 64) down to 64-blocks; the
-    // blocks' inverses come from one launch, and each leaf is one product applied
-    // in place: the output has a single column tile (right solve, r <= 64) or a
-    // single row tile (left solve), so every workgroup of k_gemm reads all of
-    // its operand rows (columns) before it writes them, and the INT8 path reads
-    // the limb planes it made beforehand.
+    // Larger ones: the inverses of all 64 x 64 diagonal blocks come from one
+    // launch; then recursive halving (on multiples of 64) down to orders <= 256,
+    // each solved in one launch (k_trsm_stripe: stripes of independent rows, or
+    // columns of a left solve, take the 64-blocks in order), with the updates
+    // between halves as products.
     static unsigned ts_grid(int64_t nrhs) {
         const int64_t per = (int64_t)TS_COLS * (TS_THREADS / 64);
         return (unsigned)((nrhs + per - 1) / per);
@@ -523,9 +611,10 @@ struct Engine {
         trsm_ru_rec(B, m, r, T, ws.tinv);
     }
     void trsm_ru_rec(MatV B, int64_t m, int64_t r, MatV T, double* Nb) {
-        if (r <= 64) {   // B <- B - B N (N strictly upper: column j sums j products)
-            gemm_ld(B.p, B.rs, m, r, GemmSeg{MatV{B.p, B.rs, 1}, MatV{Nb, 64, 1}, r},
-                    (double)m * (double)r * (double)(r - 1));
+        if (r <= TS_MAXR) {   // one launch: row stripes, 64-column blocks in order
+            REQUIRE((m + TSR - 1) / TSR < ((int64_t)1 << 31));
+            LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trsm_stripe, dim3((unsigned)((m + TSR - 1) / TSR)), dim3(256), 0, st, B, m,
+                   (int)r, T, Nb, 0, F);
             return;
         }
         int64_t r1 = std::max<int64_t>(64, (r / 2) / 64 * 64);
@@ -547,9 +636,10 @@ struct Engine {
         trsm_ll_rec(B, r, ncols, T, ws.tinv);
     }
     void trsm_ll_rec(MatV B, int64_t r, int64_t ncols, MatV T, double* Nb) {
-        if (r <= 64) {   // B <- B - N B (N strictly lower: row i sums i products)
-            gemm_ld(B.p, B.rs, r, ncols, GemmSeg{MatV{Nb, 64, 1}, MatV{B.p, B.rs, 1}, r},
-                    (double)ncols * (double)r * (double)(r - 1));
+        if (r <= TS_MAXR) {   // one launch, on the transposed views: X^T = B^T T^{-T}
+            REQUIRE((ncols + TSR - 1) / TSR < ((int64_t)1 << 31));
+            LAUNCH(PLDL_CLASS_TRSM_LEAF, k_trsm_stripe, dim3((unsigned)((ncols + TSR - 1) / TSR)), dim3(256), 0, st,
+                   MatV{B.p, B.cs, B.rs}, ncols, (int)r, MatV{T.p, T.cs, T.rs}, Nb, 1, F);
             return;
         }
         int64_t r1 = std::max<int64_t>(64, (r / 2) / 64 * 64);
@@ -938,7 +1028,9 @@ struct pldl_ctx {
     uint32_t* itab = nullptr;  // inverse table of modulus itab_p
     uint32_t itab_p = 0;
     int path = PLDL_PATH_F64;  // matrix cores of the products (pldl_set_path)
-    I8Space i8;
+    GrowBuf i8;
+    GrowBuf wbuf;              // Winograd temporaries
+    int64_t wino_min = 0;      // pldl_set_winograd
     // autotuned base-case thresholds: (p, n, threshold); pldl_factor takes the entry of
     // the same p (else any p) nearest to its n on a log scale, else 128
     struct Tune { uint32_t p; int64_t n; int t; };
@@ -962,6 +1054,8 @@ struct pldl_ctx {
         E.path = pth;
         E.i8 = &i8;
         E.i8_min_flops = i8_min;
+        E.wg = &wbuf;
+        E.wino_min = wino_min;
     }
     // table x -> x^{-1} mod p, built on the device the first time p is used
     const uint32_t* inv_table(uint32_t p, hipStream_t st) {
@@ -1031,6 +1125,7 @@ int pldl_destroy(pldl_ctx* ctx) {
     (void)hipDeviceSynchronize();
     ctx->ws.release();
     ctx->i8.release();
+    ctx->wbuf.release();
     if (ctx->bws) (void)hipFree(ctx->bws);
     if (ctx->bqueue) (void)hipFree(ctx->bqueue);
     if (ctx->itab) (void)hipFree(ctx->itab);
@@ -1071,6 +1166,7 @@ int pldl_factor(pldl_ctx* ctx, uint32_t p, int64_t n, void* A, int64_t lda, int3
         sc.products_i8 = ctx->prof.n_i8;
         sc.launches = ctx->prof.n_launch;
         sc.host_waits = ctx->prof.n_wait;
+        sc.products_winograd = ctx->prof.n_wino;
         *sched_out = sc;
     };
     if (n == 0) { *rank = 0; fill_sched(); return PLDL_OK; }
@@ -1614,6 +1710,14 @@ int pldl_autotune(pldl_ctx* ctx, uint32_t p, const int64_t* n_list, int64_t coun
         for (const std::string& r : rows) out << r << "\n";
     }
     return rc;
+}
+
+int pldl_set_winograd(pldl_ctx* ctx, int64_t min_order) {
+    if (!ctx) return -1;
+    if (min_order != 0 && (min_order < 256 || min_order > 65535))
+        return fail(ctx, -2, "min_order must be 0 (off) or in [256, 65535]");
+    ctx->wino_min = min_order;
+    return PLDL_OK;
 }
 
 int pldl_set_path(pldl_ctx* ctx, int32_t path) {

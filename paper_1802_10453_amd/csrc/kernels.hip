@@ -631,6 +631,159 @@ __global__ __launch_bounds__(1024) void k_trinv_blocks(MatV T, int64_t r, int lo
     }
 }
 
+// X = B T^{-1} for T unit upper of order r <= 256 (TS_MAXR), in one launch.
+// B (m x r) is cut into stripes of TSR rows, one workgroup each (the rows of a
+// right solve are independent).  Column block j of the stripe (64 columns) is
+//   Y_j = B_j - sum_{i<j} X_i T_ij,   X_j = Y_j - Y_j N_j   (= Y_j T_jj^{-1}),
+// with N_j = -(strict part of T_jj^{-1}) from k_trinv_blocks (row-major 64 x 64;
+// n_trans: read it transposed).  The solved blocks stay in LDS as the left
+// operand of the next ones.  The 64 x 64 tiles of T and N go through LDS in the
+// order they are used (T_0j .. T_{j-1,j}, N_j for j = 0, 1, ...); none depends
+// on the solution, so each is loaded into registers TS_PF tiles ahead.  Every
+// product sums at most 256 products of centered residues (< 2^52), so one
+// reduction per block suffices.  A left solve X = T^{-1} B (T unit lower) is
+// this solve on transposed views: X^T = B^T T^{-T}.
+__global__ __launch_bounds__(256) void k_trsm_stripe(MatV B, int64_t m, int r, MatV T, const double* N, int n_trans,
+                                                     Field F) {
+    constexpr int PF = 3, EPT = 4096 / 256;   // tiles in flight, tile elements per thread
+    __shared__ double Xs[TSR][TS_MAXR + 2];
+    __shared__ double Ts[64][64 + 2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int64_t s0 = (int64_t)blockIdx.x * TSR;
+    const int rows = (int)min((int64_t)TSR, m - s0);
+    const int nb = (r + 63) / 64, ntiles = nb * (nb + 1) / 2;
+    const int wr = (wave & 1) * 16, wc = (wave >> 1) * 32;   // this wave's 16 x 32 part of a 32 x 64 block
+    const bool t_kfast = T.rs == 1;                          // consecutive k of a T column are contiguous
+    // tile t -> (j, i): i < j is T_ij, i == j is N_j
+    auto decode = [&](int t, int& j, int& i) {
+        j = 0;
+        while (t > j) { t -= j + 1; ++j; }
+        i = t;
+    };
+    // element e of tile t for this thread: Ts row a (k), column b
+    auto tile_ab = [&](int t, int q, int& a, int& b) {
+        int j, i;
+        decode(t, j, i);
+        const int e = tid + 256 * q;
+        if (i < j && t_kfast) { a = e & 63; b = e >> 6; }
+        else { a = e >> 6; b = e & 63; }
+    };
+    auto load_tile = [&](int t, double (&v)[EPT]) {
+        if (t >= ntiles) return;
+        int j, i;
+        decode(t, j, i);
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            int a, b;
+            tile_ab(t, q, a, b);
+            double x = 0.0;
+            if (i < j) {
+                const int k = i * 64 + a, c = j * 64 + b;
+                if (k < r && c < r) x = T.p[(int64_t)k * T.rs + (int64_t)c * T.cs];
+            } else {
+                x = N[(int64_t)j * 4096 + (n_trans ? b * 64 + a : a * 64 + b)];
+            }
+            v[q] = x;
+        }
+    };
+    double pre[PF][EPT];
+#pragma unroll
+    for (int u = 0; u < PF; ++u) load_tile(u, pre[u]);
+    d4 acc[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
+    double bv[2][4];     // B_j of this thread's outputs, loaded when step j starts
+    double xv[2][4];     // X_{j-1}, written to LDS after the next barrier
+    int xpend = -1;      // column block of the pending X values
+    auto load_b = [&](int j) {
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = wr + lk + 4 * q, col = j * 64 + wc + 16 * y + lr;
+                bv[y][q] = (row < rows && col < r) ? B.p[(s0 + row) * B.rs + (int64_t)col * B.cs] : 0.0;
+            }
+    };
+    load_b(0);
+    for (int t = 0; t < ntiles; ++t) {
+        int j, i;
+        decode(t, j, i);
+        __syncthreads();   // Ts free; every wave is done reading Xs block xpend (as Y)
+        if (xpend >= 0) {
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) Xs[wr + lk + 4 * q][xpend * 64 + wc + 16 * y + lr] = fcen(xv[y][q], F);
+            xpend = -1;
+        }
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            int a, b;
+            tile_ab(t, q, a, b);
+            Ts[a][b] = fcen(pre[0][q], F);
+        }
+        double yv[2][4];
+        if (i == j) {   // Y_j = B_j - acc, the left operand of the N_j product
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    yv[y][q] = fred(bv[y][q] - acc[y][q], F);
+                    Xs[wr + lk + 4 * q][j * 64 + wc + 16 * y + lr] = fcen(yv[y][q], F);
+                }
+        }
+        // the register sets move up one; tile t + PF starts loading
+#pragma unroll
+        for (int u = 0; u + 1 < PF; ++u)
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) pre[u][q] = pre[u + 1][q];
+        load_tile(t + PF, pre[PF - 1]);
+        __syncthreads();
+        if (i < j) {
+#pragma unroll
+            for (int kk = 0; kk < 64; kk += 4) {
+                const double a = Xs[wr + lr][i * 64 + kk + lk];
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    acc[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ts[kk + lk][wc + 16 * y + lr], acc[y], 0, 0, 0);
+            }
+        } else {
+            d4 acc2[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+            for (int kk = 0; kk < 64; kk += 4) {
+                const double a = Xs[wr + lr][j * 64 + kk + lk];
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    acc2[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ts[kk + lk][wc + 16 * y + lr], acc2[y], 0, 0, 0);
+            }
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = wr + lk + 4 * q, col = j * 64 + wc + 16 * y + lr;
+                    const double x = fred(yv[y][q] - acc2[y][q], F);
+                    xv[y][q] = x;
+                    if (row < rows && col < r) B.p[(s0 + row) * B.rs + (int64_t)col * B.cs] = x;
+                }
+            xpend = j;
+            acc[0] = d4{0.0, 0.0, 0.0, 0.0};
+            acc[1] = d4{0.0, 0.0, 0.0, 0.0};
+            if (j + 1 < nb) load_b(j + 1);
+        }
+    }
+}
+
+// D = sx X + sy Y + sz Z (mod p) on rows x cols views of canonical residues
+// (a zero sign skips its operand; all zero: D = 0).  D may be one of the operands.
+__global__ void k_ew3(MatV D, MatV X, MatV Y, MatV Z, int64_t rows, int64_t cols, int sx, int sy, int sz, Field F) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
+    if (i >= rows || j >= cols) return;
+    double v = 0.0;
+    if (sx) v += sx * X.p[i * X.rs + j * X.cs];
+    if (sy) v += sy * Y.p[i * Y.rs + j * Y.cs];
+    if (sz) v += sz * Z.p[i * Z.rs + j * Z.cs];
+    D.p[i * D.rs + j * D.cs] = fred(v, F);
+}
+
 // ===========================================================================
 // Permutations.  A sigma maps new local position q to old local position
 // sig[q].  Out-of-range sigma entries (a bug upstream) are clamped so that no

@@ -48,7 +48,8 @@ class pldl_opts(ctypes.Structure):
 
 class pldl_schedule(ctypes.Structure):
     _fields_ = [("threshold_used", _i32), ("split_rule", _i32), ("path_used", _i32), ("i8_min_log2_flops", _i32),
-                ("products_f64", _i64), ("products_i8", _i64), ("launches", _i64), ("host_waits", _i64)]
+                ("products_f64", _i64), ("products_i8", _i64), ("launches", _i64), ("host_waits", _i64),
+                ("products_winograd", _i64)]
 
     def as_dict(self):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
@@ -70,6 +71,7 @@ _lib.pldl_trss.argtypes = [_vp, _u32, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp
 _lib.pldl_plduq.argtypes = [_vp, _u32, _i64, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(_i64), _vp]
 _lib.pldl_profile.argtypes = [_vp, _i32, ctypes.POINTER(pldl_stats)]
 _lib.pldl_set_path.argtypes = [_vp, _i32]
+_lib.pldl_set_winograd.argtypes = [_vp, _i64]
 _lib.pldl_char2_to_standard.argtypes = [_vp, _i64, _vp, _i64, _i32, _vp, _vp, _vp]
 _lib.pldl_autotune.argtypes = [_vp, _u32, ctypes.POINTER(_i64), _i64, ctypes.c_char_p, _vp]
 _lib.pldl_factor_batched.argtypes = [_vp, _u32, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
@@ -77,14 +79,14 @@ _lib.pldl_factor_batched.argtypes = [_vp, _u32, _i64, _vp, _vp, _vp, _i32, _vp, 
 for _f in ("pldl_create", "pldl_destroy", "pldl_factor", "pldl_solve", "pldl_invariants", "pldl_gemm", "pldl_trsm",
            "pldl_syrdk", "pldl_syrdk_noalloc",
            "pldl_trss",
-           "pldl_plduq", "pldl_profile", "pldl_set_path", "pldl_factor_batched", "pldl_char2_to_standard",
-           "pldl_autotune"):
+           "pldl_plduq", "pldl_profile", "pldl_set_path", "pldl_set_winograd", "pldl_factor_batched",
+           "pldl_char2_to_standard", "pldl_autotune"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("pldl_create", "pldl_destroy", "pldl_last_error", "pldl_factor", "pldl_solve", "pldl_invariants",
             "pldl_gemm", "pldl_trsm",
-            "pldl_syrdk", "pldl_syrdk_noalloc", "pldl_trss", "pldl_plduq", "pldl_profile", "pldl_set_path", "pldl_factor_batched",
-            "pldl_char2_to_standard", "pldl_autotune")
+            "pldl_syrdk", "pldl_syrdk_noalloc", "pldl_trss", "pldl_plduq", "pldl_profile", "pldl_set_path",
+            "pldl_set_winograd", "pldl_factor_batched", "pldl_char2_to_standard", "pldl_autotune")
 
 
 class PldlError(RuntimeError):
@@ -139,6 +141,10 @@ class Context:
     def set_path(self, path: int):
         """pldl_set_path: PLDL_PATH_F64 or PLDL_PATH_I8 for the products of later calls."""
         self._check(_lib.pldl_set_path(self._h, int(path)))
+
+    def set_winograd(self, min_order: int):
+        """pldl_set_winograd: dense products with m, n, k >= min_order take Winograd levels (0: off)."""
+        self._check(_lib.pldl_set_winograd(self._h, int(min_order)))
 
     def factor(self, A: torch.Tensor, p: int, threshold: int = 0, standard_form: bool = False,
                check_range: bool = True, path: int = PLDL_PATH_AUTO):

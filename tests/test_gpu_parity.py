@@ -110,6 +110,27 @@ def test_trsm_parity(ctx, p):
         assert (host(Bd) == ref).all()
 
 
+@pytest.mark.parametrize("p", PRIMES)
+def test_trsm_stripe_orders(ctx, p):
+    """Orders 65..257 (one stripe launch each, the last one split once), stripe counts
+    with a ragged last stripe, both sides."""
+    g = inputs.rng(p + 12)
+    for (r, k) in [(65, 1), (128, 31), (192, 33), (256, 1000), (257, 95)]:
+        print(f"[trsm stripe] p={p} r={r} k={k}", flush=True)
+        T = rnd(g, p, r, r)
+        B = rnd(g, p, r, k)
+        Bd = dev(B)
+        ctx.trsm(p, dev(T), Bd, lower=True)
+        Tl = np.tril(T, -1) + np.eye(r, dtype=np.uint32)
+        assert (host(Bd) == orc.trsm_left(p, Tl, B, lower=True)).all()
+        Bt = B.T.copy()
+        Bd = dev(Bt)
+        ctx.trsm(p, dev(T), Bd, lower=False)
+        Tu = np.triu(T, 1) + np.eye(r, dtype=np.uint32)
+        ref = orc.trsm_left(p, Tu.T.copy(), Bt.T.copy(), lower=True).T
+        assert (host(Bd) == ref).all()
+
+
 # ---------------------------------------------------------------- SYRDK / SYRD2K
 @pytest.mark.parametrize("p", PRIMES)
 def test_syrdk_parity(ctx, p):

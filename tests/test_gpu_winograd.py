@@ -1,0 +1,117 @@
+"""Winograd's variant of Strassen's product (the paper's introduction: fast matrix
+multiplication is exact over F_p) inside pldl_gemm and inside whole
+factorizations, against the CPU oracle, bit-exact."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle.oracle as orc  # noqa: E402
+from paper_1802_10453_amd import inputs  # noqa: E402
+
+from gpu_helpers import check_against_oracle, gpu_factor  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1802_10453_amd import pldl
+    c = pldl.Context(0)
+    yield c
+    c.set_winograd(0)
+    c.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x).astype(np.float64)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy().astype(np.int64).astype(np.uint32)
+
+
+def rnd(g, p, *shape):
+    return g.integers(0, p, size=shape).astype(np.uint32)
+
+
+@pytest.mark.parametrize("p", [2, 65521, 8388593])
+@pytest.mark.parametrize("m,n,k", [(600, 700, 520), (1100, 1300, 900), (257, 256, 300)])
+def test_winograd_gemm(ctx, p, m, n, k):
+    """One level (257 x 256 x 300: odd halves, strips outside the core), two levels
+    (600 x 700 x 520 and 1100 x 1300 x 900, with ragged strips at both levels)."""
+    g = inputs.rng(p + m + 7 * n + 13 * k)
+    A, B, C = rnd(g, p, m, k), rnd(g, p, k, n), rnd(g, p, m, n)
+    print(f"[winograd gemm] p={p} m={m} n={n} k={k}", flush=True)
+    ctx.set_winograd(256)
+    try:
+        Cd = dev(C)
+        ctx.gemm(p, Cd, dev(A), dev(B))
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_winograd(0)
+    assert (host(Cd) == orc.gemm(p, C, A, B)).all()
+
+
+def test_winograd_gemm_transposed_operands(ctx):
+    """Column-major views of A and B (the recursion's products read such views)."""
+    p = 8388593
+    g = inputs.rng(4242)
+    m, n, k = 640, 520, 700
+    A, B, C = rnd(g, p, m, k), rnd(g, p, k, n), rnd(g, p, m, n)
+    print("[winograd gemm] transposed", flush=True)
+    ctx.set_winograd(256)
+    try:
+        Cd = dev(C)
+        ctx.gemm(p, Cd, dev(A.T.copy()), dev(B.T.copy()), transA=True, transB=True)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_winograd(0)
+    assert (host(Cd) == orc.gemm(p, C, A, B)).all()
+
+
+def test_winograd_int8_path(ctx):
+    """The half-size products on the INT8 split (large enough to cross its cut)."""
+    from paper_1802_10453_amd import pldl
+    p = 8388593
+    g = inputs.rng(777)
+    m, n, k = 1200, 1100, 1000
+    A, B, C = rnd(g, p, m, k), rnd(g, p, k, n), rnd(g, p, m, n)
+    print("[winograd gemm] int8", flush=True)
+    ctx.set_winograd(512)
+    ctx.set_path(pldl.PLDL_PATH_I8)
+    try:
+        Cd = dev(C)
+        ctx.gemm(p, Cd, dev(A), dev(B))
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_winograd(0)
+        ctx.set_path(pldl.PLDL_PATH_F64)
+    assert (host(Cd) == orc.gemm(p, C, A, B)).all()
+
+
+@pytest.mark.parametrize("p,n,f,c", [(8388593, 2400, 700, 250), (65521, 2048, 600, 200)])
+def test_winograd_inside_factorization(ctx, p, n, f, c):
+    """A rank-deficient factorization whose recursion has dense products with m, n, k
+    >= 256: the schedule reports Winograd products, and r, R, (L, D) match the oracle."""
+    A, _ = inputs.rank_profile_matrix_input(n, p, f, c, inputs.SEED_BASE + 505 + n, check=8)
+    ctx.set_winograd(256)
+    try:
+        res = gpu_factor(ctx, A, p)
+        Ad = torch.from_numpy(A.astype(np.int32)).cuda()
+        sched = ctx.factor(Ad, p)["schedule"]
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_winograd(0)
+    assert sched["products_winograd"] > 0, sched
+    assert res["rank"] == f + 2 * c
+    check_against_oracle(A, p, res)
+
+
+def test_winograd_setter_rejects_small_orders(ctx):
+    from paper_1802_10453_amd import pldl
+    for bad in (1, 255, 65536):
+        with pytest.raises(pldl.PldlError):
+            ctx.set_winograd(bad)
+    ctx.set_winograd(0)
