@@ -12,9 +12,9 @@
 //
 // Structure: workgroup tile BM x BN (128x128 with 16 waves in a 2x8 grid, or
 // 64x64 with 16 waves in a 4x4 grid when the big tiles would leave CUs idle), K
-// tiles of 16 staged through double-buffered LDS (one barrier per K tile),
-// later K tiles' global loads in flight while the current one feeds the matrix
-// cores.
+// tiles of 32 (big) or 16 (small) staged through double-buffered LDS (one
+// barrier per K tile), later K tiles' global loads in flight while the current
+// one feeds the matrix cores.
 #include <type_traits>
 
 #include "common.h"
@@ -22,7 +22,10 @@
 namespace pldl {
 
 namespace {
-constexpr int BK = 16, PAD = 2;   // LDS row padding (doubles): breaks the bank conflicts of the transposed tile stores
+constexpr int PAD = 2;   // LDS row padding (doubles): breaks the bank conflicts of the transposed tile stores
+// K depth of an LDS tile: 32 for the big tile (twice the matrix-core work per
+// barrier; measured 3-4% faster on the largest products), 16 for the small one
+template <int BM> constexpr int gemm_bk() { return BM == 128 ? 32 : 16; }
 // waves of a workgroup (up to BN/16 along n, the rest along m): more waves than
 // SIMDs let one wave's loads and barrier waits overlap another's matrix-core work
 constexpr int BIG_WAVES = 16, SMALL_WAVES = 16;
@@ -42,7 +45,7 @@ struct GemmKArgs {
 
 template <int BM, int BN, bool A_ROW, bool B_ROW, bool LOWER_C, bool B_UPPER>
 __global__ __launch_bounds__(gemm_threads<BM>()) void k_gemm(GemmKArgs g) {
-    constexpr int NT = gemm_threads<BM>(), NW = NT / 64;
+    constexpr int NT = gemm_threads<BM>(), NW = NT / 64, BK = gemm_bk<BM>();
     constexpr int WGN = NW / 2 < BN / 16 ? NW / 2 : BN / 16, WGM = NW / WGN;   // wave grid
     constexpr int WM = BM / WGM, WN = BN / WGN;  // wave tile
     static_assert(WM % 16 == 0 && WN % 16 == 0 && WGM * WGN == NW, "wave grid");
@@ -69,8 +72,8 @@ __global__ __launch_bounds__(gemm_threads<BM>()) void k_gemm(GemmKArgs g) {
     const int lr = lane & 15, lk = lane >> 4;
 
     // per-thread load coordinates inside a tile (element e adds a fixed step)
-    //   A row-major:  row tid/16 + 16e, col tid%16     A col-major: row tid%BM, col tid/BM + (NT/BM)e
-    //   B row-major:  k tid/BN + (NT/BN)e, col tid%BN  B col-major: k tid%16, col tid/16 + 16e
+    //   A row-major:  row tid/BK + (NT/BK)e, col tid%BK   A col-major: row tid%BM, col tid/BM + (NT/BM)e
+    //   B row-major:  k tid/BN + (NT/BN)e, col tid%BN     B col-major: k tid%BK, col tid/BK + (NT/BK)e
     const int a_r0 = A_ROW ? tid / BK : tid % BM, a_c0 = A_ROW ? tid % BK : tid / BM;
     const int a_dr = A_ROW ? NT / BK : 0, a_dc = A_ROW ? 0 : NT / BM;
     const int b_k0 = B_ROW ? tid / BN : tid % BK, b_c0 = B_ROW ? tid % BN : tid / BK;
@@ -158,19 +161,28 @@ __global__ __launch_bounds__(gemm_threads<BM>()) void k_gemm(GemmKArgs g) {
         int cur = 0;
         // one K tile: feed the matrix cores from LDS, move tile t+1 from its register
         // set to the other buffer, refill that set with tile t+1+PD
+        // (the LDS reads of the next k step are issued before this step's products)
         auto body = [&](int64_t t, auto slot_c) {
+            double a[2][FM], b[2][FN];
+#pragma unroll
+            for (int q = 0; q < FM; ++q) a[0][q] = As[cur][lk][wm * WM + q * 16 + lr];
+#pragma unroll
+            for (int q = 0; q < FN; ++q) b[0][q] = Bs[cur][lk][wn * WN + q * 16 + lr];
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 4) {
-                double a[FM], b[FN];
+                const int c = (kk / 4) & 1;
+                if (kk + 4 < BK) {
 #pragma unroll
-                for (int q = 0; q < FM; ++q) a[q] = As[cur][kk + lk][wm * WM + q * 16 + lr];
+                    for (int q = 0; q < FM; ++q) a[c ^ 1][q] = As[cur][kk + 4 + lk][wm * WM + q * 16 + lr];
 #pragma unroll
-                for (int q = 0; q < FN; ++q) b[q] = Bs[cur][kk + lk][wn * WN + q * 16 + lr];
+                    for (int q = 0; q < FN; ++q) b[c ^ 1][q] = Bs[cur][kk + 4 + lk][wn * WN + q * 16 + lr];
+                }
+                __builtin_amdgcn_sched_barrier(0);   // keep those reads ahead of the products
 #pragma unroll
                 for (int x = 0; x < FM; ++x)
 #pragma unroll
                     for (int y = 0; y < FN; ++y)
-                        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+                        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][x], b[c][y], acc[x][y], 0, 0, 0);
             }
             if (t + 1 < nt) {
                 store(slot_c, cur ^ 1);
@@ -179,7 +191,7 @@ __global__ __launch_bounds__(gemm_threads<BM>()) void k_gemm(GemmKArgs g) {
             __syncthreads();
             cur ^= 1;
             since += BK;
-            if (since >= F.kred) {
+            if (since + BK > F.kred) {   // the next tile would pass the exactness bound
 #pragma unroll
                 for (int x = 0; x < FM; ++x)
 #pragma unroll
