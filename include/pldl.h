@@ -10,8 +10,9 @@
  *    row-major with an explicit leading dimension (elements, >= row length).
  *  - Residues are canonical, in [0, p).  The building-block calls take and
  *    return FP64 residues (integers held exactly in doubles).
- *  - p must be prime with 2 <= p < 2^23 (primality is the caller's duty;
- *    p >= 2^23 or p < 2 gives PLDL_EUNSUPPORTED_P).
+ *  - p must be prime with 2 <= p < 2^24 (primality is the caller's duty;
+ *    p >= 2^24 or p < 2 gives PLDL_EUNSUPPORTED_P).  The INT8 product path
+ *    covers p < 2^23; for larger p its products run on FP64.
  *  - `stream` is a hipStream_t (NULL = default stream).  Every call is ordered
  *    on that stream; calls that must return a rank to the host synchronise it.
  *  - The caller owns every array; the library never frees or reallocates
@@ -30,7 +31,7 @@ extern "C" {
 
 #define PLDL_OK 0
 #define PLDL_ERANGE 1          /* an input entry is >= p                         */
-#define PLDL_EUNSUPPORTED_P 2  /* p outside [2, 2^23)                            */
+#define PLDL_EUNSUPPORTED_P 2  /* p outside [2, 2^24)                            */
 #define PLDL_EHIP 3            /* HIP runtime error (text in pldl_last_error)    */
 #define PLDL_ENOMEM 4          /* workspace allocation failed                    */
 #define PLDL_EINTERNAL 5       /* internal consistency check failed              */
@@ -38,6 +39,8 @@ extern "C" {
 
 #define PLDL_U32 0             /* uint32 residues */
 #define PLDL_F64 1             /* FP64 residues   */
+
+#define PLDL_THRESHOLD_ONLINE (-1)  /* pldl_opts.threshold: chosen online by the context */
 
 #define PLDL_PATH_AUTO 0       /* the context's path (pldl_set_path; FP64 at creation) */
 #define PLDL_PATH_F64 1        /* products on FP64 MFMA with delayed reduction         */
@@ -67,7 +70,14 @@ typedef struct {
 typedef struct {
     int32_t path;          /* PLDL_PATH_*                                              */
     int32_t threshold;     /* base-case order t of the cascade (Section 5), 1..128;
-                              0 = the context's autotuned value (pldl_autotune), else 128 */
+                              0 = the context's autotuned value (pldl_autotune), else 128;
+                              PLDL_THRESHOLD_ONLINE = chosen by the context from the wall
+                              times of its earlier calls of the same p and order class
+                              (each of 128, 96, 64 timed once, then the fastest, with
+                              every 16th call re-timing the oldest measurement; the
+                              end of Section 6 suggests such introspective tuning).
+                              sched_out reports the value used, which with A and p
+                              fixes the result.                                       */
     int32_t standard_form; /* p == 2 only: turn relaxed 2x2 blocks into the standard
                               form of Section 2.3 (after the rank profile is taken)     */
     int32_t check_range;   /* nonzero: reject inputs with an entry >= p (PLDL_ERANGE);
@@ -111,8 +121,9 @@ const char *pldl_last_error(const pldl_ctx *ctx);
  *         (threshold, split rule, product path and counts, launches, waits).
  * Errors: -1 ctx NULL; -3 n outside [0, 65535]; -4 A NULL; -5 lda < max(1, n);
  * -6 unknown dtype; -7 e NULL; -8 perm NULL; -9 rpm NULL; -10 rank NULL;
- * -11 opts invalid (path or threshold outside [0, 128]); PLDL_EUNSUPPORTED_P
- * for p outside [2, 2^23); PLDL_ERANGE when opts->check_range is set and an
+ * -11 opts invalid (path, or threshold neither PLDL_THRESHOLD_ONLINE nor in
+ * [0, 128]); PLDL_EUNSUPPORTED_P
+ * for p outside [2, 2^24); PLDL_ERANGE when opts->check_range is set and an
  * input entry is >= p (nothing else is written); PLDL_ENOMEM, PLDL_EHIP.
  * With standard_form set and p == 2, perm/L/diag/e are returned in the standard
  * form of Section 2.3 while rpm still holds R.

@@ -10,7 +10,7 @@
 // reveals the rank profile matrix (Theorem 1) like the recursive cascade.
 //
 // The Schur complement lives in a private slot as exact residues in FP32
-// (|value| < p < 2^23), lower triangle stored by columns: entry (k, l), k >= l,
+// (|value| < p < 2^24), lower triangle stored by columns: entry (k, l), k >= l,
 // at S[l * n + k], so the column a pivot step reads is contiguous.  Updates are
 // lazy: a 1x1 pivot contributes one rank-1 term u v^T, a 2x2 pivot two; up to
 // KMAX terms wait in LDS.  Only the column factor v of a term is stored (by

@@ -9,8 +9,9 @@ namespace pldl {
 // ---------------------------------------------------------------------------
 // Field parameters.  Residues are integers held exactly in doubles; every
 // kernel keeps W canonical ([0, p)).  Products of two centered residues are
-// below p^2/4 < 2^44 for p < 2^23, so a double accumulates `kred` of them
-// (plus one carried residue) before the 2^53 exactness limit.
+// below p^2/4 (< 2^44 for p < 2^23, < 2^46 for p < 2^24), so a double
+// accumulates `kred` of them (plus one carried residue) before the 2^53
+// exactness limit: 496 at p = 8388593, 128 at p = 16777213.
 struct Field {
     double p;       // modulus
     double pinv;    // 1/p rounded

@@ -201,7 +201,7 @@ struct Workspace {
     int64_t tinv_rows = 0;    // tinv holds tinv_rows / 64 blocks
     int8_t* kind = nullptr;
     int32_t *orig = nullptr, *sig = nullptr, *tmpo = nullptr, *info = nullptr, *pidx = nullptr;
-    int32_t* ipool = nullptr;          // PLDUQ: stack of index snapshots, then scratch
+    int32_t* ipool = nullptr;          // stack of PLDUQ orders and orig snapshots, then scratch
     int64_t ipool_len = 0;             // ints of the stack part
     int32_t* ipool_scratch = nullptr;  // two halves: inverse map, reorder source
     int64_t ipool_scratch_len = 0;
@@ -253,10 +253,10 @@ struct Workspace {
                 throw Err(PLDL_ENOMEM, "alloc");
             }
         if (hipMalloc((void**)&info, 1024 * sizeof(int32_t)) != hipSuccess) { release(); throw Err(PLDL_ENOMEM, "alloc"); }
-        // snapshot stack: 3 segments of at most m entries per row-split level (<= 11 levels
-        // for m <= 65535), the orig snapshots of the ranges that move the rows under them
-        // at their end (at most 2m along one recursion path), then the scratch (inverse
-        // map and source, m + 64 each)
+        // stack: the row and column orders of both halves of a PLDUQ row split (at most
+        // 4 segments of m entries per level, <= 11 levels for m <= 65535), the orig
+        // snapshots of the ranges that move the rows under them at their end (at most 2m
+        // along one recursion path), then the scratch (inverse map and source, m + 64 each)
         ipool_len = 44 * (m + 64);
         ipool_scratch_len = 2 * (m + 64);
         if (hipMalloc((void**)&ipool, (ipool_len + ipool_scratch_len) * sizeof(int32_t)) != hipSuccess) {
@@ -824,14 +824,14 @@ struct Engine {
     // T (TR x TC, leading dimension ldT) holds Y^T: Y[i][j] = T[j][i].  pR / pC
     // give the original row / column index at each position of Y.  A call on rows
     // [a0, a1) and columns [c0, c1) reorders rows and columns of that submatrix
-    // only, and keeps pR[a0 .. a1) and pC[c0 .. c1) up to date; its caller
-    // carries the new orders to the other parts of the matrix that hold data
-    // (from snapshots of pR / pC taken before the call), so no step moves the
-    // whole width of Y.  The caller of the whole PLDUQ applies pC to W once.
+    // only, keeps pR[a0 .. a1) and pC[c0 .. c1) up to date and returns the row
+    // and column orders it applied; its caller carries them to the other parts
+    // of the matrix that hold data, so no step moves the whole width of Y.  The
+    // caller of the whole PLDUQ applies pC to W once.
     double* T = nullptr;
     int64_t ldT = 0, TR = 0, TC = 0;
     int32_t *pR = nullptr, *pC = nullptr;
-    int64_t ip_top = 0;   // stack pointer in ws.ipool (snapshots of pR / pC segments)
+    int64_t ip_top = 0;   // stack pointer in ws.ipool
 
     int32_t* ipush(int64_t cnt) {
         REQUIRE(ip_top + cnt + 64 <= ws.ipool_len);
@@ -1046,6 +1046,50 @@ struct pldl_ctx {
             }
         return best;
     }
+    // Online threshold (the introspective refinement suggested at the end of
+    // Section 6): per (p, order rounded to a power of two), the wall time of
+    // every pldl_factor call made with threshold = PLDL_THRESHOLD_ONLINE.  Each
+    // candidate is tried once, then the fastest is used; every 16th call
+    // re-times the candidate with the oldest measurement, so the choice follows
+    // changes of the running instances (load, other processes).
+    static constexpr int N_ONLINE = 3;
+    static constexpr int online_cand[N_ONLINE] = {128, 96, 64};
+    struct Online { double ms[N_ONLINE]; int64_t when[N_ONLINE]; int64_t calls; };
+    std::vector<std::pair<std::pair<uint32_t, int>, Online>> online;
+    Online& online_slot(uint32_t p, int64_t n) {
+        int lg = 0;
+        while (((int64_t)1 << (lg + 1)) <= n) ++lg;
+        for (auto& e : online)
+            if (e.first.first == p && e.first.second == lg) return e.second;
+        Online o{};
+        for (int c = 0; c < N_ONLINE; ++c) { o.ms[c] = -1.0; o.when[c] = -1; }
+        online.push_back({{p, lg}, o});
+        return online.back().second;
+    }
+    int online_pick(uint32_t p, int64_t n, int* slot) {
+        Online& o = online_slot(p, n);
+        int pick = -1;
+        for (int c = 0; c < N_ONLINE && pick < 0; ++c)
+            if (o.ms[c] < 0.0) pick = c;
+        if (pick < 0 && o.calls % 16 == 15) {   // re-time the oldest measurement
+            pick = 0;
+            for (int c = 1; c < N_ONLINE; ++c)
+                if (o.when[c] < o.when[pick]) pick = c;
+        }
+        if (pick < 0) {
+            pick = 0;
+            for (int c = 1; c < N_ONLINE; ++c)
+                if (o.ms[c] < o.ms[pick]) pick = c;
+        }
+        *slot = pick;
+        return online_cand[pick];
+    }
+    void online_record(uint32_t p, int64_t n, int slot, double ms) {
+        Online& o = online_slot(p, n);
+        o.ms[slot] = ms;
+        o.when[slot] = o.calls;
+        ++o.calls;
+    }
     void* bws = nullptr;       // batched factorizations: one slot per persistent workgroup
     int bslots = 0;
     int32_t* bqueue = nullptr;
@@ -1080,7 +1124,7 @@ int fail(pldl_ctx* c, int code, const std::string& m) {
     return code;
 }
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
-bool bad_p(uint32_t p) { return p < 2 || p >= (1u << 23); }
+bool bad_p(uint32_t p) { return p < 2 || p >= (1u << 24); }
 
 template <typename Fn>
 int guarded(pldl_ctx* ctx, Fn&& fn) {
@@ -1138,7 +1182,7 @@ const char* pldl_last_error(const pldl_ctx* ctx) { return ctx ? ctx->err.c_str()
 int pldl_factor(pldl_ctx* ctx, uint32_t p, int64_t n, void* A, int64_t lda, int32_t dtype, void* e, int32_t* perm,
                 int32_t* rpm, int64_t* rank, const pldl_opts* opts, pldl_schedule* sched_out, void* stream) {
     if (!ctx) return -1;
-    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^24");
     if (n < 0 || n > 65535) return fail(ctx, -3, "n out of range [0, 65535]");
     if (n > 0 && !A) return fail(ctx, -4, "A is NULL");
     if (lda < std::max<int64_t>(1, n)) return fail(ctx, -5, "lda < max(1, n)");
@@ -1151,8 +1195,13 @@ int pldl_factor(pldl_ctx* ctx, uint32_t p, int64_t n, void* A, int64_t lda, int3
     if (opts) o = *opts;
     if (o.path != PLDL_PATH_AUTO && o.path != PLDL_PATH_F64 && o.path != PLDL_PATH_I8)
         return fail(ctx, -11, "unknown path");
-    if (o.threshold < 0 || o.threshold > 128) return fail(ctx, -11, "threshold must be in [0, 128]");
-    int t = o.threshold ? o.threshold : ctx->tuned_threshold(p, n);
+    if (o.threshold < PLDL_THRESHOLD_ONLINE || o.threshold > 128)
+        return fail(ctx, -11, "threshold must be PLDL_THRESHOLD_ONLINE or in [0, 128]");
+    int online_slot = -1;
+    int t = o.threshold > 0 ? o.threshold
+          : o.threshold == 0 ? ctx->tuned_threshold(p, n)
+          : (n > 0 ? ctx->online_pick(p, n, &online_slot) : 128);
+    const auto t_call = std::chrono::steady_clock::now();
     const int path_used = o.path == PLDL_PATH_AUTO ? ctx->path : o.path;
     ctx->prof.reset_counts();
     auto fill_sched = [&]() {
@@ -1220,6 +1269,9 @@ int pldl_factor(pldl_ctx* ctx, uint32_t p, int64_t n, void* A, int64_t lda, int3
         prof->n_wait++;
         *rank = r;
     });
+    if (rc == PLDL_OK && online_slot >= 0)
+        ctx->online_record(p, n, online_slot,
+                           std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_call).count());
     if (rc == PLDL_OK) fill_sched();
     return rc;
 }
@@ -1227,7 +1279,7 @@ int pldl_factor(pldl_ctx* ctx, uint32_t p, int64_t n, void* A, int64_t lda, int3
 int pldl_gemm(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda, int32_t transA,
               const double* B, int64_t ldb, int32_t transB, double* C, int64_t ldc, int32_t lower_only, void* stream) {
     if (!ctx) return -1;
-    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^24");
     if (m < 0) return fail(ctx, -3, "m < 0");
     if (n < 0) return fail(ctx, -4, "n < 0");
     if (k < 0) return fail(ctx, -5, "k < 0");
@@ -1254,7 +1306,7 @@ int pldl_gemm(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, int64_t k, const 
 int pldl_trsm(pldl_ctx* ctx, uint32_t p, int32_t lower, int64_t m, int64_t n, const double* T, int64_t ldt, double* B,
               int64_t ldb, void* stream) {
     if (!ctx) return -1;
-    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^24");
     if (m < 0) return fail(ctx, -4, "m < 0");
     if (n < 0) return fail(ctx, -5, "n < 0");
     int64_t tord = lower ? m : n;
@@ -1277,7 +1329,7 @@ int pldl_trsm(pldl_ctx* ctx, uint32_t p, int32_t lower, int64_t m, int64_t n, co
 int pldl_syrdk(pldl_ctx* ctx, uint32_t p, int64_t n, int64_t k, const double* A, int64_t lda, const double* B,
                int64_t ldb, const double* dd, const double* de, double* C, int64_t ldc, void* stream) {
     if (!ctx) return -1;
-    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^24");
     if (n < 0) return fail(ctx, -3, "n < 0");
     if (k < 0) return fail(ctx, -4, "k < 0");
     if (n > 0 && k > 0 && !A) return fail(ctx, -5, "A is NULL");
@@ -1313,7 +1365,7 @@ int pldl_syrdk(pldl_ctx* ctx, uint32_t p, int64_t n, int64_t k, const double* A,
 int pldl_syrdk_noalloc(pldl_ctx* ctx, uint32_t p, int64_t n, int64_t k, const double* A, int64_t lda, const double* B,
                        int64_t ldb, const double* dd, const double* de, double* C, int64_t ldc, void* stream) {
     if (!ctx) return -1;
-    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^24");
     if (n < 0) return fail(ctx, -3, "n < 0");
     if (k < 0) return fail(ctx, -4, "k < 0");
     if (n > 0 && k > 0 && !A) return fail(ctx, -5, "A is NULL");
@@ -1351,7 +1403,7 @@ int pldl_solve(pldl_ctx* ctx, uint32_t p, int64_t n, const void* F, int64_t lda,
                const int32_t* perm, int64_t rank, double* B, int64_t ldb, int64_t nrhs, int32_t* consistent,
                void* stream) {
     if (!ctx) return -1;
-    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^24");
     if (n < 0 || n > 65535) return fail(ctx, -3, "n out of range [0, 65535]");
     if (n > 0 && !F) return fail(ctx, -4, "F is NULL");
     if (lda < std::max<int64_t>(1, n)) return fail(ctx, -5, "lda < max(1, n)");
@@ -1406,7 +1458,7 @@ int pldl_solve(pldl_ctx* ctx, uint32_t p, int64_t n, const void* F, int64_t lda,
 int pldl_invariants(pldl_ctx* ctx, uint32_t p, int64_t n, const void* F, int64_t lda, int32_t dtype, const void* e,
                     int64_t rank, int64_t* out, void* stream) {
     if (!ctx) return -1;
-    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^24");
     if (n < 0 || n > 65535) return fail(ctx, -3, "n out of range [0, 65535]");
     if (n > 0 && !F) return fail(ctx, -4, "F is NULL");
     if (lda < std::max<int64_t>(1, n)) return fail(ctx, -5, "lda < max(1, n)");
@@ -1430,7 +1482,7 @@ int pldl_invariants(pldl_ctx* ctx, uint32_t p, int64_t n, const void* F, int64_t
 int pldl_trss(pldl_ctx* ctx, uint32_t p, int64_t n, const double* U, int64_t ldu, const double* C, int64_t ldc,
               double* X, int64_t ldx, void* stream) {
     if (!ctx) return -1;
-    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^24");
     if (n < 0 || 2 * n > 65535) return fail(ctx, -3, "n out of range");
     if (n > 0 && !U) return fail(ctx, -4, "U is NULL");
     if (ldu < std::max<int64_t>(1, n)) return fail(ctx, -5, "ldu too small");
@@ -1466,7 +1518,7 @@ int pldl_trss(pldl_ctx* ctx, uint32_t p, int64_t n, const double* U, int64_t ldu
 int pldl_plduq(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, double* Y, int64_t ldy, int32_t* rows, int32_t* cols,
                int64_t* rank, void* stream) {
     if (!ctx) return -1;
-    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^24");
     if (m < 0 || m > 65535) return fail(ctx, -3, "m out of range");
     if (n < 0 || n > 65535) return fail(ctx, -4, "n out of range");
     if (m > 0 && n > 0 && !Y) return fail(ctx, -5, "Y is NULL");
@@ -1508,7 +1560,7 @@ int pldl_factor_batched(pldl_ctx* ctx, uint32_t p, int64_t batch, const int64_t*
                         int32_t dtype, void* const* e, int32_t* const* perm, int32_t* const* rpm, int64_t* rank,
                         int32_t* status, const pldl_opts* opts, void* stream) {
     if (!ctx) return -1;
-    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^24");
     if (batch < 0 || batch > ((int64_t)1 << 30)) return fail(ctx, -3, "batch out of range");
     if (batch > 0 && !n) return fail(ctx, -4, "n is NULL");
     if (batch > 0 && !A) return fail(ctx, -5, "A is NULL");
@@ -1594,7 +1646,7 @@ int pldl_char2_to_standard(pldl_ctx* ctx, int64_t n, void* A, int64_t lda, int32
 int pldl_autotune(pldl_ctx* ctx, uint32_t p, const int64_t* n_list, int64_t count, const char* table_path,
                   void* stream) {
     if (!ctx) return -1;
-    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^23");
+    if (bad_p(p)) return fail(ctx, PLDL_EUNSUPPORTED_P, "p must satisfy 2 <= p < 2^24");
     if (count < 0) return fail(ctx, -4, "count < 0");
     if (count > 0 && !n_list) return fail(ctx, -3, "n_list is NULL");
     for (int64_t k = 0; k < count; ++k)

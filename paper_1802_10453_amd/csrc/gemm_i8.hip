@@ -242,6 +242,7 @@ size_t i8_workspace_bytes(uint32_t p, int64_t m, int64_t n, const GemmSeg* segs,
 bool i8_prepare(hipStream_t s, const Field& F, int64_t m, int64_t n, const GemmSeg* segs, int nseg, bool b_upper,
                 int8_t* ws, size_t ws_bytes, I8Product* out) {
     const uint32_t p = (uint32_t)F.ip;
+    if (p >= (1u << 23)) return false;   // 3 balanced digits cover |a| < 2^22 only: such products run on FP64
     const int L = i8_limbs(p);
     if (i8_workspace_bytes(p, m, n, segs, nseg) > ws_bytes) return false;
     int64_t ktot = 0;   // both segments share the INT32 accumulators

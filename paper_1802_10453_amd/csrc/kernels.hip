@@ -72,6 +72,22 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_leaf(double* W, int64_t ld, i
     auto ralive = [&](int q) -> bool { return (rbits >> q) & 1u; };
     auto calive = [&](int q) -> bool { return (cbits >> q) & 1u; };
 
+    // The delayed reduction holds while p + (products since the last reduction)
+    // * (p/2 + 2)^2 < 2^53: never within 128 steps for p < 2^23 (3 products per
+    // 2x2 step); for larger p every entry is reduced once the bound is near.
+    const double hb = F.half + 2.0;
+    const int prod_cap = (int)fmin(1.0e9, floor((9007199254740992.0 - 2.0 * F.p) / (hb * hb)));
+    int since = 0;
+    auto reduce_before = [&](int next) {
+        if (since + next > prod_cap) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < TW; ++b) m[a][b] = fredc(m[a][b], F);
+            since = 0;
+        }
+        since += next;
+    };
     int r = 0, nz = 0, step = 0;
     for (int i = 0; i < s; ++i) {
         if (!alive(i)) continue;
@@ -125,6 +141,7 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_leaf(double* W, int64_t ld, i
                 int l = c0 + b;
                 vc[b] = calive(b) ? colI[bI][l] : 0.0;
             }
+            reduce_before(1);
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -184,6 +201,7 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_leaf(double* W, int64_t ld, i
                 la[b] = fredc(el * xi, F);
             }
             // S[k][l] -= x (a_k b_l + b_k a_l) + d22 b_k b_l = e_k b_l + c_k a_l + f_k b_l
+            reduce_before(3);
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -639,9 +657,10 @@ __global__ __launch_bounds__(1024) void k_trinv_blocks(MatV T, int64_t r, int lo
 // n_trans: read it transposed).  The solved blocks stay in LDS as the left
 // operand of the next ones.  The 64 x 64 tiles of T and N go through LDS in the
 // order they are used (T_0j .. T_{j-1,j}, N_j for j = 0, 1, ...); none depends
-// on the solution, so each is loaded into registers TS_PF tiles ahead.  Every
-// product sums at most 256 products of centered residues (< 2^52), so one
-// reduction per block suffices.  A left solve X = T^{-1} B (T unit lower) is
+// on the solution, so each is loaded into registers PF tiles ahead.  A block
+// sums at most 192 + 64 products of centered residues: below 2^53 for p < 2^23
+// (kred >= 496); for larger p the running sum is reduced between tiles once
+// kred products would be exceeded.  A left solve X = T^{-1} B (T unit lower) is
 // this solve on transposed views: X^T = B^T T^{-T}.
 __global__ __launch_bounds__(256) void k_trsm_stripe(MatV B, int64_t m, int r, MatV T, const double* N, int n_trans,
                                                      Field F) {
@@ -739,6 +758,12 @@ __global__ __launch_bounds__(256) void k_trsm_stripe(MatV B, int64_t m, int r, M
         load_tile(t + PF, pre[PF - 1]);
         __syncthreads();
         if (i < j) {
+            if (i > 0 && 64 * (i + 1) > F.kred) {   // (larger p only) keep the running sum below 2^53
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[y][q] = fredc(acc[y][q], F);
+            }
 #pragma unroll
             for (int kk = 0; kk < 64; kk += 4) {
                 const double a = Xs[wr + lr][i * 64 + kk + lk];

@@ -24,6 +24,7 @@ _vp, _i64, _i32, _u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.
 
 PLDL_U32, PLDL_F64 = 0, 1
 PLDL_PATH_AUTO, PLDL_PATH_F64, PLDL_PATH_I8 = 0, 1, 2
+PLDL_THRESHOLD_ONLINE = -1
 ERRORS = {1: "PLDL_ERANGE", 2: "PLDL_EUNSUPPORTED_P", 3: "PLDL_EHIP", 4: "PLDL_ENOMEM", 5: "PLDL_EINTERNAL",
           6: "PLDL_ETOOBIG"}
 NOALLOC_SCRATCH_DOUBLES = 1 << 21

@@ -67,7 +67,7 @@ def check_one(A, p, args, t):
     assert (e == ref["de"]).all()
 
 
-@pytest.mark.parametrize("p", [2, 3, 32749, 65521, 8388593])
+@pytest.mark.parametrize("p", [2, 3, 32749, 65521, 8388593, 16777213])
 def test_batched_parity(ctx, p):
     sizes = [1, 2, 3, 17, 64, 65, 100, 127, 128, 129, 200, 257, 383, 512, 31, 500]
     print(f"[batched] p={p} sizes={sizes}", flush=True)

@@ -67,6 +67,25 @@ def test_gemm_big_tile_dense(ctx, p, tb):
     assert (host(Cd) == orc.gemm(p, C, A, B)).all()
 
 
+@pytest.mark.parametrize("p", [8388593, 16777213])
+def test_gemm_big_tile_adversarial_bounds(ctx, p):
+    """Big tiles (2048 x 2048) with every operand at the extreme centered value and
+    K around the delayed-reduction chunk (496 at p = 8388593, 128 at 16777213) and
+    past it: the accumulators must be reduced before any partial sum passes 2^53."""
+    m = n = 2048
+    for v in ((p - 1) // 2, (p + 1) // 2):
+        for k in (127, 129, 495, 497, 1000):
+            print(f"[big tile bounds] p={p} v={v} k={k}", flush=True)
+            A = np.full((m, k), v, dtype=np.uint32)
+            B = np.full((k, n), v, dtype=np.uint32)
+            C = np.full((m, n), p - 1, dtype=np.uint32)
+            Cd = dev(C)
+            ctx.gemm(p, Cd, dev(A), dev(B))
+            want = (p - 1 - (k * v * v) % p) % p
+            got = host(Cd)
+            assert (got == want).all(), (v, k, int(got[0, 0]), want)
+
+
 def test_gemm_big_tile_ragged_edges(ctx):
     """Big tiles with ragged M, N and K edges (2050 x 2000, k = 333)."""
     p = 8388593
@@ -187,9 +206,9 @@ def test_factor_argument_errors(ctx):
     assert call(rank_out=False) == -10
     assert call(opts=pldl.pldl_opts(9, 0, 0, 0)) == -11
     assert call(opts=pldl.pldl_opts(0, 129, 0, 0)) == -11
-    assert call(opts=pldl.pldl_opts(0, -1, 0, 0)) == -11
+    assert call(opts=pldl.pldl_opts(0, -2, 0, 0)) == -11   # (-1 is PLDL_THRESHOLD_ONLINE)
     assert call(pp=1) == pldl.ERRORS_BY_NAME["PLDL_EUNSUPPORTED_P"]
-    assert call(pp=1 << 23) == pldl.ERRORS_BY_NAME["PLDL_EUNSUPPORTED_P"]
+    assert call(pp=1 << 24) == pldl.ERRORS_BY_NAME["PLDL_EUNSUPPORTED_P"]
     assert "p must satisfy" in ctx.last_error()
     # n = 0 is valid and needs no arrays
     assert call(nn=0, a=None, lda=1, ee=None, pe=None, rp=None) == 0
@@ -229,3 +248,47 @@ def test_factor_range_error_and_schedule(ctx):
     assert sc["threshold_used"] == 48 and sc["split_rule"] == 64
     assert sc["path_used"] == pldl.PLDL_PATH_F64 and sc["products_i8"] == 0
     assert sc["products_f64"] > 0 and sc["launches"] > sc["products_f64"] and sc["host_waits"] >= 1
+
+
+# ---------------------------------------------------------------- online threshold
+def _factor_host(ctx, A, p, threshold):
+    n = A.shape[0]
+    Ad = torch.from_numpy(A.astype(np.int32)).cuda()
+    out = ctx.factor(Ad, p, threshold=threshold)
+    torch.cuda.synchronize()
+    Ah = Ad.cpu().numpy().astype(np.int64).astype(np.uint32)
+    L = np.tril(Ah, -1)
+    L[np.arange(n), np.arange(n)] = 1
+    res = dict(perm=out["perm"].cpu().numpy().astype(np.int32), rpm=out["rpm"].cpu().numpy().astype(np.int32), L=L,
+               dd=np.diag(Ah).copy(), de=out["e"].cpu().numpy().astype(np.int64).astype(np.uint32), rank=out["rank"])
+    return res, out["schedule"]
+
+
+def test_online_threshold(ctx):
+    """threshold = PLDL_THRESHOLD_ONLINE: the first calls of an order class time
+    each candidate once (128, 96, 64 in that order), later ones use the fastest;
+    every call's result matches the oracle and equals the explicit call with the
+    threshold it reports."""
+    from paper_1802_10453_amd import pldl
+    p, n = 65521, 900
+    A, _ = inputs.rank_profile_matrix_input(n, p, 300, 150, inputs.SEED_BASE + 611, check=8)
+    ref = orc.search(A, p)
+    used = []
+    for call in range(5):
+        print(f"[online] call {call}", flush=True)
+        res, sc = _factor_host(ctx, A, p, pldl.PLDL_THRESHOLD_ONLINE)
+        used.append(sc["threshold_used"])
+        check_against_oracle(A, p, res, ref=ref)
+        exp, sc2 = _factor_host(ctx, A, p, sc["threshold_used"])
+        assert sc2["threshold_used"] == sc["threshold_used"]
+        assert (exp["perm"] == res["perm"]).all() and (exp["L"] == res["L"]).all()
+    print("[online] thresholds used:", used, flush=True)
+    assert used[:3] == [128, 96, 64], used
+    assert all(t in (128, 96, 64) for t in used[3:]), used
+
+
+def test_online_threshold_rejects_other_negatives(ctx):
+    from paper_1802_10453_amd import pldl
+    A = np.zeros((8, 8), dtype=np.uint32)
+    with pytest.raises(pldl.PldlError):
+        ctx.factor(torch.from_numpy(A.astype(np.int32)).cuda(), 65521, threshold=-2)

@@ -14,7 +14,7 @@ from paper_1802_10453_amd import inputs  # noqa: E402
 from gpu_helpers import check_against_oracle, gpu_factor  # noqa: E402
 
 # one, two and three limbs, each near its limb-count boundary
-PRIMES = [2, 3, 251, 257, 32749, 32771, 65521, 8388593]
+PRIMES = [2, 3, 251, 257, 32749, 32771, 65521, 8388593, 16777213]   # the last runs on FP64 products
 
 
 @pytest.fixture(scope="module")

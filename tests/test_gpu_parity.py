@@ -16,7 +16,7 @@ from paper_1802_10453_amd import inputs  # noqa: E402
 
 from gpu_helpers import check_against_oracle, freivalds, gpu_factor, structure  # noqa: E402
 
-PRIMES = [2, 3, 65521, 8388593]
+PRIMES = [2, 3, 65521, 8388593, 16777213]   # the last: above 2^23, delayed-reduction chunk 128
 
 
 @pytest.fixture(scope="module")
@@ -58,12 +58,12 @@ def test_gemm_parity(ctx, p, ta, tb):
         assert (host(Cd) == orc.gemm(p, C, A, B)).all()
 
 
-@pytest.mark.parametrize("p", [65521, 8388593])
+@pytest.mark.parametrize("p", [65521, 8388593, 16777213])
 def test_gemm_adversarial_bounds(ctx, p):
     """All operands at the extreme centered value (p-1)/2 (and p-1), K at and past the
     delayed-reduction chunk: every partial sum sits at the 2^53 exactness limit."""
     for v in ((p - 1) // 2, (p + 1) // 2, p - 1):
-        for k in (495, 496, 497, 1000, 2049):
+        for k in (127, 128, 129, 495, 496, 497, 1000, 2049):
             m, n = 33, 65
             A = np.full((m, k), v, dtype=np.uint32)
             B = np.full((k, n), v, dtype=np.uint32)
@@ -74,7 +74,7 @@ def test_gemm_adversarial_bounds(ctx, p):
             assert (host(Cd) == ref.astype(np.uint32)).all(), (v, k)
 
 
-@pytest.mark.parametrize("p", [2, 65521, 8388593])
+@pytest.mark.parametrize("p", [2, 65521, 8388593, 16777213])
 def test_gemm_lower_only(ctx, p):
     g = inputs.rng(p + 3)
     for (n, k) in [(1, 4), (127, 33), (300, 260)]:
@@ -155,7 +155,7 @@ def test_syrdk_parity(ctx, p):
 
 
 # ---------------------------------------------------------------- TRSS (Algorithm 1)
-@pytest.mark.parametrize("p", [3, 65521, 8388593, 2])
+@pytest.mark.parametrize("p", [3, 65521, 8388593, 2, 16777213])
 def test_trss_parity(ctx, p):
     g = inputs.rng(p + 17)
     for n in (1, 2, 17, 64, 65, 130, 300):
@@ -181,7 +181,7 @@ def test_trss_char2_rejects_nonzero_diagonal(ctx):
 
 
 # ---------------------------------------------------------------- PLDUQ
-@pytest.mark.parametrize("p", [2, 65521, 8388593])
+@pytest.mark.parametrize("p", [2, 65521, 8388593, 16777213])
 def test_plduq_parity(ctx, p):
     g = inputs.rng(p + 19)
     for (m, n, k) in [(1, 1, 1), (5, 9, 3), (40, 30, 25), (33, 300, 20), (70, 600, 64), (100, 90, 100), (64, 64, 0)]:
@@ -315,7 +315,7 @@ def test_recursive_random(ctx, p, t):
             assert (res["rpm"] == rpm).all()
 
 
-@pytest.mark.parametrize("p", [65521, 8388593, 2])
+@pytest.mark.parametrize("p", [65521, 8388593, 2, 16777213])
 def test_recursive_medium(ctx, p):
     """Several tiles of every kernel and a ragged tail (n not a tile multiple)."""
     n = 777

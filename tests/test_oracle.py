@@ -17,7 +17,7 @@ import oracle.oracle as orc
 from paper_1802_10453_amd import inputs
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_examples.json")
-PRIMES = [2, 3, 5, 7, 65521, 8388593]
+PRIMES = [2, 3, 5, 7, 65521, 8388593, 16777213]
 
 
 # ---------------------------------------------------------------- helpers (independent)
