@@ -73,24 +73,22 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_leaf(double* W, int64_t ld, i
     auto calive = [&](int q) -> bool { return (cbits >> q) & 1u; };
 
     // The delayed reduction holds while p + (products since the last reduction)
-    // * (p/2 + 2)^2 < 2^53: never within 128 steps for p < 2^23 (3 products per
-    // 2x2 step); for larger p every entry is reduced once the bound is near.
+    // * (p/2 + 2)^2 < 2^53: never within 128 steps for p < 2^23 (at most 3
+    // products per step); for larger p every entry is reduced at the start of a
+    // step (where little else is live) once the next step could pass the bound.
     const double hb = F.half + 2.0;
     const int prod_cap = (int)fmin(1.0e9, floor((9007199254740992.0 - 2.0 * F.p) / (hb * hb)));
     int since = 0;
-    auto reduce_before = [&](int next) {
-        if (since + next > prod_cap) {
+    int r = 0, nz = 0, step = 0;
+    for (int i = 0; i < s; ++i) {
+        if (!alive(i)) continue;
+        if (since + 3 > prod_cap) {
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < TW; ++b) m[a][b] = fredc(m[a][b], F);
             since = 0;
         }
-        since += next;
-    };
-    int r = 0, nz = 0, step = 0;
-    for (int i = 0; i < s; ++i) {
-        if (!alive(i)) continue;
         const int bI = step & 1;
         ++step;
         // owners of column i publish the reduced column
@@ -141,7 +139,7 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_leaf(double* W, int64_t ld, i
                 int l = c0 + b;
                 vc[b] = calive(b) ? colI[bI][l] : 0.0;
             }
-            reduce_before(1);
+            since += 1;
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -174,8 +172,9 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_leaf(double* W, int64_t ld, i
             if (tid == 0) { bx[r] = x; by[r] = (F.ip == 2) ? y : 0.0; bt[r] = 2; order[r] = i; order[r + 1] = j; }
             kill(i);
             kill(j);
-            // row coefficients e_k = x a_k, c_k = x b_k, f_k = d22 b_k; column coefficients b_l, a_l
-            double re[4], rc[4], rf[4], ra[4], cb[4], ca[4];
+            // row coefficients e_k + f_k (e_k = x a_k, f_k = d22 b_k) and c_k = x b_k;
+            // column coefficients b_l, a_l
+            double re[4], rc[4], ra[4], cb[4];
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
                 int k = r0 + a;
@@ -184,9 +183,8 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_leaf(double* W, int64_t ld, i
                 double bk = fredc(ci * xi, F);
                 double ek = fredc(cj - fredc(w * bk, F), F);
                 ra[a] = fredc(ek * xi, F);
-                re[a] = ek;
+                re[a] = ek + fredc(d22 * bk, F);   // |e + f| <= p + 4: counts as two products
                 rc[a] = ci;
-                rf[a] = fredc(d22 * bk, F);
                 cb[a] = bk;  // reused below for this thread's rows when writing L
             }
             double lb[TW], la[TW];
@@ -200,8 +198,8 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_leaf(double* W, int64_t ld, i
                 lb[b] = bl;
                 la[b] = fredc(el * xi, F);
             }
-            // S[k][l] -= x (a_k b_l + b_k a_l) + d22 b_k b_l = e_k b_l + c_k a_l + f_k b_l
-            reduce_before(3);
+            // S[k][l] -= x (a_k b_l + b_k a_l) + d22 b_k b_l = (e_k + f_k) b_l + c_k a_l
+            since += 3;
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -209,7 +207,6 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_leaf(double* W, int64_t ld, i
                     double t = m[a][b];
                     t = fma(-re[a], lb[b], t);
                     t = fma(-rc[a], la[b], t);
-                    t = fma(-rf[a], lb[b], t);
                     m[a][b] = t;
                 }
             if (tx == i / TW) {
