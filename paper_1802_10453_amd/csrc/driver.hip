@@ -745,8 +745,7 @@ struct Engine {
         REQUIRE(nc <= 65535 && mz <= 65535);
         T = ws.tmp2; ldT = mz; TR = nc; TC = mz; pR = ws.pidx; pC = ws.pidx + mz;
         LAUNCH(PLDL_CLASS_OTHER, k_copy2d, dim3(nblk(mz), (unsigned)nc), dim3(256), 0, st, T, mz, W + s0 * ld + lo, ld, nc, mz);
-        LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(mz)), dim3(256), 0, st, pR, mz);
-        LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(nc)), dim3(256), 0, st, pC, nc);
+        LAUNCH(PLDL_CLASS_OTHER, k_iota2, dim3(nblk(std::max(mz, nc))), dim3(256), 0, st, pR, mz, pC, nc);
         int64_t rY = plduq_all(mz, nc);
         if (rY > 0) {
             perm_sym(s0, hi, pC, 2, al, hi);
@@ -904,14 +903,12 @@ struct Engine {
     // bottom half of a row split is updated with the top half's pivots (TRSM,
     // GEMM) and continues on the columns the top half left.  On return row a0 + q
     // holds the row that was at a0 + srcR[q], column c0 + q the column that was at
-    // c0 + srcC[q] (the caller carries these orders to the parts it holds).
-    int64_t plduq_t(int64_t a0, int64_t a1, int64_t c0, int64_t c1, int32_t* srcR, int32_t* srcC) {
+    // c0 + srcC[q] (the caller carries these orders to the parts it holds); when
+    // *moved is false nothing moved and the orders (the identity) are not written.
+    int64_t plduq_t(int64_t a0, int64_t a1, int64_t c0, int64_t c1, int32_t* srcR, int32_t* srcC, bool* moved) {
         const int64_t m = a1 - a0;
-        if (m <= 0 || c1 <= c0) {   // nothing moves
-            if (m > 0) LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(m)), dim3(256), 0, st, srcR, m);
-            if (c1 > c0) LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(c1 - c0)), dim3(256), 0, st, srcC, c1 - c0);
-            return 0;
-        }
+        *moved = m > 0 && c1 > c0;
+        if (!*moved) return 0;
         REQUIRE(a1 <= TC && c1 <= TR);
         if (m <= 64) return plduq_slab(a0, a1, c0, c1, srcR, srcC);
         const int64_t ip_save = ip_top;
@@ -919,7 +916,8 @@ struct Engine {
         const int64_t h = am - a0, mb = a1 - am, len = c1 - c0;
         int32_t* sRt = ipush(h);
         int32_t* sCt = ipush(len);
-        const int64_t r1 = plduq_t(a0, am, c0, c1, sRt, sCt);
+        bool tmv = false, bmv = false;
+        const int64_t r1 = plduq_t(a0, am, c0, c1, sRt, sCt, &tmv);
         if (r1 > 0) {
             const int64_t ncr = len - r1;
             // the bottom rows take the top half's column order
@@ -936,7 +934,7 @@ struct Engine {
         }
         int32_t* sRb = ipush(mb);
         int32_t* sCb = ipush(std::max<int64_t>(len - r1, 1));
-        const int64_t r2 = plduq_t(am, a1, c0 + r1, c1, sRb, sCb);
+        const int64_t r2 = plduq_t(am, a1, c0 + r1, c1, sRb, sCb, &bmv);
         if (r2 > 0) {
             // the top rows take the bottom half's column order, the bottom rows' multipliers its row order
             tcolperm(c0 + r1, len - r1, sCb, a0, h);
@@ -950,9 +948,9 @@ struct Engine {
                 idx_reorder(pR, a0 + r1, rl, src);
             }
         }
-        // this call's orders, composed from its halves' (a bottom half without pivots moved nothing)
-        LAUNCH(PLDL_CLASS_OTHER, k_compose_cols, dim3(nblk(len)), dim3(256), 0, st, srcC, sCt, r1, sCb, len);
-        LAUNCH(PLDL_CLASS_OTHER, k_compose_rows, dim3(nblk(m)), dim3(256), 0, st, srcR, sRt, h, sRb, m, r1, r2);
+        // this call's orders, composed from its halves' (a half on which nothing moved: null)
+        LAUNCH(PLDL_CLASS_OTHER, k_compose, dim3(nblk(std::max(len, m))), dim3(256), 0, st, srcC, tmv ? sCt : nullptr,
+               bmv ? sCb : nullptr, len, srcR, tmv ? sRt : nullptr, bmv ? sRb : nullptr, h, m, r1, r2);
         ip_top = ip_save;
         return r1 + r2;
     }
@@ -961,7 +959,8 @@ struct Engine {
         const int64_t ip_save = ip_top;
         int32_t* sR = ipush(rows);
         int32_t* sC = ipush(cols);
-        const int64_t r = plduq_t(0, rows, 0, cols, sR, sC);
+        bool moved = false;
+        const int64_t r = plduq_t(0, rows, 0, cols, sR, sC, &moved);
         ip_top = ip_save;
         return r;
     }
@@ -1544,8 +1543,7 @@ int pldl_plduq(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, double* Y, int64
         Workspace& ws = ctx->ws;
         E.T = ws.tmp2; E.ldT = m; E.TR = n; E.TC = m; E.pR = ws.pidx; E.pC = ws.pidx + m;
         LAUNCH(PLDL_CLASS_OTHER, k_transpose, dim3(nblk(n), (unsigned)m), dim3(256), 0, st, E.T, m, Y, ldy, m, n);
-        LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(m)), dim3(256), 0, st, E.pR, m);
-        LAUNCH(PLDL_CLASS_OTHER, k_iota, dim3(nblk(n)), dim3(256), 0, st, E.pC, n);
+        LAUNCH(PLDL_CLASS_OTHER, k_iota2, dim3(nblk(std::max(m, n))), dim3(256), 0, st, E.pR, m, E.pC, n);
         int64_t r = E.plduq_all(m, n);
         LAUNCH(PLDL_CLASS_OTHER, k_transpose, dim3(nblk(m), (unsigned)n), dim3(256), 0, st, Y, ldy, E.T, m, n, m);
         HIPCHK(hipMemcpyAsync(rows, E.pR, m * sizeof(int32_t), hipMemcpyDeviceToDevice, st));

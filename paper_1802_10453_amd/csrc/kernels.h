@@ -62,9 +62,8 @@ __global__ void k_trsm_stripe(MatV B, int64_t m, int r, MatV T, const double* N,
 __global__ void k_inv_scatter(const int32_t* snap, int64_t len, int32_t* inv);
 __global__ void k_src_gather(const int32_t* cur, int64_t len, const int32_t* inv, int32_t* src);
 __global__ void k_rot_src(int64_t len, int64_t rot1, int32_t* src);
-__global__ void k_compose_cols(int32_t* src, const int32_t* top, int64_t r1, const int32_t* bot, int64_t len);
-__global__ void k_compose_rows(int32_t* src, const int32_t* top, int64_t h, const int32_t* bot, int64_t len,
-                               int64_t r1, int64_t r2);
+__global__ void k_compose(int32_t* srcc, const int32_t* topc, const int32_t* botc, int64_t len, int32_t* srcr,
+                          const int32_t* topr, const int32_t* botr, int64_t h, int64_t m, int64_t r1, int64_t r2);
 __global__ void k_reorder_src_1wg(const int32_t* snap, const int32_t* cur, int64_t len, int32_t* inv, int32_t* src);
 __global__ void k_idx_reorder_1wg(int32_t* idx, int64_t a, int64_t len, const int32_t* src);
 __global__ void k_tcolperm(double* T, int64_t ld, int64_t j0, int64_t len, const int32_t* src, int64_t i0,
@@ -125,6 +124,7 @@ __global__ void k_char2_std(double* W, int64_t ld, int64_t n, double* dd, double
                             int phase);
 
 __global__ void k_iota(int32_t* a, int64_t n);
+__global__ void k_iota2(int32_t* a, int64_t na, int32_t* b, int64_t nb);
 __global__ void k_zlp_sigma(int32_t* sig, int64_t mz, int64_t nc, int64_t rY);
 __global__ void k_apply_d(const double* A, int64_t lda, int64_t n, int64_t k, const double* dd, const double* de,
                           double* out, Field F);

@@ -302,27 +302,30 @@ __global__ __launch_bounds__(1024) void k_idx_reorder_1wg(int32_t* idx, int64_t 
     for (int64_t q = threadIdx.x; q < len; q += 1024) idx[a + q] = buf[q];
 }
 
-// The order a PLDUQ node leaves on its columns, from its halves' orders: the top
-// half reordered all len columns (top), the bottom half the columns after the top's
-// r1 pivot columns (bot, relative to r1).  src[q] = old position of the column now at q.
-__global__ void k_compose_cols(int32_t* src, const int32_t* top, int64_t r1, const int32_t* bot, int64_t len) {
+// The orders a PLDUQ node leaves on its columns and rows, from its halves'
+// orders (src[q] = old position of the entry now at q; a null order is the
+// identity: a half on which nothing moved).
+// Columns: the top half reordered all len columns (topc), the bottom half the
+// columns after the top's r1 pivot columns (botc, relative to r1).
+// Rows: the top half reordered rows [0, h) (topr), the bottom half rows
+// [h, m) (botr, relative to h); then, when the bottom half took pivots
+// (r2 > 0), the rotation that puts the bottom half's r2 pivot rows right after
+// the top half's r1 (the top's non-pivot rows follow them).
+__global__ void k_compose(int32_t* srcc, const int32_t* topc, const int32_t* botc, int64_t len, int32_t* srcr,
+                          const int32_t* topr, const int32_t* botr, int64_t h, int64_t m, int64_t r1, int64_t r2) {
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (q < len) src[q] = q < r1 ? top[q] : top[r1 + bot[q - r1]];
-}
-// The same for its rows: the top half reordered rows [0, h) (top), the bottom half
-// rows [h, len) (bot, relative to h); then, when the bottom half took pivots
-// (r2 > 0), the rotation that puts the bottom half's r2 pivot rows right after the
-// top half's r1 (the top's non-pivot rows follow them).
-__global__ void k_compose_rows(int32_t* src, const int32_t* top, int64_t h, const int32_t* bot, int64_t len,
-                               int64_t r1, int64_t r2) {
-    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (q >= len) return;
-    int64_t p = q;   // position before the rotation
-    if (r2 > 0 && q >= r1 && q < h + r2) {
-        const int64_t t = q - r1;
-        p = t < r2 ? h + t : r1 + (t - r2);
+    if (q < len) {
+        const int64_t t = q < r1 ? q : r1 + (botc ? botc[q - r1] : q - r1);
+        srcc[q] = topc ? topc[t] : (int32_t)t;
     }
-    src[q] = p < h ? top[p] : (int32_t)(h + bot[p - h]);
+    if (q < m) {
+        int64_t p = q;   // position before the rotation
+        if (r2 > 0 && q >= r1 && q < h + r2) {
+            const int64_t t = q - r1;
+            p = t < r2 ? h + t : r1 + (t - r2);
+        }
+        srcr[q] = p < h ? (topr ? topr[p] : (int32_t)p) : (int32_t)(h + (botr ? botr[p - h] : p - h));
+    }
 }
 
 // src[q] of the rotation that moves the first rot1 of len positions after the others
@@ -1338,6 +1341,12 @@ __global__ void k_char2_std(double* W, int64_t ld, int64_t n, double* dd, double
 __global__ void k_iota(int32_t* a, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < n) a[i] = (int32_t)i;
+}
+// both index vectors of a PLDUQ in one launch
+__global__ void k_iota2(int32_t* a, int64_t na, int32_t* b, int64_t nb) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < na) a[i] = (int32_t)i;
+    if (i < nb) b[i] = (int32_t)i;
 }
 
 // sigma (local old index) of the Algorithm 3 assembly order
