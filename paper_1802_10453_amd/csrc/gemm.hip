@@ -23,9 +23,10 @@ namespace pldl {
 
 namespace {
 constexpr int PAD = 2;   // LDS row padding (doubles): breaks the bank conflicts of the transposed tile stores
-// K depth of an LDS tile: 32 for the big tile (twice the matrix-core work per
-// barrier; measured 3-4% faster on the largest products), 16 for the small one
-template <int BM> constexpr int gemm_bk() { return BM == 128 ? 32 : 16; }
+// K depth of an LDS tile: 32 on both tiles (twice the matrix-core work per
+// barrier of 16: 3-4% faster on the largest products, and fewer barriers on the
+// short K loops of the small ones)
+template <int BM> constexpr int gemm_bk() { return 32; }
 // waves of a workgroup (up to BN/16 along n, the rest along m): more waves than
 // SIMDs let one wave's loads and barrier waits overlap another's matrix-core work
 constexpr int BIG_WAVES = 16, SMALL_WAVES = 16;
