@@ -210,6 +210,131 @@ __global__ __launch_bounds__(256) void k_gemm_i8(I8Args g) {
     stamp_end(g.stamp);
 }
 
+// Large products: workgroup tile 128 x 128, eight waves in a 2 x 4 grid, wave
+// tile 64 x 32 (4 x 2 MFMA blocks).  Each 64-deep K step of every limb plane
+// goes through LDS (double-buffered, one barrier per step; the next step's
+// global reads are in flight during the current step's products), so an A
+// fragment serves two B blocks and a B fragment four A blocks, all from LDS.
+// LDS rows are 80 bytes (64 of data): the 16-byte fragment reads of 16
+// consecutive rows then fall on distinct banks.
+constexpr int I8B_TILE = 128, I8B_ROW = 80, I8B_THREADS = 512;
+
+template <int L, bool LOWER_C>
+__global__ __launch_bounds__(I8B_THREADS) void k_gemm_i8_big(I8Args g) {
+    constexpr int NS = 2 * L - 1, T = I8B_TILE, RB = I8B_ROW;
+    constexpr int PLANE = T * RB;                 // bytes of one limb plane of one operand tile
+    __shared__ __attribute__((aligned(16))) int8_t lds[2 * 2 * L * PLANE];   // [buffer][A, B][limb][T][RB]
+    stamp_begin(g.stamp);
+    const int bid = blockIdx.x;
+    int ti, tj;
+    if (LOWER_C) {
+        ti = (int)((sqrt(8.0 * (double)bid + 1.0) - 1.0) * 0.5);
+        while ((ti + 1) * (ti + 2) / 2 <= bid) ++ti;
+        while (ti * (ti + 1) / 2 > bid) --ti;
+        tj = bid - ti * (ti + 1) / 2;
+    } else {
+        ti = bid / g.tiles_n;
+        tj = bid - ti * g.tiles_n;
+    }
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 2, wn = wave & 3;      // wave tile rows wm*64 .., columns wn*32 ..
+    const int r16 = lane & 15, kg = lane >> 4;
+    const int64_t ti0 = (int64_t)ti * T, tj0 = (int64_t)tj * T;
+    // this thread's share of a stage: row (or column) tid/4 of the tile, 16 bytes at k (tid%4)*16
+    const int lrow = tid >> 2, lk = (tid & 3) * 16;
+
+    v4i acc[4][2][NS];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int q = 0; q < NS; ++q) acc[x][y][q] = v4i{0, 0, 0, 0};
+
+#pragma unroll 1
+    for (int seg = 0; seg < 2; ++seg) {
+        const int64_t Kp = g.Kp[seg];
+        if (Kp <= 0) continue;
+        const int64_t pa = g.m * Kp, pb = g.n * Kp;
+        // rows / columns past the edge are clamped: their products land in outputs never stored
+        const int8_t* ga = g.A[seg] + min(ti0 + lrow, g.m - 1) * Kp + lk;
+        const int8_t* gb = g.B[seg] + min(tj0 + lrow, g.n - 1) * Kp + lk;
+        v4i ra[L], rb[L];
+        auto gload = [&](int64_t k0) {
+#pragma unroll
+            for (int t = 0; t < L; ++t) {
+                ra[t] = *(const v4i*)(ga + t * pa + k0);
+                rb[t] = *(const v4i*)(gb + t * pb + k0);
+            }
+        };
+        auto lstore = [&](int buf) {
+            int8_t* base = lds + buf * 2 * L * PLANE;
+#pragma unroll
+            for (int t = 0; t < L; ++t) {
+                *(v4i*)(base + t * PLANE + lrow * RB + lk) = ra[t];
+                *(v4i*)(base + (L + t) * PLANE + lrow * RB + lk) = rb[t];
+            }
+        };
+        __syncthreads();   // LDS of a previous segment fully read
+        gload(0);
+        lstore(0);
+        const int64_t nst = Kp / 64;
+        if (nst > 1) gload(64);
+        __syncthreads();
+        int cur = 0;
+#pragma unroll 1
+        for (int64_t st = 0; st < nst; ++st) {
+            const int8_t* A_l = lds + cur * 2 * L * PLANE;
+            const int8_t* B_l = A_l + L * PLANE;
+            v4i fb[2][L];
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int u = 0; u < L; ++u)
+                    fb[y][u] = *(const v4i*)(B_l + u * PLANE + (wn * 32 + y * 16 + r16) * RB + kg * 16);
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                v4i fa[L];
+#pragma unroll
+                for (int t = 0; t < L; ++t)
+                    fa[t] = *(const v4i*)(A_l + t * PLANE + (wm * 64 + x * 16 + r16) * RB + kg * 16);
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+#pragma unroll
+                    for (int t = 0; t < L; ++t)
+#pragma unroll
+                        for (int u = 0; u < L; ++u)
+                            acc[x][y][t + u] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[t], fb[y][u], acc[x][y][t + u],
+                                                                                    0, 0, 0);
+            }
+            if (st + 1 < nst) {
+                lstore(cur ^ 1);
+                if (st + 2 < nst) gload((st + 2) * 64);
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
+    }
+    // epilogue: lane l, register r of a block holds D[4*(l/16) + r][l%16]
+    const Field F = g.F;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = ti0 + wm * 64 + x * 16 + 4 * kg + r, col = tj0 + wn * 32 + y * 16 + r16;
+                if (row < g.m && col < g.n && (!LOWER_C || col <= row)) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) v = fma(fred((double)acc[x][y][q][r], F), g.w[q], v);
+                    double* c = g.C + row * g.ldc + col;
+                    *c = fred(*c - fred(v, F), F);
+                }
+            }
+    stamp_end(g.stamp);
+}
+
 template <int L>
 void split_launch(hipStream_t s, const Field& F, MatV X, int64_t rows, int64_t K, int64_t Kp, bool upper_mask,
                   int8_t* planes) {
@@ -217,8 +342,17 @@ void split_launch(hipStream_t s, const Field& F, MatV X, int64_t rows, int64_t K
     hipLaunchKernelGGL(k_split_i8<L>, grid, dim3(256), 0, s, X, rows, K, Kp, upper_mask ? 1 : 0, planes, F);
 }
 
+// The 128 x 128 tile once it still gives every compute unit a workgroup, else 64 x 64.
 template <int L>
-void gemm_launch(hipStream_t s, const I8Args& g, bool lower_c) {
+void gemm_launch(hipStream_t s, I8Args g, bool lower_c) {
+    const int64_t tmb = (g.m + I8B_TILE - 1) / I8B_TILE, tnb = (g.n + I8B_TILE - 1) / I8B_TILE;
+    const int64_t big = lower_c ? tmb * (tmb + 1) / 2 : tmb * tnb;
+    if (big >= 256) {
+        g.tiles_n = (int)tnb;
+        if (lower_c) hipLaunchKernelGGL((k_gemm_i8_big<L, true>), dim3((unsigned)big), dim3(I8B_THREADS), 0, s, g);
+        else hipLaunchKernelGGL((k_gemm_i8_big<L, false>), dim3((unsigned)big), dim3(I8B_THREADS), 0, s, g);
+        return;
+    }
     const int tm = (int)((g.m + 63) / 64);
     const int blocks = lower_c ? tm * (tm + 1) / 2 : tm * g.tiles_n;
     if (lower_c) hipLaunchKernelGGL((k_gemm_i8<L, true>), dim3(blocks), dim3(256), 0, s, g);

@@ -103,6 +103,76 @@ def test_i8_lower_only_and_syrd2k(ctx, p):
         assert (np.tril(host(Cd)) == np.tril(orc.syrd2k(p, C, A, B, dd, de))).all()
 
 
+# ---------------------------------------------------------------- the 128 x 128 INT8 tile
+# (products of at least 256 tiles of 128 x 128: LDS-staged limb planes, eight waves)
+@pytest.mark.parametrize("p", [251, 32749, 8388593])
+@pytest.mark.parametrize("tb", [0, 1])
+def test_i8_big_tile_dense(ctx, p, tb):
+    """m = n = 2048 (256 tiles), k = 600 (a ragged last 64-deep step): one, two and
+    three limbs against the oracle."""
+    g = inputs.rng(p * 3 + tb)
+    m = n = 2048
+    k = 600
+    print(f"[i8 big tile] dense p={p} tb={tb}", flush=True)
+    A, B, C = rnd(g, p, m, k), rnd(g, p, k, n), rnd(g, p, m, n)
+    Cd = dev(C)
+    ctx.gemm(p, Cd, dev(A), dev(B.T.copy() if tb else B), transB=bool(tb))
+    assert (host(Cd) == orc.gemm(p, C, A, B)).all()
+
+
+def test_i8_big_tile_ragged_edges(ctx):
+    """Ragged M, N and K edges on the big tile (2100 x 2050, k = 333, A transposed)."""
+    p = 8388593
+    g = inputs.rng(777)
+    m, n, k = 2100, 2050, 333
+    print("[i8 big tile] ragged", flush=True)
+    A, B, C = rnd(g, p, m, k), rnd(g, p, k, n), rnd(g, p, m, n)
+    Cd = dev(C)
+    ctx.gemm(p, Cd, dev(A.T.copy()), dev(B), transA=True)
+    assert (host(Cd) == orc.gemm(p, C, A, B)).all()
+
+
+@pytest.mark.parametrize("p", [32749, 8388593])
+def test_i8_big_tile_lower_syrd2k(ctx, p):
+    """SYRDK and SYRD2K of order 2900 (276 lower tiles of 128 x 128), k = 200: the
+    lower-triangle tile order and both segments in one accumulator set."""
+    g = inputs.rng(p + 55)
+    n, k = 2900, 200
+    print(f"[i8 big tile] syrd2k p={p}", flush=True)
+    A, B = rnd(g, p, n, k), rnd(g, p, n, k)
+    C = np.tril(rnd(g, p, n, n))
+    dd = rnd(g, p, k)
+    de = np.zeros(k, dtype=np.uint32)
+    for q in range(0, k - 1, 7):
+        de[q] = 1 + q
+        dd[q] = dd[q + 1] = 0
+    Cd = dev(C)
+    ctx.syrdk(p, Cd, dev(A), dev(dd), dev(de))
+    assert (np.tril(host(Cd)) == np.tril(orc.syrdk(p, C, A, dd, de))).all()
+    Cd = dev(C)
+    ctx.syrdk(p, Cd, dev(A), dev(dd), dev(de), B=dev(B))
+    assert (np.tril(host(Cd)) == np.tril(orc.syrd2k(p, C, A, B, dd, de))).all()
+
+
+@pytest.mark.parametrize("p,c", [(8388593, -32896), (32749, -16256)])
+def test_i8_big_tile_accumulation_bound(ctx, p, c):
+    """Every operand the residue with centered value c, whose two low balanced digits
+    are -128 (three limbs: shift class 1 then gains 2 * 128^2 = 2^15 per k, the
+    bound), with K = 65535, the longest product the INT32 classes take: the closed
+    form C - K c^2 mod p on the whole 2048 x 2048 output."""
+    m = n = 2048
+    k = 65535
+    v = c % p
+    print(f"[i8 big tile] bound p={p}", flush=True)
+    A = torch.full((m, k), float(v), dtype=torch.float64, device="cuda")
+    B = torch.full((k, n), float(v), dtype=torch.float64, device="cuda")
+    Cd = torch.full((m, n), float(p - 1), dtype=torch.float64, device="cuda")
+    ctx.gemm(p, Cd, A, B)
+    want = (p - 1 - (k * v * v) % p) % p
+    got = host(Cd)
+    assert (got == want).all(), (int(got[0, 0]), want)
+
+
 @pytest.mark.parametrize("p", [3, 65521, 8388593])
 def test_i8_trsm(ctx, p):
     g = inputs.rng(p + 9)
