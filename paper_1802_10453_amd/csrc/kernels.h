@@ -57,7 +57,7 @@ __global__ void k_bc_leaf(double* W, int64_t ld, int64_t lo, int s, Field F, con
 constexpr int TS_THREADS = 256, TS_COLS = 2;   // small TRSM: workgroup size, right-hand sides per wave
 __global__ void k_trsm_small(double* B, int64_t ldb, int64_t nrhs, int r, MatV T, int right, Field F);
 __global__ void k_ew3(MatV D, MatV X, MatV Y, MatV Z, int64_t rows, int64_t cols, int sx, int sy, int sz, Field F);
-constexpr int TSR = 32, TS_MAXR = 256;   // stripe TRSM: rows per workgroup, largest order
+constexpr int TSR = 16, TS_MAXR = 256;   // stripe TRSM: rows per workgroup, largest order
 __global__ void k_trsm_stripe(MatV B, int64_t m, int r, MatV T, const double* N, int n_trans, Field F);
 __global__ void k_inv_scatter(const int32_t* snap, int64_t len, int32_t* inv);
 __global__ void k_src_gather(const int32_t* cur, int64_t len, const int32_t* inv, int32_t* src);

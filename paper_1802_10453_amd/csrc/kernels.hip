@@ -672,7 +672,10 @@ __global__ __launch_bounds__(256) void k_trsm_stripe(MatV B, int64_t m, int r, M
     const int64_t s0 = (int64_t)blockIdx.x * TSR;
     const int rows = (int)min((int64_t)TSR, m - s0);
     const int nb = (r + 63) / 64, ntiles = nb * (nb + 1) / 2;
-    const int wr = (wave & 1) * 16, wc = (wave >> 1) * 32;   // this wave's 16 x 32 part of a 32 x 64 block
+    // NRT row tiles of 16 per stripe; this wave's 16 x (16 NRT) part of a TSR x 64 block
+    constexpr int NRT = TSR / 16;
+    static_assert(NRT * 16 == TSR && (NRT == 1 || NRT == 2), "stripe height");
+    const int wr = (wave % NRT) * 16, wc = (wave / NRT) * 16 * NRT;
     const bool t_kfast = T.rs == 1;                          // consecutive k of a T column are contiguous
     // tile t -> (j, i): i < j is T_ij, i == j is N_j
     auto decode = [&](int t, int& j, int& i) {
@@ -709,13 +712,15 @@ __global__ __launch_bounds__(256) void k_trsm_stripe(MatV B, int64_t m, int r, M
     double pre[PF][EPT];
 #pragma unroll
     for (int u = 0; u < PF; ++u) load_tile(u, pre[u]);
-    d4 acc[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
-    double bv[2][4];     // B_j of this thread's outputs, loaded when step j starts
-    double xv[2][4];     // X_{j-1}, written to LDS after the next barrier
+    d4 acc[NRT];
+#pragma unroll
+    for (int y = 0; y < NRT; ++y) acc[y] = d4{0.0, 0.0, 0.0, 0.0};
+    double bv[NRT][4];   // B_j of this thread's outputs, loaded when step j starts
+    double xv[NRT][4];   // X_{j-1}, written to LDS after the next barrier
     int xpend = -1;      // column block of the pending X values
     auto load_b = [&](int j) {
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < NRT; ++y)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int row = wr + lk + 4 * q, col = j * 64 + wc + 16 * y + lr;
@@ -729,7 +734,7 @@ __global__ __launch_bounds__(256) void k_trsm_stripe(MatV B, int64_t m, int r, M
         __syncthreads();   // Ts free; every wave is done reading Xs block xpend (as Y)
         if (xpend >= 0) {
 #pragma unroll
-            for (int y = 0; y < 2; ++y)
+            for (int y = 0; y < NRT; ++y)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) Xs[wr + lk + 4 * q][xpend * 64 + wc + 16 * y + lr] = fcen(xv[y][q], F);
             xpend = -1;
@@ -740,10 +745,10 @@ __global__ __launch_bounds__(256) void k_trsm_stripe(MatV B, int64_t m, int r, M
             tile_ab(t, q, a, b);
             Ts[a][b] = fcen(pre[0][q], F);
         }
-        double yv[2][4];
+        double yv[NRT][4];
         if (i == j) {   // Y_j = B_j - acc, the left operand of the N_j product
 #pragma unroll
-            for (int y = 0; y < 2; ++y)
+            for (int y = 0; y < NRT; ++y)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     yv[y][q] = fred(bv[y][q] - acc[y][q], F);
@@ -760,7 +765,7 @@ __global__ __launch_bounds__(256) void k_trsm_stripe(MatV B, int64_t m, int r, M
         if (i < j) {
             if (i > 0 && 64 * (i + 1) > F.kred) {   // (larger p only) keep the running sum below 2^53
 #pragma unroll
-                for (int y = 0; y < 2; ++y)
+                for (int y = 0; y < NRT; ++y)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) acc[y][q] = fredc(acc[y][q], F);
             }
@@ -768,20 +773,22 @@ __global__ __launch_bounds__(256) void k_trsm_stripe(MatV B, int64_t m, int r, M
             for (int kk = 0; kk < 64; kk += 4) {
                 const double a = Xs[wr + lr][i * 64 + kk + lk];
 #pragma unroll
-                for (int y = 0; y < 2; ++y)
+                for (int y = 0; y < NRT; ++y)
                     acc[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ts[kk + lk][wc + 16 * y + lr], acc[y], 0, 0, 0);
             }
         } else {
-            d4 acc2[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
+            d4 acc2[NRT];
+#pragma unroll
+            for (int y = 0; y < NRT; ++y) acc2[y] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int kk = 0; kk < 64; kk += 4) {
                 const double a = Xs[wr + lr][j * 64 + kk + lk];
 #pragma unroll
-                for (int y = 0; y < 2; ++y)
+                for (int y = 0; y < NRT; ++y)
                     acc2[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ts[kk + lk][wc + 16 * y + lr], acc2[y], 0, 0, 0);
             }
 #pragma unroll
-            for (int y = 0; y < 2; ++y)
+            for (int y = 0; y < NRT; ++y)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int row = wr + lk + 4 * q, col = j * 64 + wc + 16 * y + lr;
@@ -790,8 +797,8 @@ __global__ __launch_bounds__(256) void k_trsm_stripe(MatV B, int64_t m, int r, M
                     if (row < rows && col < r) B.p[(s0 + row) * B.rs + (int64_t)col * B.cs] = x;
                 }
             xpend = j;
-            acc[0] = d4{0.0, 0.0, 0.0, 0.0};
-            acc[1] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int y = 0; y < NRT; ++y) acc[y] = d4{0.0, 0.0, 0.0, 0.0};
             if (j + 1 < nb) load_b(j + 1);
         }
     }
