@@ -225,9 +225,9 @@ def main():
                     help="processes that build the batched input (-1: up to 16, 0: this process)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the base-case threshold with pldl_autotune before the warm-up (untimed)")
-    ap.add_argument("--path", default="f64", choices=["f64", "i8"],
-                    help="matrix cores of the products: FP64 with delayed reduction, or INT8 with residues "
-                         "split into signed bytes")
+    ap.add_argument("--path", default="auto", choices=["auto", "f64", "i8"],
+                    help="matrix cores of the products: the library's default (auto: INT8 split for p < 2^23, "
+                         "else FP64), FP64 with delayed reduction, or INT8 with residues split into signed bytes")
     ap.add_argument("--no-profile", action="store_true", help="time without per-launch events (no roofline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--winograd", type=int, default=0, metavar="MIN_ORDER",
@@ -259,7 +259,7 @@ def main():
     nrun = args.warmup + args.steps + (0 if args.no_profile else 1)
     copies = [A0.clone() for _ in range(nrun)]
     ctx = pldl.Context(0)
-    ctx.set_path(pldl.PLDL_PATH_I8 if args.path == "i8" else pldl.PLDL_PATH_F64)
+    ctx.set_path({"auto": pldl.PLDL_PATH_AUTO, "f64": pldl.PLDL_PATH_F64, "i8": pldl.PLDL_PATH_I8}[args.path])
     ctx.set_winograd(args.winograd)
     threshold_used = args.threshold or 128
     if args.autotune and not args.threshold:
@@ -310,13 +310,14 @@ def main():
         full = ctx.profile(0)
     r = out["rank"]
     sched = out["schedule"]   # of the last timed step: threshold, split rule, path, launches, host waits
+    path = "i8" if sched["path_used"] == pldl.PLDL_PATH_I8 else "f64"   # the path the steps took
     value = eff_ops(n, r) / (ms / 1e3) / 1e9
     roofline = None
     if stats is not None:
-        pr = PRODUCT[args.path]
+        pr = PRODUCT[path]
         g = stats[pr["cls"]]
-        traffic = measured_traffic(args.path, cfg["name"], n, p, r)
-        if args.path == "f64":
+        traffic = measured_traffic(path, cfg["name"], n, p, r)
+        if path == "f64":
             achieved = g["flops"] / (g["ms"] / 1e3) / 1e12 if g["ms"] > 0 else 0.0
             roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
                             frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=traffic,
@@ -352,9 +353,9 @@ def main():
         "metric": METRIC,
         "value": round(value, 2), "unit": "GOPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.path == "f64" else "i8", "data": "synthetic",
+        "dtype": "f64" if path == "f64" else "i8", "data": "synthetic",
         "config": {"workload": cfg["name"], "n": n, "p": p, "rank": r, "threshold": sched["threshold_used"],
-                   "path": "fp64-mfma" if args.path == "f64" else "int8-split-mfma",
+                   "path": "fp64-mfma" if path == "f64" else "int8-split-mfma",
                    "winograd_min_order": args.winograd, "input": "uint32 residues in HBM", "schedule": sched},
         "roofline": roofline, "cpu_baseline": cpu,
     }

@@ -42,7 +42,7 @@ extern "C" {
 
 #define PLDL_THRESHOLD_ONLINE (-1)  /* pldl_opts.threshold: chosen online by the context */
 
-#define PLDL_PATH_AUTO 0       /* the context's path (pldl_set_path; FP64 at creation) */
+#define PLDL_PATH_AUTO 0       /* the context's path (pldl_set_path; by prime at creation) */
 #define PLDL_PATH_F64 1        /* products on FP64 MFMA with delayed reduction         */
 #define PLDL_PATH_I8 2         /* products on INT8 MFMA: residues split into 1-3 signed
                                   bytes, INT32 accumulation, mod-p recombination         */
@@ -311,8 +311,10 @@ int pldl_syrdk_noalloc(pldl_ctx *ctx, uint32_t p, int64_t n, int64_t k, const do
 /*
  * Matrix cores used by the products (GEMM, TRMM, SYRDK, SYRD2K of Section 3)
  * of every later call on this context whose options say PLDL_PATH_AUTO, and of
- * the building-block calls above.  path: PLDL_PATH_F64 (default) or
- * PLDL_PATH_I8.  The INT8 path writes each operand as L signed-byte digit
+ * the building-block calls above.  path: PLDL_PATH_AUTO (the default at
+ * creation: pldl_factor takes the INT8 path when p < 2^23, where three
+ * balanced limbs cover the residues, and FP64 otherwise; the building-block
+ * calls take FP64), PLDL_PATH_F64 or PLDL_PATH_I8.  The INT8 path writes each operand as L signed-byte digit
  * planes (L = 1 for p < 2^8, 2 for p < 2^15, else 3) into a context buffer
  * grown on demand, and runs the L^2 byte products on v_mfma_i32_16x16x64_i8;
  * results are identical to the FP64 path (both are exact).  Inside

@@ -1026,7 +1026,7 @@ struct pldl_ctx {
     std::string err;
     uint32_t* itab = nullptr;  // inverse table of modulus itab_p
     uint32_t itab_p = 0;
-    int path = PLDL_PATH_F64;  // matrix cores of the products (pldl_set_path)
+    int path = PLDL_PATH_AUTO; // matrix cores of the products (pldl_set_path)
     GrowBuf i8;
     GrowBuf wbuf;              // Winograd temporaries
     int64_t wino_min = 0;      // pldl_set_winograd
@@ -1201,7 +1201,9 @@ int pldl_factor(pldl_ctx* ctx, uint32_t p, int64_t n, void* A, int64_t lda, int3
           : o.threshold == 0 ? ctx->tuned_threshold(p, n)
           : (n > 0 ? ctx->online_pick(p, n, &online_slot) : 128);
     const auto t_call = std::chrono::steady_clock::now();
-    const int path_used = o.path == PLDL_PATH_AUTO ? ctx->path : o.path;
+    // PLDL_PATH_AUTO: the INT8 split wherever its limbs cover the residues (p < 2^23)
+    int path_used = o.path == PLDL_PATH_AUTO ? ctx->path : o.path;
+    if (path_used == PLDL_PATH_AUTO) path_used = p < (1u << 23) ? PLDL_PATH_I8 : PLDL_PATH_F64;
     ctx->prof.reset_counts();
     auto fill_sched = [&]() {
         if (!sched_out) return;
@@ -1294,7 +1296,7 @@ int pldl_gemm(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, int64_t k, const 
         GemmSeg s{transA ? MatV{(double*)A, 1, lda} : MatV{(double*)A, lda, 1},
                   transB ? MatV{(double*)B, 1, ldb} : MatV{(double*)B, ldb, 1}, k};
         Engine E(ctx->ws, st, p, 0, 128, &ctx->prof);
-        ctx->setup(E, ctx->path, 0.0);
+        ctx->setup(E, ctx->path == PLDL_PATH_I8 ? PLDL_PATH_I8 : PLDL_PATH_F64, 0.0);
         double outs = lower_only ? (double)m * (double)(m + 1) / 2.0 : (double)m * (double)n;
         if (m > 0 && n > 0 && k > 0) E.mm(C, ldc, m, n, &s, 1, lower_only != 0, false, 2.0 * outs * (double)k);
         HIPCHK(hipGetLastError());
@@ -1317,7 +1319,7 @@ int pldl_trsm(pldl_ctx* ctx, uint32_t p, int32_t lower, int64_t m, int64_t n, co
     return guarded(ctx, [&]() {
         ctx->ws.ensure(1);
         Engine E(ctx->ws, st, p, 0, 128, &ctx->prof);
-        ctx->setup(E, ctx->path, 0.0);
+        ctx->setup(E, ctx->path == PLDL_PATH_I8 ? PLDL_PATH_I8 : PLDL_PATH_F64, 0.0);
         if (lower) E.trsm_ll(MatV{B, ldb, 1}, m, n, MatV{(double*)T, ldt, 1});
         else E.trsm_ru(MatV{B, ldb, 1}, m, n, MatV{(double*)T, ldt, 1});
         HIPCHK(hipGetLastError());
@@ -1354,7 +1356,7 @@ int pldl_syrdk(pldl_ctx* ctx, uint32_t p, int64_t n, int64_t k, const double* A,
         }
         GemmSeg segs[2] = {s0, s1};
         Engine E(ctx->ws, st, p, 0, 128, &ctx->prof);
-        ctx->setup(E, ctx->path, 0.0);
+        ctx->setup(E, ctx->path == PLDL_PATH_I8 ? PLDL_PATH_I8 : PLDL_PATH_F64, 0.0);
         E.mm(C, ldc, n, n, segs, 2, true, false, 2.0 * (double)n * (double)(n + 1) / 2.0 * (double)(B ? 2 * k : k));
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
@@ -1419,7 +1421,7 @@ int pldl_solve(pldl_ctx* ctx, uint32_t p, int64_t n, const void* F, int64_t lda,
         ctx->ws.ensure(n);
         Workspace& ws = ctx->ws;
         Engine E(ws, st, p, n, 128, &ctx->prof);
-        ctx->setup(E, ctx->path, 0.0);
+        ctx->setup(E, ctx->path == PLDL_PATH_I8 ? PLDL_PATH_I8 : PLDL_PATH_F64, 0.0);
         E.itab = ctx->inv_table(p, st);
         Prof* prof = &ctx->prof;
         const Field Fl = E.F;
@@ -1496,7 +1498,7 @@ int pldl_trss(pldl_ctx* ctx, uint32_t p, int64_t n, const double* U, int64_t ldu
         int64_t N2 = 2 * n;
         ctx->ws.ensure(N2);
         Engine E(ctx->ws, st, p, N2, 128, &ctx->prof);
-        ctx->setup(E, ctx->path, 0.0);
+        ctx->setup(E, ctx->path == PLDL_PATH_I8 ? PLDL_PATH_I8 : PLDL_PATH_F64, 0.0);
         Prof* prof = &ctx->prof;
         Workspace& ws = ctx->ws;
         HIPCHK(hipMemsetAsync(ws.info, 0, sizeof(int32_t) * 4, st));
@@ -1537,7 +1539,7 @@ int pldl_plduq(pldl_ctx* ctx, uint32_t p, int64_t m, int64_t n, double* Y, int64
         }
         ctx->ws.ensure(std::max(m, n));
         Engine E(ctx->ws, st, p, std::max(m, n), 128, &ctx->prof);
-        ctx->setup(E, ctx->path, 0.0);
+        ctx->setup(E, ctx->path == PLDL_PATH_I8 ? PLDL_PATH_I8 : PLDL_PATH_F64, 0.0);
         E.itab = ctx->inv_table(p, st);
         Prof* prof = &ctx->prof;
         Workspace& ws = ctx->ws;
@@ -1772,7 +1774,8 @@ int pldl_set_winograd(pldl_ctx* ctx, int64_t min_order) {
 
 int pldl_set_path(pldl_ctx* ctx, int32_t path) {
     if (!ctx) return -1;
-    if (path != PLDL_PATH_F64 && path != PLDL_PATH_I8) return fail(ctx, -2, "path must be PLDL_PATH_F64 or PLDL_PATH_I8");
+    if (path != PLDL_PATH_AUTO && path != PLDL_PATH_F64 && path != PLDL_PATH_I8)
+        return fail(ctx, -2, "path must be PLDL_PATH_AUTO, PLDL_PATH_F64 or PLDL_PATH_I8");
     ctx->path = path;
     return PLDL_OK;
 }

@@ -140,7 +140,8 @@ class Context:
 
     # ------------------------------------------------------------------ pldl_factor
     def set_path(self, path: int):
-        """pldl_set_path: PLDL_PATH_F64 or PLDL_PATH_I8 for the products of later calls."""
+        """pldl_set_path: PLDL_PATH_AUTO (INT8 products in pldl_factor for p < 2^23), PLDL_PATH_F64 or
+        PLDL_PATH_I8 for the products of later calls."""
         self._check(_lib.pldl_set_path(self._h, int(path)))
 
     def set_winograd(self, min_order: int):

@@ -129,7 +129,7 @@ def test_i8_factor_crosses_product_cut(ctx, p, n, f, c):
         out = ctx.factor(Ad, p)
         torch.cuda.synchronize()
     finally:
-        ctx.set_path(pldl.PLDL_PATH_F64)
+        ctx.set_path(pldl.PLDL_PATH_AUTO)
     sc = out["schedule"]
     assert sc["path_used"] == pldl.PLDL_PATH_I8
     assert sc["products_i8"] > 0, sc
@@ -176,7 +176,7 @@ def test_i8_syrd2k_accumulation_bound(ctx):
         assert st["gemm_i8"]["launches"] > 0
         assert (host(Cd) == (-k * a * a) % p).all()
     finally:
-        ctx.set_path(pldl.PLDL_PATH_F64)
+        ctx.set_path(pldl.PLDL_PATH_AUTO)
 
 
 # ---------------------------------------------------------------- pldl_factor's error returns
@@ -242,11 +242,13 @@ def test_factor_range_error_and_schedule(ctx):
     torch.cuda.synchronize()
     assert torch.equal(Ad, Ar) and torch.equal(out_bad["perm"], out_red["perm"])
     # a valid input: schedule fields
+    ctx.set_path(pldl.PLDL_PATH_AUTO)
     Ad = torch.from_numpy(A.astype(np.int32)).cuda()
     out = ctx.factor(Ad, p, threshold=48)
     sc = out["schedule"]
     assert sc["threshold_used"] == 48 and sc["split_rule"] == 64
-    assert sc["path_used"] == pldl.PLDL_PATH_F64 and sc["products_i8"] == 0
+    # the context's default path takes INT8 products for p < 2^23, none this small
+    assert sc["path_used"] == pldl.PLDL_PATH_I8 and sc["products_i8"] == 0
     assert sc["products_f64"] > 0 and sc["launches"] > sc["products_f64"] and sc["host_waits"] >= 1
 
 

@@ -42,7 +42,7 @@ def test_c2_full_size(ctx, c2_input, path):
     try:
         res = gpu_factor(ctx, A, cfg["p"])
     finally:
-        ctx.set_path(pldl.PLDL_PATH_F64)
+        ctx.set_path(pldl.PLDL_PATH_AUTO)
     assert res["rank"] == cfg["f"] + 2 * cfg["c"]
     assert (res["rpm"] == rpm).all()
     structure(res, cfg["p"])

@@ -87,7 +87,7 @@ def test_winograd_int8_path(ctx):
         torch.cuda.synchronize()
     finally:
         ctx.set_winograd(0)
-        ctx.set_path(pldl.PLDL_PATH_F64)
+        ctx.set_path(pldl.PLDL_PATH_AUTO)
     assert (host(Cd) == orc.gemm(p, C, A, B)).all()
 
 
