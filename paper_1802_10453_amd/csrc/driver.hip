@@ -428,8 +428,7 @@ struct Engine {
                                              flops * (double)(L * L));
                 i8_run(st, F, pr, C, ldc, lower, sp);
                 prof->end(st);
-                for (int q = 0; q < nseg; ++q) prof->n_launch += (segs[q].k > 0) ? 2 : 0;
-                prof->n_launch++;
+                prof->n_launch += 2;   // the limb split of every operand, the product
                 prof->n_i8++;
                 return;
             }

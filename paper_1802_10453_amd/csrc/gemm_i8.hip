@@ -19,8 +19,9 @@
 // (65535 * 2^15 < 2^31); a longer product falls back to FP64.
 //
 // Operands are first split into K-contiguous limb planes (one pass, 8 bytes
-// read and L bytes written per element; K padded to a multiple of 64 with
-// zeros): plane t of A is m x Kp, plane t of B holds B^T (n x Kp).  A wave's
+// read and L bytes written per element, every operand of a product in one
+// launch; K padded to a multiple of 64 with zeros): plane t of A is m x Kp,
+// plane t of B holds B^T (n x Kp).  A wave's
 // MFMA fragment is then 16 contiguous bytes per lane: lane l takes row l%16
 // (of A) or column l%16 (of B^T) and the k-group l/16 of each 64-wide K step,
 // the same k map on both sides as the instruction requires.
@@ -52,12 +53,31 @@ __device__ __forceinline__ void split_digits(double v, const Field& F, int8_t* d
 // rows x Kp int8.  upper_mask: X(i, k) is taken as 0 for k > i (the TRMM
 // triangle of B, seen transposed).  A 64 x 64 tile goes through LDS so that the
 // global reads follow whichever stride is 1.
+// All the operands of one product are split in one launch: blocks
+// [blk0[q], blk0[q+1]) take operand q, 64 x 64 tiles in row-major order of its
+// (rows / 64) x (Kp / 64) tile grid.
+struct SplitArgs {
+    MatV X[4];
+    int64_t rows[4], K[4], Kp[4];
+    int upper[4];
+    int8_t* planes[4];
+    int64_t blk0[5];
+    int nx;
+};
+
 template <int L>
-__global__ __launch_bounds__(256) void k_split_i8(MatV X, int64_t rows, int64_t K, int64_t Kp, int upper_mask,
-                                                  int8_t* planes, Field F) {
+__global__ __launch_bounds__(256) void k_split_i8(SplitArgs sa, Field F) {
     __shared__ double tile[SPLIT_T][SPLIT_T + 1];
     const int tid = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.y * SPLIT_T, k0 = (int64_t)blockIdx.x * SPLIT_T;
+    const int64_t blk = blockIdx.x;
+    int op = 0;
+    while (op + 1 < sa.nx && blk >= sa.blk0[op + 1]) ++op;
+    const MatV X = sa.X[op];
+    const int64_t rows = sa.rows[op], K = sa.K[op], Kp = sa.Kp[op];
+    const int upper_mask = sa.upper[op];
+    int8_t* planes = sa.planes[op];
+    const int64_t local = blk - sa.blk0[op], kt = Kp / SPLIT_T;
+    const int64_t r0 = (local / kt) * SPLIT_T, k0 = (local % kt) * SPLIT_T;
     const bool kfast = X.cs == 1;
 #pragma unroll
     for (int e = 0; e < SPLIT_T * SPLIT_T / 256; ++e) {
@@ -336,18 +356,17 @@ __global__ __launch_bounds__(I8B_THREADS) void k_gemm_i8_big(I8Args g) {
 }
 
 template <int L>
-void split_launch(hipStream_t s, const Field& F, MatV X, int64_t rows, int64_t K, int64_t Kp, bool upper_mask,
-                  int8_t* planes) {
-    dim3 grid((unsigned)(Kp / SPLIT_T), (unsigned)((rows + SPLIT_T - 1) / SPLIT_T));
-    hipLaunchKernelGGL(k_split_i8<L>, grid, dim3(256), 0, s, X, rows, K, Kp, upper_mask ? 1 : 0, planes, F);
+void split_launch(hipStream_t s, const Field& F, const SplitArgs& sa) {
+    hipLaunchKernelGGL(k_split_i8<L>, dim3((unsigned)sa.blk0[sa.nx]), dim3(256), 0, s, sa, F);
 }
 
-// The 128 x 128 tile once it still gives every compute unit a workgroup, else 64 x 64.
+// The 128 x 128 tile from 128 such tiles (half the compute units; measured a little faster
+// than the 64 x 64 tile there), else 64 x 64.
 template <int L>
 void gemm_launch(hipStream_t s, I8Args g, bool lower_c) {
     const int64_t tmb = (g.m + I8B_TILE - 1) / I8B_TILE, tnb = (g.n + I8B_TILE - 1) / I8B_TILE;
     const int64_t big = lower_c ? tmb * (tmb + 1) / 2 : tmb * tnb;
-    if (big >= 256) {
+    if (big >= 128) {
         g.tiles_n = (int)tnb;
         if (lower_c) hipLaunchKernelGGL((k_gemm_i8_big<L, true>), dim3((unsigned)big), dim3(I8B_THREADS), 0, s, g);
         else hipLaunchKernelGGL((k_gemm_i8_big<L, false>), dim3((unsigned)big), dim3(I8B_THREADS), 0, s, g);
@@ -385,6 +404,13 @@ bool i8_prepare(hipStream_t s, const Field& F, int64_t m, int64_t n, const GemmS
     *out = I8Product{};
     out->m = m; out->n = n; out->L = L;
     int8_t* cur = ws;
+    SplitArgs sa{};
+    auto add = [&](MatV X, int64_t rows, int64_t K, int64_t Kp, bool upper, int8_t* planes) {
+        const int q = sa.nx++;
+        sa.X[q] = X; sa.rows[q] = rows; sa.K[q] = K; sa.Kp[q] = Kp; sa.upper[q] = upper ? 1 : 0;
+        sa.planes[q] = planes;
+        sa.blk0[q + 1] = sa.blk0[q] + (rows + SPLIT_T - 1) / SPLIT_T * (Kp / SPLIT_T);
+    };
     for (int i = 0; i < 2; ++i) {
         if (i >= nseg || segs[i].k <= 0) continue;
         const int64_t K = segs[i].k, Kp = (K + 63) / 64 * 64;
@@ -394,11 +420,15 @@ bool i8_prepare(hipStream_t s, const Field& F, int64_t m, int64_t n, const GemmS
         cur += (256 - ((uintptr_t)cur & 255)) & 255;
         // B^T (n x K): element (j, k) = B(k, j)
         const MatV bt{segs[i].B.p, segs[i].B.cs, segs[i].B.rs};
-        const bool mask = b_upper && i == 0;
-        if (L == 1) { split_launch<1>(s, F, segs[i].A, m, K, Kp, false, ap); split_launch<1>(s, F, bt, n, K, Kp, mask, bp); }
-        if (L == 2) { split_launch<2>(s, F, segs[i].A, m, K, Kp, false, ap); split_launch<2>(s, F, bt, n, K, Kp, mask, bp); }
-        if (L == 3) { split_launch<3>(s, F, segs[i].A, m, K, Kp, false, ap); split_launch<3>(s, F, bt, n, K, Kp, mask, bp); }
+        add(segs[i].A, m, K, Kp, false, ap);
+        add(bt, n, K, Kp, b_upper && i == 0, bp);
         out->A[i] = ap; out->B[i] = bp; out->Kp[i] = Kp;
+    }
+    if (sa.nx > 0) {
+        if (sa.blk0[sa.nx] >= ((int64_t)1 << 31)) return false;
+        if (L == 1) split_launch<1>(s, F, sa);
+        if (L == 2) split_launch<2>(s, F, sa);
+        if (L == 3) split_launch<3>(s, F, sa);
     }
     return true;
 }

@@ -104,7 +104,7 @@ def test_i8_lower_only_and_syrd2k(ctx, p):
 
 
 # ---------------------------------------------------------------- the 128 x 128 INT8 tile
-# (products of at least 256 tiles of 128 x 128: LDS-staged limb planes, eight waves)
+# (products of at least 128 tiles of 128 x 128: LDS-staged limb planes, eight waves)
 @pytest.mark.parametrize("p", [251, 32749, 8388593])
 @pytest.mark.parametrize("tb", [0, 1])
 def test_i8_big_tile_dense(ctx, p, tb):
