@@ -135,8 +135,9 @@ int pldl_factor(pldl_ctx *ctx, uint32_t p, int64_t n, void *A, int64_t lda, int3
 /*
  * pldl_factor_batched -- `batch` independent factorizations (each as
  * pldl_factor, order n_b <= 512) in one persistent launch: workgroups take
- * matrices from a device counter, so uneven orders and ranks balance by
- * themselves.  Each matrix is factored by the base-case elimination of
+ * matrices from a device counter, largest order first (a counting sort on the
+ * device), so uneven orders and ranks balance and the last matrices started
+ * are the small ones.  Each matrix is factored by the base-case elimination of
  * Section 5 (rows in increasing order, lexicographically first nonzero of the
  * Schur-complement row as pivot, 1x1 / 2x2 blocks, relaxed 2x2 blocks in
  * characteristic 2, zero rows set aside): perm is that elimination's
@@ -153,10 +154,11 @@ int pldl_factor(pldl_ctx *ctx, uint32_t p, int64_t n, void *A, int64_t lda, int3
  *  opts           may be NULL; threshold and path are ignored; standard_form
  *                 must be 0 (-13).
  * The call is asynchronous (no host synchronisation: read rank and status
- * after synchronising `stream`) and launches two kernels, so it can be
+ * after synchronising `stream`) and launches three kernels, so it can be
  * captured in a HIP graph.  The first call on a context allocates its
- * workspace (two workgroup slots per compute unit, 2 MiB each) and the inverse
- * table of p: make that first call outside a capture.  Per-matrix pointers are
+ * workspace (four workgroup slots per compute unit, 1 MiB each) and the
+ * inverse table of p and the order array (int32, 65536 entries, grown by a
+ * larger batch than every earlier one): make such calls outside a capture.  Per-matrix pointers are
  * trusted (the host cannot check device arrays without synchronising).
  */
 int pldl_factor_batched(pldl_ctx *ctx, uint32_t p, int64_t batch, const int64_t *n, void *const *A,

@@ -53,7 +53,8 @@ struct BatchArgs {
     int64_t* rank;
     int32_t* status;
     float* ws;           // one NB_MAX^2 slot per workgroup
-    int32_t* queue;      // next matrix index
+    int32_t* queue;      // next position in `order`
+    const int32_t* order; // matrix indices, largest order first
     Field F;
     int check_range;
 };
@@ -154,7 +155,10 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(8))) void k
     for (int q = tid; q < KMAX * NB_MAX; q += NTH) (&sh.v[0][0])[q] = 0.0f;
 
     for (;;) {
-        if (tid == 0) sh.m = atomicAdd(g.queue, 1);
+        if (tid == 0) {
+            const int64_t q = atomicAdd(g.queue, 1);
+            sh.m = q < g.batch ? (int64_t)g.order[q] : g.batch;
+        }
         __syncthreads();
         const int64_t mi = sh.m;
         __syncthreads();
@@ -344,6 +348,34 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(8))) void k
 
 __global__ void k_zero_counter(int32_t* q) { *q = 0; }
 
+// The order the workgroups take the matrices in: largest n first (a counting
+// sort on n by one workgroup; invalid orders last).  Started largest-first, the
+// persistent workgroups finish together: taken in index order, a batch of
+// mixed orders leaves a tail of large matrices started last.
+__global__ __launch_bounds__(1024) void k_batch_order(const int64_t* n, int64_t batch, int32_t* order) {
+    constexpr int NBK = NB_MAX + 2;   // bucket NB_MAX - n for 0 <= n <= NB_MAX, NB_MAX + 1 for the rest
+    __shared__ int cnt[NBK];
+    const int tid = threadIdx.x;
+    auto key = [&](int64_t i) -> int {
+        const int64_t v = n[i];
+        return (v >= 0 && v <= NB_MAX) ? NB_MAX - (int)v : NB_MAX + 1;
+    };
+    for (int b = tid; b < NBK; b += 1024) cnt[b] = 0;
+    __syncthreads();
+    for (int64_t i = tid; i < batch; i += 1024) atomicAdd(&cnt[key(i)], 1);
+    __syncthreads();
+    if (tid == 0) {   // exclusive prefix sums: the first position of each bucket
+        int run = 0;
+        for (int b = 0; b < NBK; ++b) {
+            const int c = cnt[b];
+            cnt[b] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int64_t i = tid; i < batch; i += 1024) order[atomicAdd(&cnt[key(i)], 1)] = (int32_t)i;
+}
+
 }  // namespace
 
 int batched_nb_max() { return NB_MAX; }
@@ -355,12 +387,13 @@ size_t batched_slot_bytes() { return (size_t)NB_MAX * NB_MAX * sizeof(float); }
 void launch_factor_batched(hipStream_t s, const Field& F, const uint32_t* itab, int64_t batch, const int64_t* n,
                            void* const* A, const int64_t* lda, int32_t dtype, void* const* e, int32_t* const* perm,
                            int32_t* const* rpm, int64_t* rank, int32_t* status, int check_range, void* ws,
-                           int slots, int32_t* queue) {
+                           int slots, int32_t* queue, int32_t* order) {
     BatchArgs g{};
     g.batch = batch; g.n = n; g.A = A; g.lda = lda; g.dtype = dtype; g.e = e; g.perm = perm; g.rpm = rpm;
-    g.rank = rank; g.status = status; g.ws = (float*)ws; g.queue = queue; g.F = F;
+    g.rank = rank; g.status = status; g.ws = (float*)ws; g.queue = queue; g.order = order; g.F = F;
     g.check_range = check_range;
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, queue);
+    hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, s, n, batch, order);
     hipLaunchKernelGGL(k_factor_batched, dim3((unsigned)slots), dim3(NTH), 0, s, g, itab);
 }
 

@@ -125,7 +125,8 @@ size_t batched_slot_bytes();
 void launch_factor_batched(hipStream_t s, const Field& F, const uint32_t* itab, int64_t batch, const int64_t* n,
                            void* const* A, const int64_t* lda, int32_t dtype, void* const* e, int32_t* const* perm,
                            int32_t* const* rpm, int64_t* rank, int32_t* status, int check_range, void* ws,
-                           int slots, int32_t* queue);
+                           int slots, int32_t* queue,
+                           int32_t* order);
 
 // Longest K (summed over the segments of one product) the INT8 split accumulates
 // exactly in INT32: a shift class gains at most 2^15 per k, 65535 * 2^15 < 2^31.

@@ -1091,6 +1091,8 @@ struct pldl_ctx {
     void* bws = nullptr;       // batched factorizations: one slot per persistent workgroup
     int bslots = 0;
     int32_t* bqueue = nullptr;
+    int32_t* border = nullptr;   // the batch's matrix order (largest first), grown to the largest batch
+    int64_t border_cap = 0;
     // an Engine on this context's workspace, products on `path`
     void setup(Engine& E, int pth, double i8_min) {
         E.path = pth;
@@ -1170,6 +1172,7 @@ int pldl_destroy(pldl_ctx* ctx) {
     ctx->wbuf.release();
     if (ctx->bws) (void)hipFree(ctx->bws);
     if (ctx->bqueue) (void)hipFree(ctx->bqueue);
+    if (ctx->border) (void)hipFree(ctx->border);
     if (ctx->itab) (void)hipFree(ctx->itab);
     delete ctx;
     return PLDL_OK;
@@ -1589,11 +1592,26 @@ int pldl_factor_batched(pldl_ctx* ctx, uint32_t p, int64_t batch, const int64_t*
             }
             ctx->bslots = slots;
         }
+        if (batch > ctx->border_cap) {   // (at least 65536 entries; a larger batch than that allocates)
+            const int64_t cap = std::max<int64_t>(batch, (int64_t)1 << 16);
+            if (ctx->border) {
+                HIPCHK(hipStreamSynchronize(st));
+                (void)hipFree(ctx->border);
+            }
+            ctx->border = nullptr;
+            ctx->border_cap = 0;
+            if (hipMalloc((void**)&ctx->border, (size_t)cap * sizeof(int32_t)) != hipSuccess) {
+                (void)hipGetLastError();
+                ctx->border = nullptr;
+                throw Err(PLDL_ENOMEM, "batched order allocation failed");
+            }
+            ctx->border_cap = cap;
+        }
         const uint32_t* itab = ctx->inv_table(p, st);
         Field F = make_field(p);
         ctx->prof.begin(st, PLDL_CLASS_BASE_CASE);
         launch_factor_batched(st, F, itab, batch, n, A, lda, dtype, e, perm, rpm, rank, status, o.check_range,
-                              ctx->bws, ctx->bslots, ctx->bqueue);
+                              ctx->bws, ctx->bslots, ctx->bqueue, ctx->border);
         ctx->prof.end(st);
         HIPCHK(hipGetLastError());
     });
