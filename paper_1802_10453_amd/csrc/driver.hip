@@ -544,7 +544,10 @@ struct Engine {
     // rows past it take it later, composed with the enclosing range's own order
     // (see recall).
     int64_t n_perms = 0;   // symmetric permutations applied so far
-    void perm_sym(int64_t lo, int64_t hi, const int32_t* sig, int parts, int64_t al, int64_t below) {
+    // skip_ident: sig may be the identity (a leaf's, queued before the host has seen
+    // it); the kernels then move nothing.
+    void perm_sym(int64_t lo, int64_t hi, const int32_t* sig, int parts, int64_t al, int64_t below,
+                  bool skip_ident = false) {
         const int64_t s = hi - lo;
         if (s <= 1) return;
         REQUIRE(below >= hi && below <= n);
@@ -556,7 +559,7 @@ struct Engine {
         // rows below in one pass through LDS when a row segment fits
         const bool below1 = (parts & 4) && below > hi && s <= SEG_PERM_LDS;
         PermGeom g{};
-        g.n = n; g.lo = lo; g.hi = hi; g.s = s; g.c0 = c0; g.parts = parts;
+        g.n = n; g.lo = lo; g.hi = hi; g.s = s; g.c0 = c0; g.parts = parts; g.skip_ident = skip_ident ? 1 : 0;
         g.nb0 = nblk(std::max<int64_t>(lo - c0, 1), 256 * PERM_EPT);
         g.nb1 = nblk(s, 256 * PERM_EPT);
         g.B0 = ((parts & 1) && lo > c0) ? s * g.nb0 : 0;
@@ -579,7 +582,7 @@ struct Engine {
             const int64_t nwg = (below - hi + rpw - 1) / rpw;
             REQUIRE(nwg < ((int64_t)1 << 31));
             hipLaunchKernelGGL(k_seg_perm, dim3((unsigned)nwg), dim3(256), (size_t)rpw * s * sizeof(double), st, W, ld,
-                               lo, s, hi, below, sig, rpw);
+                               lo, s, hi, below, sig, rpw, skip_ident ? 1 : 0);
             prof->n_launch += 1;
         }
         prof->end(st);
@@ -677,12 +680,11 @@ struct Engine {
         const int32_t gen = next_hgen();
         LAUNCH(PLDL_CLASS_BASE_CASE, k_bc_leaf, dim3(1), dim3(BC_THREADS), 0, st, W, ld, lo, s, F, itab, ws.dd, ws.de, ws.sig,
                ws.hinfo_dev, ws.hinfo_dev + 1, ws.hinfo_dev + HW_FLAG, gen);
+        // the leaf's order applied to the rows left of and below it, queued behind the leaf
+        // before the host waits for its rank (the kernels skip an identity order)
+        perm_sym(lo, hi, ws.sig, 1 | 4 | 8, al, below, true);
         int32_t* h = wait_leaf(gen);
-        int64_t r = h[0];
-        bool ident = true;
-        for (int q = 0; q < s; ++q) ident &= (h[1 + q] == q);
-        if (!ident) perm_sym(lo, hi, ws.sig, 1 | 4 | 8, al, below);
-        return r;
+        return h[0];
     }
 
     // ---- Algorithm 2 -----------------------------------------------------------
@@ -877,7 +879,7 @@ struct Engine {
             const int rpw = (int)std::max<int64_t>(1, SEG_PERM_ROWS_LDS / len);
             const int64_t nwg = (nj + rpw - 1) / rpw;
             hipLaunchKernelGGL(k_seg_perm, dim3((unsigned)nwg), dim3(256), (size_t)rpw * len * sizeof(double), st, T,
-                               ldT, i0, len, j0, j0 + nj, src, rpw);
+                               ldT, i0, len, j0, j0 + nj, src, rpw, 0);
             prof->n_launch += 1;
         } else {
             dim3 g(nblk(len), (unsigned)nj);

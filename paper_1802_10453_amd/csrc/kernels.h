@@ -78,7 +78,7 @@ __global__ void k_zlp_sigma_total(int32_t* sig, int64_t mz, int64_t nc, int64_t 
                                   const int32_t* pC);
 __global__ void k_trinv_blocks(MatV T, int64_t r, int lower, double* N, Field F);
 __global__ void k_trss_leaf(double* W, int64_t ld, int64_t s0, int64_t u0, int r, Field F);
-struct PermGeom { int64_t n, lo, hi, s, c0, nb0, nb1, B0, B1, B2, B3; int parts; };
+struct PermGeom { int64_t n, lo, hi, s, c0, nb0, nb1, B0, B1, B2, B3; int parts, skip_ident; };
 __global__ void k_perm_sym(double* W, int64_t ld, PermGeom g, const int32_t* sig, double* tmp,
                            int32_t* orig, int32_t* tmpo, int dir);
 __global__ void k_scale_pack(double* X, int64_t ld, int64_t rows, int64_t cols, const double* P, int64_t ldp,
@@ -110,7 +110,7 @@ __global__ void k_store_output(T* A, int64_t lda, const double* W, int64_t ld, i
                                const double* de, T* e, const int32_t* orig, int32_t* perm, const int32_t* colblk,
                                const int32_t* dinv);
 __global__ void k_seg_perm(double* W, int64_t ld, int64_t lo, int64_t s, int64_t hi, int64_t n, const int32_t* sig,
-                             int rpw);
+                             int rpw, int skip_ident);
 __global__ void k_dead_snapshot(const int32_t* orig, int64_t d0, int64_t d1, int64_t n, int32_t blk, int32_t* colblk,
                                 int32_t* inv);
 __global__ void k_dead_gather(const double* W, int64_t ld, int64_t n, const int32_t* orig, const int32_t* colblk,

@@ -825,6 +825,13 @@ __device__ __forceinline__ int64_t sigma_at(const int32_t* sig, int64_t q, int64
     const int64_t v = sig[q];
     return (v < 0 || v >= sz) ? 0 : v;
 }
+// Whether sig[0 .. s) is the identity (the same answer in every thread of the block).
+// A permutation queued before the host has seen it (a base-case leaf's) skips itself so.
+__device__ bool sig_identity(const int32_t* sig, int64_t s) {
+    int moved = 0;
+    for (int64_t q = threadIdx.x; q < s; q += blockDim.x) moved |= sig[q] != (int32_t)q;
+    return !__syncthreads_or(moved);
+}
 
 // Symmetric permutation of the position range [lo, hi) of W, through tmp:
 // part 0 rows [lo,hi) x cols [c0,lo) (the columns left of the range that are
@@ -835,6 +842,7 @@ __device__ __forceinline__ int64_t sigma_at(const int32_t* sig, int64_t q, int64
 __global__ __launch_bounds__(256) void k_perm_sym(double* W, int64_t ld, PermGeom g, const int32_t* sig,
                                                  double* tmp, int32_t* orig, int32_t* tmpo, int dir) {
     constexpr int EPT = PERM_EPT, CH = 256 * EPT;   // elements per thread, per block
+    if (g.skip_ident && sig_identity(sig, g.s)) return;
     int64_t b = blockIdx.x;
     const int64_t s = g.s, lo = g.lo, hi = g.hi;
     const int tid = threadIdx.x;
@@ -916,8 +924,9 @@ __global__ __launch_bounds__(256) void k_perm_sym(double* W, int64_t ld, PermGeo
 // a symmetric permutation, and PLDUQ's row reorders of its transposed copy.
 // Eight loads in flight per thread.
 __global__ __launch_bounds__(256) void k_seg_perm(double* W, int64_t ld, int64_t lo, int64_t s, int64_t hi,
-                                                    int64_t n, const int32_t* sig, int rpw) {
+                                                    int64_t n, const int32_t* sig, int rpw, int skip_ident) {
     extern __shared__ double seg[];
+    if (skip_ident && sig_identity(sig, s)) return;
     const int64_t r0 = hi + (int64_t)blockIdx.x * rpw;
     const int nr = (int)min((int64_t)rpw, n - r0);
     const int si = (int)s, tot = nr * si, tid = threadIdx.x;
