@@ -66,6 +66,8 @@ static inline unsigned nblk(int64_t x, int b = 256) { return (unsigned)((x + b -
 constexpr int HW_SLAB = 256;
 // mapped host word a leaf launch raises to its generation once its results are written
 constexpr int HW_FLAG = 512;
+// device word of ws.info that a PLDUQ slab writes its rank to
+constexpr int INFO_SLAB_RANK = 16;
 // "no column left of the range is read later" (see Engine::recall)
 constexpr int64_t AL_NONE = INT64_MAX;
 
@@ -860,13 +862,15 @@ struct Engine {
         return src;
     }
     // reorder T rows [j0, j0+len) (Y columns) by src, in T columns [i0, i0+ni) (Y rows)
-    void tcolperm(int64_t j0, int64_t len, const int32_t* src, int64_t i0, int64_t ni) {
+    // skip_zero: a device word; nothing moves when it holds 0 (see plduq_t)
+    void tcolperm(int64_t j0, int64_t len, const int32_t* src, int64_t i0, int64_t ni,
+                  const int32_t* skip_zero = nullptr) {
         if (len <= 1 || ni <= 0) return;
         REQUIRE(len <= 65535 && len * ni <= ws.cap * ws.cap);
         dim3 g(nblk(ni, 256 * PERM_EPT), (unsigned)len);
         prof->begin(st, PLDL_CLASS_PERM, 0.0, 16.0 * (double)len * (double)ni);
-        hipLaunchKernelGGL(k_tcolperm, g, dim3(256), 0, st, T, ldT, j0, len, src, i0, ni, ws.tmp1, 0);
-        hipLaunchKernelGGL(k_tcolperm, g, dim3(256), 0, st, T, ldT, j0, len, src, i0, ni, ws.tmp1, 1);
+        hipLaunchKernelGGL(k_tcolperm, g, dim3(256), 0, st, T, ldT, j0, len, src, i0, ni, ws.tmp1, 0, skip_zero);
+        hipLaunchKernelGGL(k_tcolperm, g, dim3(256), 0, st, T, ldT, j0, len, src, i0, ni, ws.tmp1, 1, skip_zero);
         prof->end(st);
         prof->n_launch += 2;
     }
@@ -911,18 +915,29 @@ struct Engine {
         *moved = m > 0 && c1 > c0;
         if (!*moved) return 0;
         REQUIRE(a1 <= TC && c1 <= TR);
-        if (m <= 64) return plduq_slab(a0, a1, c0, c1, srcR, srcC);
+        if (m <= 64) return plduq_slab_wait(plduq_slab_launch(a0, a1, c0, c1, srcR, srcC), m);
         const int64_t ip_save = ip_top;
         const int64_t am = a0 + std::max<int64_t>(64, (m / 2) / 64 * 64);
         const int64_t h = am - a0, mb = a1 - am, len = c1 - c0;
         int32_t* sRt = ipush(h);
         int32_t* sCt = ipush(len);
         bool tmv = false, bmv = false;
-        const int64_t r1 = plduq_t(a0, am, c0, c1, sRt, sCt, &tmv);
+        int64_t r1;
+        const bool top_slab = h <= 64;
+        if (top_slab) {
+            // The bottom rows take the top slab's column order: queued behind the slab
+            // before the host waits for its rank (skipped on the device when it is 0).
+            const int32_t gen = plduq_slab_launch(a0, am, c0, c1, sRt, sCt);
+            tmv = true;
+            tcolperm(c0, len, sCt, am, mb, ws.info + INFO_SLAB_RANK);
+            r1 = plduq_slab_wait(gen, h);
+        } else {
+            r1 = plduq_t(a0, am, c0, c1, sRt, sCt, &tmv);
+        }
         if (r1 > 0) {
             const int64_t ncr = len - r1;
             // the bottom rows take the top half's column order
-            tcolperm(c0, len, sCt, am, mb);
+            if (!top_slab) tcolperm(c0, len, sCt, am, mb);
             // Wb^T = U_t^{-T} Y_b1^T  (U_t^T unit lower at T[c0.., a0..])
             trsm_ll(MatV{T + c0 * ldT + am, ldT, 1}, r1, mb, MatV{T + c0 * ldT + a0, ldT, 1});
             // Y_b2^T -= V_t^T Wb^T
@@ -971,7 +986,7 @@ struct Engine {
     // in row order inside a chunk; on return the slab's pivot rows and pivot
     // columns come first (pivot order), pR / pC updated.  The host reads the
     // slab's rank from mapped host words (one wait per slab).
-    int64_t plduq_slab(int64_t a0, int64_t a1, int64_t c0, int64_t c1, int32_t* srcR, int32_t* srcC) {
+    int32_t plduq_slab_launch(int64_t a0, int64_t a1, int64_t c0, int64_t c1, int32_t* srcR, int32_t* srcC) {
         const int64_t m = a1 - a0;
         const int64_t nch = (c1 - c0 + PS_CHUNK - 1) / PS_CHUNK;
         REQUIRE(m >= 1 && m <= 64 && nch >= 1 && nch <= PS_MAXCH);
@@ -979,13 +994,18 @@ struct Engine {
         g.T = T; g.ld = ldT; g.a0 = a0; g.m = (int)m; g.nch = (int)nch; g.c0 = c0; g.c1 = c1;
         g.F = F; g.itab = itab; g.pR = pR; g.pC = pC; g.sh = ws.ps;
         g.srcR = srcR; g.srcC = srcC;
+        g.rdev = ws.info + INFO_SLAB_RANK;
         g.gen = ++ws.ps_gen;
         g.hout = ws.hinfo_dev + HW_SLAB;   // (the base case uses words 0 .. 128)
         g.hflag = ws.hinfo_dev + HW_FLAG;
         g.hgen = next_hgen();
         ws.hinfo[HW_SLAB + 1] = 0;
         LAUNCH(PLDL_CLASS_PLDUQ_LEAF, k_plduq_slab, dim3((unsigned)nch), dim3(PS_THREADS), 0, st, g);
-        const int32_t* h = wait_leaf(g.hgen);
+        return g.hgen;
+    }
+    // the rank of the slab launched with generation gen (m rows), once it has written it
+    int64_t plduq_slab_wait(int32_t gen, int64_t m) {
+        const int32_t* h = wait_leaf(gen);
         if (h[HW_SLAB + 1]) throw Err(PLDL_EINTERNAL, "PLDUQ slab: a chunk waited too long for its predecessor (launch aborted)");
         const int64_t R = h[HW_SLAB];
         REQUIRE(R >= 0 && R <= m);

@@ -49,6 +49,7 @@ struct PsArgs {
     int32_t hgen;
     int32_t* srcC;        // out: column position c0 + q holds the column that was at c0 + srcC[q]
     int32_t* srcR;        // out: slab row a0 + q holds the row that was at a0 + srcR[q]
+    int32_t* rdev;        // out: device word, the slab rank (read by launches queued behind the slab)
 };
 __global__ void k_plduq_slab(PsArgs g);
 
@@ -67,7 +68,7 @@ __global__ void k_compose(int32_t* srcc, const int32_t* topc, const int32_t* bot
 __global__ void k_reorder_src_1wg(const int32_t* snap, const int32_t* cur, int64_t len, int32_t* inv, int32_t* src);
 __global__ void k_idx_reorder_1wg(int32_t* idx, int64_t a, int64_t len, const int32_t* src);
 __global__ void k_tcolperm(double* T, int64_t ld, int64_t j0, int64_t len, const int32_t* src, int64_t i0,
-                           int64_t ni, double* tmp, int phase);
+                           int64_t ni, double* tmp, int phase, const int32_t* skip_zero);
 __global__ void k_trowperm(double* T, int64_t ld, int64_t j0, int64_t nj, int64_t i0, int64_t len,
                            const int32_t* src, double* tmp, int phase);
 __global__ void k_inv_table(uint32_t* tab, Field F);

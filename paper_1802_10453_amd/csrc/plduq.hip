@@ -318,6 +318,7 @@ __global__ __launch_bounds__(PS_THREADS) void k_plduq_slab(PsArgs g) {
         }
     }
     if (b == g.nch - 1 && tid == 0) {
+        g.rdev[0] = R;
         g.hout[0] = R;
         // the host polls this word instead of waiting for the launch to end
         __threadfence_system();
