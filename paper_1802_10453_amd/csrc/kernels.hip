@@ -339,12 +339,20 @@ __global__ void k_rot_src(int64_t len, int64_t rot1, int32_t* src) {
 // Reorder T rows j0 .. j0+len (Y columns) by src, restricted to T columns
 // [i0, i0+ni) (Y rows): phase 0 gathers into tmp, phase 1 copies back.  With
 // skip_zero set, nothing moves when *skip_zero is 0 (the rank of the PLDUQ slab
-// that wrote src: a slab without pivots leaves the columns in place).
+// that wrote src: a slab without pivots leaves the columns in place).  Such a
+// launch is queued before the host has seen the slab end; if the slab aborted,
+// src may be incomplete, so an entry outside [0, len) reads column q instead
+// (the host reports the abort; the gather must only stay inside T).
 __global__ void k_tcolperm(double* T, int64_t ld, int64_t j0, int64_t len, const int32_t* src, int64_t i0,
                            int64_t ni, double* tmp, int phase, const int32_t* skip_zero) {
     const int64_t ib = (int64_t)blockIdx.x * (256 * PERM_EPT) + threadIdx.x, q = blockIdx.y;
     if (q >= len || (skip_zero && *skip_zero == 0)) return;
-    const double* from = phase == 0 ? T + (j0 + src[q]) * ld + i0 : tmp + q * ni;
+    int64_t sq = q;
+    if (phase == 0) {
+        sq = src[q];
+        if ((uint64_t)sq >= (uint64_t)len) sq = q;
+    }
+    const double* from = phase == 0 ? T + (j0 + sq) * ld + i0 : tmp + q * ni;
     double* to = phase == 0 ? tmp + q * ni : T + (j0 + q) * ld + i0;
     double v[PERM_EPT];
 #pragma unroll
