@@ -950,10 +950,21 @@ struct Engine {
         }
         int32_t* sRb = ipush(mb);
         int32_t* sCb = ipush(std::max<int64_t>(len - r1, 1));
-        const int64_t r2 = plduq_t(am, a1, c0 + r1, c1, sRb, sCb, &bmv);
+        // a bottom half that is one slab: the top rows' reorder by its column order is
+        // queued the same way, before the host waits for its rank
+        const bool bot_slab = mb <= 64 && len > r1;
+        int64_t r2;
+        if (bot_slab) {
+            const int32_t gen = plduq_slab_launch(am, a1, c0 + r1, c1, sRb, sCb);
+            bmv = true;
+            tcolperm(c0 + r1, len - r1, sCb, a0, h, ws.info + INFO_SLAB_RANK);
+            r2 = plduq_slab_wait(gen, mb);
+        } else {
+            r2 = plduq_t(am, a1, c0 + r1, c1, sRb, sCb, &bmv);
+        }
         if (r2 > 0) {
             // the top rows take the bottom half's column order, the bottom rows' multipliers its row order
-            tcolperm(c0 + r1, len - r1, sCb, a0, h);
+            if (!bot_slab) tcolperm(c0 + r1, len - r1, sCb, a0, h);
             if (r1 > 0) trowperm(c0, r1, am, mb, sRb);
             // pivot rows of both halves first: rotate the top non-pivots behind the bottom pivots
             if (h > r1) {
