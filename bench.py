@@ -2,8 +2,9 @@
 """Throughput of the rank-profile-revealing PLDL^TP^T factorization over F_p on one MI355X.
 
 Metric (Section 6 of the paper): effective GOPS = (r^3/3 + n^2 r - r^2 n) / (1e9 * time),
-one step = one whole factorization (pldl_factor: recursive cascade, every product on
-the FP64 matrix cores) of a seeded synthetic matrix already resident in HBM.
+one step = one whole factorization (pldl_factor: recursive cascade, the products on
+the matrix cores of the library's default path, INT8 split for p < 2^23 and FP64
+otherwise; --path forces one) of a seeded synthetic matrix already resident in HBM.
 
 Default workload: n = 16384 over F_8388593 with a uniformly random rank profile of
 rank 12288 (A = L R L^T, L random unit lower, R a seeded symmetric rook placement).
